@@ -1,0 +1,25 @@
+"""FP64 CPU oracle for the screen-space visibility-bitmask gather.
+
+TEST INFRASTRUCTURE.  Only the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product path (the HIP
+library and its Python binding) never imports, links or calls it, and the oracle shares
+no code, table or constant generator with that path.
+"""
+from .ssvb_oracle import (  # noqa: F401
+    Camera,
+    Params,
+    ROUND,
+    PSEUDOCODE,
+    NOISE_HASH,
+    NOISE_R2,
+    NOISE_FIXED,
+    NOISE_NAMES,
+    pcg_hash,
+    pixel_hash,
+    r2_constants,
+    direction_lut,
+    slice_noise,
+    step_q4,
+    compute,
+    sh_eval,
+)

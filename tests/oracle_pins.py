@@ -1,0 +1,671 @@
+"""Pins of the FP64 oracle against facts fixed by the paper's model and by geometry.
+
+Each ``pin_*`` function takes an oracle module ``O`` (the real one, or a deliberately
+broken copy in the mutation test) and raises AssertionError when the oracle disagrees
+with an independent source of truth: closed forms of plane geometry, the GTAO horizon
+integral that the infinite-thickness limit must reproduce (Section 3.1; Eqs. 2-3), the
+analytic occluded fraction of an infinite wall, a brute-force intersection of the
+thick-heightfield model (brute_force.py) and algebraic invariants of Algorithm 1.
+None of these re-types the oracle's own formulas.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import brute_force as BF
+from gbuffer_scene import crease_gbuffer, make_camera, make_scene, plane_gbuffer, render_gbuffer
+
+INF = float("inf")
+
+
+# ----------------------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------------------
+
+def ocam(O, cam):
+    return O.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.view_to_world)
+
+
+def const_sh(rgb):
+    """SH coefficients of a constant probe of colour ``rgb``."""
+    sh = np.zeros((9, 3))
+    sh[0] = np.asarray(rgb) / (0.5 * math.sqrt(1.0 / math.pi))
+    return tuple(sh.reshape(-1))
+
+
+def bits_of(mask32, nb=32):
+    return [(int(mask32) >> k) & 1 for k in range(nb)]
+
+
+def popcount32(a):
+    a = np.asarray(a, dtype=np.uint64)
+    return np.array([bin(int(v)).count("1") for v in a.reshape(-1)]).reshape(a.shape)
+
+
+def range_mask(a, b):
+    """uint32 with bits [a, b) set (0 <= a, b <= 32)."""
+    if b <= a:
+        return 0
+    return ((1 << b) - 1) ^ ((1 << a) - 1)
+
+
+def integer_step_params(O, k_px, steps, **kw):
+    """FIXED noise, two axis-aligned slices and steps of exactly ``k_px`` pixels, so every
+    sample sits on a texel centre on the pixel's row (slice 0) or column (slice 1)."""
+    return O.Params(slices=2, steps=steps, radius=1e6, max_radius_px=float(k_px * (steps + 1)),
+                    noise=O.NOISE_FIXED, **kw)
+
+
+_TINY = {}
+
+
+def tiny_scene():
+    """A 64x48 view into a dense box scene: objects, ground and some background sky."""
+    if "s" not in _TINY:
+        sc = make_scene(7, 40, 20)
+        cam = make_camera(64, 48, fov_y_deg=60, pitch_deg=-25)
+        gb = render_gbuffer(sc, cam, cache=False)
+        _TINY["s"] = (gb, cam, sc)
+    return _TINY["s"]
+
+
+# ----------------------------------------------------------------------------------------
+# P1: an unoccluded plane facing the camera sets no bit
+# ----------------------------------------------------------------------------------------
+
+def pin_plane_fronto(O):
+    cam = make_camera(41, 31, fov_y_deg=90, pitch_deg=0)
+    gb = plane_gbuffer(cam, (0, 0, 1), (0, 0, -4.0))
+    C = (0.3, 0.5, 0.7)
+    for t in (0.1, 0.5, INF):
+        prm = O.Params(slices=3, steps=6, radius=1.5, thickness=t, noise=O.NOISE_HASH, seed=11,
+                       ambient_sh=const_sh(C))
+        r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, return_masks=True)
+        assert np.all(r["masks"] == 0), "a fronto-parallel plane must set no sector"
+        assert np.all(r["ao"] == 1.0)
+        assert np.all(r["gi"] == 0.0)
+        assert np.allclose(r["ambient"], np.asarray(C), rtol=1e-7, atol=0)  # SH stored as float32
+
+
+def pin_plane_tilted(O):
+    """Tilted plane facing the camera, samples exactly on texel centres: no bits."""
+    cam = make_camera(33, 25, fov_y_deg=90, pitch_deg=0)
+    n = np.array([0.35, -0.3, 1.0])
+    gb = plane_gbuffer(cam, n, (0, 0, -5.0))
+    for t in (0.05, 0.7, INF):
+        for k in (1, 3):
+            prm = integer_step_params(O, k, 5, thickness=t)
+            r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, return_masks=True)
+            assert np.all(r["masks"] == 0)
+            assert np.all(r["ao"] == 1.0)
+            assert np.all(r["gi"] == 0.0)
+
+
+def pin_plane_ambient_linear(O):
+    """Centre pixel of a fronto-parallel plane under a linear SH probe: the mean of the
+    subregion directions is v / (N_a sin(pi / (2 N_a))), a closed form."""
+    cam = make_camera(31, 31, fov_y_deg=90, pitch_deg=0)
+    gb = plane_gbuffer(cam, (0, 0, 1), (0, 0, -3.0))
+    rng = np.random.default_rng(5)
+    R = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    if np.linalg.det(R) < 0:
+        R[:, 0] = -R[:, 0]
+    cam = cam.__class__(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
+                        tuple(float(np.float32(v)) for v in R.reshape(-1)))
+    sh = np.zeros((9, 3))
+    sh[0] = [0.2, 0.1, 0.3]
+    sh[1:4] = rng.uniform(-0.5, 0.5, (3, 3))
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    y00 = 0.5 * math.sqrt(1.0 / math.pi)
+    Rf = np.array([float(np.float32(v)) for v in R.reshape(-1)]).reshape(3, 3)
+    shf = np.array([float(np.float32(v)) for v in sh.reshape(-1)]).reshape(9, 3)
+    for na in (1, 2, 4, 8):
+        prm = O.Params(slices=5, steps=4, radius=1.0, thickness=0.5, noise=O.NOISE_HASH, seed=3,
+                       ambient_samples=na, ambient_sh=tuple(sh.reshape(-1)))
+        r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                      pixels=([15], [15]))
+        dbar = Rf @ np.array([0.0, 0.0, 1.0]) / (na * math.sin(math.pi / (2 * na)))
+        want = shf[0] * y00 + c1 * (shf[1] * dbar[1] + shf[2] * dbar[2] + shf[3] * dbar[0])
+        assert np.allclose(r["ambient"][0], want, atol=1e-12), (na, r["ambient"][0], want)
+
+
+# ----------------------------------------------------------------------------------------
+# P2: infinite thickness reproduces the horizon (GTAO) integral
+# ----------------------------------------------------------------------------------------
+
+def _horizons_integer_lattice(gb, cam, k, steps, ys, xs):
+    """GTAO horizon search on the two axis slices: for each pixel, slice and side, the
+    maximum cosine between v and the direction to a valid sample (Jimenez et al.; the
+    paper's Figure "SliceGTAO"), returned as theta relative to the projected normal,
+    plus gamma.  Independent of the oracle: plain 3D geometry of texel centres."""
+    depth = gb["depth"].astype(np.float64)
+    nrm = gb["normal"][..., :3].astype(np.float64)
+    H, W = depth.shape
+    cam4 = (cam.fx, cam.fy, cam.cx, cam.cy)
+    out = np.full((len(ys), 2, 2), np.nan)
+    gam = np.zeros((len(ys), 2))
+    for idx, (y, x) in enumerate(zip(ys, xs)):
+        z_p = depth[y, x]
+        for sl, (Dx, Dy) in enumerate(((4096, 0), (0, 4096))):
+            p, v, e, g = BF.slice_frame(cam4, x, y, z_p, nrm[y, x], Dx, Dy)
+            gam[idx, sl] = g
+            for si, s in enumerate((1, -1)):
+                best = -np.inf
+                for j in range(steps):
+                    X = x + s * k * (j + 1) * (1 if Dx else 0)
+                    Y = y + s * k * (j + 1) * (1 if Dy else 0)
+                    if not (0 <= X < W and 0 <= Y < H):
+                        continue
+                    z = depth[Y, X]
+                    if not (np.isfinite(z) and z > 0):
+                        continue
+                    P = z * np.array([(X + 0.5 - cam.cx) / cam.fx, -(Y + 0.5 - cam.cy) / cam.fy, -1.0])
+                    d = P - p
+                    best = max(best, float(np.dot(d, v) / np.linalg.norm(d)))
+                if best > -np.inf:
+                    out[idx, sl, si] = s * math.acos(min(1.0, best)) - g
+    return out, gam
+
+
+def _horizon_case(O, nb):
+    gb, cam, _ = tiny_scene()
+    k, steps = 2, 6
+    prm = integer_step_params(O, k, steps, thickness=INF, sectors=nb, ambient_samples=4)
+    valid = np.argwhere(gb["depth"] > 0)
+    sel = valid[:: max(1, len(valid) // 150)]
+    ys, xs = sel[:, 0], sel[:, 1]
+    r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, pixels=(ys, xs),
+                  return_masks=True)
+    hz, gam = _horizons_integer_lattice(gb, cam, k, steps, ys, xs)
+    return r, hz, gam
+
+
+def pin_horizon_infinite_thickness(O):
+    """t = inf: each side's mask is the sectors from its horizon to the hemisphere edge."""
+    r, hz, _ = _horizon_case(O, 32)
+    checked = 0
+    for idx in range(hz.shape[0]):
+        for sl in range(2):
+            want = 0
+            tie = False
+            for si, s in enumerate((1, -1)):
+                th = hz[idx, sl, si]
+                if np.isnan(th):
+                    continue
+                th = min(max(th, -math.pi / 2), math.pi / 2)
+                x = 32 * (th + math.pi / 2) / math.pi + 0.5
+                if abs(x - round(x)) < 1e-7:
+                    tie = True
+                a = math.floor(x)
+                want |= range_mask(a, 32) if s == 1 else range_mask(0, a)
+            if tie:
+                continue
+            assert int(r["masks"][idx, sl]) == want, (idx, sl, hex(int(r["masks"][idx, sl])), hex(want))
+            checked += 1
+    assert checked > 200
+
+
+def pin_horizon_uniform_integral(O):
+    """t = inf: per slice, the unoccluded fraction equals the visible arc between the two
+    horizons over pi (uniform sectors, Eq. 4), within one sector at N_b = 32 and 1024."""
+    for nb in (32, 1024):
+        r, hz, _ = _horizon_case(O, nb)
+        m = r["masks"]
+        for idx in range(hz.shape[0]):
+            for sl in range(2):
+                hi = hz[idx, sl, 0]
+                lo = hz[idx, sl, 1]
+                hi = math.pi / 2 if np.isnan(hi) else min(max(hi, -math.pi / 2), math.pi / 2)
+                lo = -math.pi / 2 if np.isnan(lo) else min(max(lo, -math.pi / 2), math.pi / 2)
+                vis = max(0.0, hi - lo) / math.pi
+                if nb == 32:
+                    occ = bin(int(m[idx, sl])).count("1")
+                else:
+                    occ = int(m[idx, sl].sum())
+                assert abs((1 - occ / nb) - vis) <= 1.0 / nb + 1e-12, (nb, idx, sl, 1 - occ / nb, vis)
+
+
+def gtao_inner(h1, h2, gamma):
+    """GTAO's closed-form inner integral of cos(theta - gamma) |sin theta| over the
+    visible arc [h1, h2] (h1 <= 0 <= h2, angles from v), Jimenez et al. 2016, which
+    the paper's Eqs. 2-3 restate."""
+    return 0.25 * (-math.cos(2 * h1 - gamma) + math.cos(gamma) + 2 * h1 * math.sin(gamma)) + \
+        0.25 * (-math.cos(2 * h2 - gamma) + math.cos(gamma) + 2 * h2 * math.sin(gamma))
+
+
+def _cos_weight(a, b, gamma):
+    """Integral over theta_v in [a, b] of cos(theta_v - gamma) |sin theta_v|."""
+    def F(t):  # antiderivative of cos(t - g) sin t
+        return 0.5 * (t * math.sin(gamma) - 0.5 * math.cos(2 * t - gamma))
+    total = 0.0
+    for lo, hi, sgn in ((a, min(b, 0.0), -1.0), (max(a, 0.0), b, 1.0)):
+        if hi > lo:
+            total += sgn * (F(hi) - F(lo))
+    return total
+
+
+def pin_gtao_cosine_closed_form(O):
+    """t = inf, N_b = 1024: the cosine-weighted popcount of unoccluded sectors matches
+    GTAO's analytic horizon integral within two sectors' weight."""
+    nb = 1024
+    r, hz, gam = _horizon_case(O, nb)
+    m = r["masks"]
+    # the closed form itself agrees with quadrature
+    for g in (-0.7, 0.0, 0.4):
+        for h1, h2 in ((-0.3 + g, 0.5 + g), (g - math.pi / 2, g + math.pi / 2)):
+            if h1 <= 0 <= h2:
+                assert abs(gtao_inner(h1, h2, g) - _cos_weight(h1, h2, g)) < 1e-12
+    for idx in range(hz.shape[0]):
+        for sl in range(2):
+            g = gam[idx, sl]
+            hp = hz[idx, sl, 0]
+            hm = hz[idx, sl, 1]
+            h2 = g + (math.pi / 2 if np.isnan(hp) else min(max(hp, -math.pi / 2), math.pi / 2))
+            h1 = g + (-math.pi / 2 if np.isnan(hm) else min(max(hm, -math.pi / 2), math.pi / 2))
+            if not (h1 <= 0 <= h2):
+                continue
+            weights = [_cos_weight(g - math.pi / 2 + kk * math.pi / nb, g - math.pi / 2 + (kk + 1) * math.pi / nb, g)
+                       for kk in range(nb)]
+            got = sum(w for w, bit in zip(weights, m[idx, sl]) if not bit)
+            want = gtao_inner(h1, h2, g)
+            assert abs(got - want) <= 2 * max(weights) + 1e-9, (idx, sl, got, want)
+
+
+# ----------------------------------------------------------------------------------------
+# P3: an infinite wall at a known angle
+# ----------------------------------------------------------------------------------------
+
+def _crease(alpha, size=41, D=4.0):
+    cam = make_camera(size, size, fov_y_deg=90, pitch_deg=0)
+    return crease_gbuffer(cam, D, alpha), cam
+
+
+def pin_wall_infinite_thickness(O):
+    """Centre row of a crease (floor + wall rising at alpha beyond the hinge column), t = inf:
+    the + side mask starts at the elevation of the highest wall sample above the floor."""
+    size, D, k, steps = 41, 4.0, 2, 6
+    c = size // 2
+    for deg in (30.0, 37.0, 45.0, 60.0):
+        alpha = math.radians(deg)
+        gb, cam = _crease(alpha, size, D)
+        prm = integer_step_params(O, k, steps, thickness=INF)
+        xs = np.arange(c - 12, c + 1)
+        ys = np.full_like(xs, c)
+        r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                      pixels=(ys, xs), return_masks=True)
+        f = float(np.float32(cam.fx))
+        for idx, x in enumerate(xs):
+            z_p = float(gb["depth"][c, x])
+            p = np.array([z_p * (x + 0.5 - c - 0.5) / f, 0.0, -z_p])
+            beta = 0.0
+            for j in range(steps):
+                X = x + k * (j + 1)
+                if X >= size:
+                    break
+                z = float(gb["depth"][c, X])
+                P = np.array([z * (X + 0.5 - c - 0.5) / f, 0.0, -z])
+                d = P - p
+                beta = max(beta, math.atan2(d[2], d[0]))  # elevation above the floor
+            xarg = 32 * (1 - beta / math.pi) + 0.5
+            if abs(xarg - round(xarg)) < 1e-6:
+                continue
+            want = range_mask(math.floor(xarg), 32)
+            assert int(r["masks"][idx, 0]) == want, (deg, x, hex(int(r["masks"][idx, 0])), hex(want))
+            assert int(r["masks"][idx, 1]) == 0
+            assert abs(r["ao"][idx] - (1 - bin(want).count("1") / 32 + 1) / 2) < 1e-15
+        # the hinge pixel itself: the wall direction is exactly alpha above the floor
+        a = math.floor(32 * (1 - alpha / math.pi) + 0.5)
+        assert int(r["masks"][-1, 0]) == range_mask(a, 32)
+    # alpha = 45 degrees at the hinge: AO = (0.75 + 1) / 2 exactly
+    gb, cam = _crease(math.pi / 4, size, D)
+    r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam),
+                  integer_step_params(O, k, steps, thickness=INF), pixels=([c], [c]))
+    assert r["ao"][0] == 0.875
+
+
+def pin_wall_finite_thickness(O):
+    """Hinge pixel, finite t: the occluded arc runs from the wall direction to the back
+    angle of the nearest wall sample, atan2(l cos a, l sin a - t) (plane geometry)."""
+    size, D, k, steps = 41, 4.0, 2, 6
+    c = size // 2
+    for deg in (35.0, 50.0):
+        alpha = math.radians(deg)
+        gb, cam = _crease(alpha, size, D)
+        f = float(np.float32(cam.fx))
+        X = c + k
+        z = float(gb["depth"][c, X])
+        d = np.array([z * (X - c) / f, 0.0, D - z])      # nearest wall sample minus p
+        for t0, slope in ((0.02, 0.0), (0.1, 0.0), (0.3, 0.0), (0.8, 0.0), (0.0, 0.05), (0.1, 0.1)):
+            t = t0 + slope * D       # thickness grows linearly with the pixel's depth
+            prm = integer_step_params(O, k, steps, thickness=t0, thickness_slope=slope)
+            r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                          pixels=([c], [c]), return_masks=True)
+            th_b = min(math.pi / 2, math.atan2(d[0], d[2] - t))
+            a = math.floor(32 * (1 - alpha / math.pi) + 0.5)
+            xb = 32 * (th_b + math.pi / 2) / math.pi + 0.5
+            if abs(xb - round(xb)) < 1e-6:
+                continue
+            b = math.floor(xb)
+            assert int(r["masks"][0, 0]) == range_mask(a, b), (deg, t, hex(int(r["masks"][0, 0])), a, b)
+
+
+def pin_wall_indirect(O):
+    """Floor pixels facing a lit wall, t = inf: GI is the sum over wall samples, near to
+    far, of (newly covered sectors / N_b) (n_p . l) (-n_w . l), with the sectors from
+    each sample's elevation above the floor and l, n_w from plane geometry."""
+    size, D, k, steps = 41, 4.0, 2, 6
+    c = size // 2
+    for deg in (40.0, 65.0):
+        alpha = math.radians(deg)
+        gb, cam = _crease(alpha, size, D)
+        prm = integer_step_params(O, k, steps, thickness=INF)
+        xs = np.arange(c - 12, c)
+        ys = np.full_like(xs, c)
+        r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, pixels=(ys, xs))
+        f = float(np.float32(cam.fx))
+        n_p = np.array([0.0, 0.0, 1.0])
+        n_w = np.array([-math.sin(alpha), 0.0, math.cos(alpha)])
+        tested = 0
+        for idx, x in enumerate(xs):
+            z_p = float(gb["depth"][c, x])
+            p = np.array([z_p * (x - c) / f, 0.0, -z_p])
+            covered_from = 32
+            gi = 0.0
+            tie = False
+            for j in range(steps):
+                X = x + k * (j + 1)
+                z = float(gb["depth"][c, X])
+                P = np.array([z * (X - c) / f, 0.0, -z])
+                d = P - p
+                beta = math.atan2(d[2], d[0])
+                xa = 32 * (1 - beta / math.pi) + 0.5
+                tie |= abs(xa - round(xa)) < 1e-6
+                a = math.floor(xa)
+                if a < covered_from:
+                    l = d / np.linalg.norm(d)
+                    gi += (covered_from - a) / 32 * max(0.0, n_p @ l) * max(0.0, -(n_w @ l))
+                    covered_from = a
+            if tie:
+                continue
+            want = gi / 2  # two slices; the other slice and the other side see only floor
+            assert np.allclose(r["gi"][idx], want, rtol=1e-6, atol=1e-9), (deg, x, r["gi"][idx], want)
+            tested += want > 0
+        assert tested >= 5
+
+
+def wall_ao_analytic(alpha):
+    """1 - (2 / pi^2) * integral_0^{pi/2} atan(tan(alpha) cos(phi)) dphi (Simpson, FP64)."""
+    n = 4000
+    h = (math.pi / 2) / n
+    s = 0.0
+    for i in range(n + 1):
+        w = 1 if i in (0, n) else (4 if i % 2 else 2)
+        s += w * math.atan(math.tan(alpha) * math.cos(i * h))
+    return 1.0 - (2.0 / math.pi ** 2) * (s * h / 3.0)
+
+
+def pin_wall_random_rotations(O):
+    """Hinge pixel, 64 randomly rotated slices, t = inf: AO converges to the wall's
+    analytic occluded fraction."""
+    size, D = 1201, 4.0
+    c = size // 2
+    for deg in (45.0, 25.0):
+        alpha = math.radians(deg)
+        gb, cam = _crease(alpha, size, D)
+        ref = wall_ao_analytic(alpha)
+        for seed in (0, 1):
+            prm = O.Params(slices=64, steps=4, radius=4.0, thickness=INF, noise=O.NOISE_HASH, seed=seed)
+            r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, pixels=([c], [c]))
+            assert abs(r["ao"][0] - ref) < 0.01, (deg, seed, r["ao"][0], ref)
+
+
+# ----------------------------------------------------------------------------------------
+# P4: brute force against the thick-heightfield model
+# ----------------------------------------------------------------------------------------
+
+def _bf_pixels(gb, count, seed):
+    valid = np.argwhere(gb["depth"] > 0)
+    rng = np.random.default_rng(seed)
+    return valid[rng.choice(len(valid), size=min(count, len(valid)), replace=False)]
+
+
+def pin_bruteforce_sound(O):
+    """Every sector the oracle occludes has its centre inside the model's occluded set."""
+    gb, cam, _ = tiny_scene()
+    cam4 = (cam.fx, cam.fy, cam.cx, cam.cy)
+    lut_dx = [math.floor(4096 * math.cos(math.pi * k / 4096) + 0.5) for k in range(4096)]
+    lut_dy = [math.floor(4096 * math.sin(math.pi * k / 4096) + 0.5) for k in range(4096)]
+    q, steps, nd = 24, 6, 8
+    sel = _bf_pixels(gb, 60, 1)
+    for t in (0.3, INF):
+        prm = O.Params(slices=nd, steps=steps, radius=1e6, max_radius_px=q * (steps + 1) / 16.0,
+                       thickness=t, noise=O.NOISE_FIXED)
+        r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                      pixels=(sel[:, 0], sel[:, 1]), return_masks=True)
+        nset = 0
+        for idx, (y, x) in enumerate(sel):
+            for i in range(nd):
+                kk = (i * 65536) // (16 * nd)
+                lam = (q / 16.0, q * steps / 16.0)
+                ivals, _ = BF.occluded_intervals(gb["depth"].astype(np.float64), cam4, x, y,
+                                                 gb["normal"][y, x, :3].astype(np.float64),
+                                                 lut_dx[kk], lut_dy[kk], t, lam, lam)
+                m = int(r["masks"][idx, i])
+                for bit in range(32):
+                    if (m >> bit) & 1:
+                        nset += 1
+                        centre = -math.pi / 2 + (bit + 0.5) * math.pi / 32
+                        assert BF.is_occluded(ivals, centre, 1e-7), (t, y, x, i, bit)
+        assert nset > 100
+
+
+def pin_bruteforce_converges(O):
+    """With ever denser steps over a fixed reach and N_b = 1024, each slice's occluded
+    fraction converges to the model's exact occluded measure."""
+    gb, cam, _ = tiny_scene()
+    cam4 = (cam.fx, cam.fy, cam.cx, cam.cy)
+    depth = gb["depth"].astype(np.float64)
+    sel = _bf_pixels(gb, 12, 2)
+    reach_q4 = 16 * 10  # 10 px
+    nb, t = 1024, 0.3
+    errs = {}
+    for q in (16, 4, 1):
+        steps = reach_q4 // q
+        prm = O.Params(slices=2, steps=steps, sectors=nb, radius=1e6, min_step_q4=1,
+                       max_radius_px=q * (steps + 1) / 16.0, thickness=t, noise=O.NOISE_FIXED,
+                       ambient_samples=4)
+        r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                      pixels=(sel[:, 0], sel[:, 1]), return_masks=True)
+        e = []
+        for idx, (y, x) in enumerate(sel):
+            for i, (Dx, Dy) in enumerate(((4096, 0), (0, 4096))):
+                lam = (q / 16.0, q * steps / 16.0)
+                ivals, _ = BF.occluded_intervals(depth, cam4, x, y, gb["normal"][y, x, :3].astype(np.float64),
+                                                 Dx, Dy, t, lam, lam)
+                exact = BF.occluded_measure(ivals) / math.pi
+                got = r["masks"][idx, i].sum() / nb
+                e.append(abs(got - exact))
+        errs[q] = (max(e), float(np.mean(e)))
+    # the residual at 1/16 px comes from the first neighbour texel at grazing angles,
+    # whose angular span changes fastest within one texel; it shrinks with the step
+    assert errs[1][1] <= 0.01 and errs[1][0] <= 0.04, errs
+    assert errs[1][1] < errs[4][1] < errs[16][1], errs
+
+
+# ----------------------------------------------------------------------------------------
+# P5: invariants of Algorithm 1
+# ----------------------------------------------------------------------------------------
+
+def pin_invariants(O):
+    gb, cam, sc = tiny_scene()
+    oc = ocam(O, cam)
+    base = dict(slices=3, steps=5, radius=1.2, noise=O.NOISE_HASH, seed=9,
+                ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    runs = {}
+    for t in (0.1, 0.4, INF):
+        runs[t] = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, O.Params(thickness=t, **base),
+                            return_masks=True)
+    r = runs[0.4]
+    assert np.all((r["ao"] >= 0) & (r["ao"] <= 1))
+    # the mask can only grow with thickness, so AO can only fall
+    m1, m2, m3 = (runs[t]["masks"].astype(np.uint64) for t in (0.1, 0.4, INF))
+    assert np.all((m1 & ~m2) == 0) and np.all((m2 & ~m3) == 0)
+    assert np.all(runs[0.1]["ao"] >= r["ao"]) and np.all(r["ao"] >= runs[INF]["ao"])
+    # GI is linear in radiance; AO and ambient do not depend on it
+    r2 = O.compute(gb["depth"], gb["normal"], 2 * gb["radiance"], oc, O.Params(thickness=0.4, **base))
+    assert np.array_equal(r2["gi"], 2 * r["gi"])
+    assert np.array_equal(r2["ao"], r["ao"]) and np.array_equal(r2["ambient"], r["ambient"])
+    r0 = O.compute(gb["depth"], gb["normal"], 0 * gb["radiance"], oc, O.Params(thickness=0.4, **base))
+    assert np.all(r0["gi"] == 0)
+    # sum over steps of new sectors = final occluded sectors, and each weight <= 1
+    cmax = gb["radiance"][..., :3].max()
+    assert np.all(r["gi"] <= cmax * (1 - r["ao"])[..., None] + 1e-12)
+    assert np.all(r["gi"] >= 0)
+    # a constant probe gives ambient = colour * AO
+    C = (0.25, 0.5, 1.0)
+    rc = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc,
+                   O.Params(thickness=0.4, **{**base, "ambient_sh": const_sh(C)}))
+    fg = gb["depth"] > 0
+    assert np.allclose(rc["ambient"][fg], rc["ao"][fg][:, None] * np.asarray(C), rtol=1e-7, atol=1e-12)
+    # background pixels
+    bg = gb["depth"] <= 0
+    assert bg.any()
+    assert np.all(r["ao"][bg] == 1) and np.all(r["gi"][bg] == 0) and np.all(r["ambient"][bg] == 0)
+    # occlusion exists in this scene
+    assert r["ao"].min() < 0.8 and (r["gi"].max() > 0)
+
+
+def pin_side_symmetry(O):
+    """Mirroring the scene left-right mirrors every mask: the slice at phi maps to
+    pi - phi and sector k of the mirrored slice is sector N_b - 1 - k."""
+    gb, cam, _ = tiny_scene()
+    W = cam.width
+    # a horizontally mirrored G-buffer seen through the mirrored camera (cx -> W - cx)
+    gbm = {"depth": gb["depth"][:, ::-1].copy(), "normal": gb["normal"][:, ::-1].copy(),
+           "radiance": gb["radiance"][:, ::-1].copy()}
+    gbm["normal"][..., 0] *= -1
+    camm = cam.__class__(cam.width, cam.height, cam.fx, cam.fy, float(np.float32(W - cam.cx)), cam.cy,
+                         cam.view_to_world)
+    prm = integer_step_params(O, 2, 5, thickness=0.5)
+    r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, return_masks=True)
+    rm = O.compute(gbm["depth"], gbm["normal"], gbm["radiance"], ocam(O, camm), prm, return_masks=True)
+    rev = lambda m: int(format(int(m), "032b")[::-1], 2)
+    # slice 0 (phi = 0) maps onto itself with its sides swapped: sector k -> N_b - 1 - k;
+    # slice 1 (phi = pi/2, a column) maps onto itself unchanged
+    diff0 = diff1 = 0
+    for y in range(cam.height):
+        for x in range(W):
+            if rev(r["masks"][y, x, 0]) != int(rm["masks"][y, W - 1 - x, 0]):
+                diff0 += 1
+            if int(r["masks"][y, x, 1]) != int(rm["masks"][y, W - 1 - x, 1]):
+                diff1 += 1
+    assert diff0 <= 2 and diff1 <= 2, (diff0, diff1)
+    assert (r["masks"] != 0).mean() > 0.2
+
+
+# ----------------------------------------------------------------------------------------
+# lattice and noise
+# ----------------------------------------------------------------------------------------
+
+def pin_lattice_geometry(O):
+    """Sample texels lie on the slice line, ordered near to far, inside the projected
+    radius, one step apart, with the jitter inside one step; the two sides mirror."""
+    gb, cam, _ = tiny_scene()
+    f = float(np.float32(cam.fy))
+    for noise in (O.NOISE_FIXED, O.NOISE_HASH, O.NOISE_R2):
+        for steps, radius in ((4, 0.6), (7, 1.5)):
+            prm = O.Params(slices=4, steps=steps, radius=radius, thickness=0.5, noise=noise, seed=4)
+            r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                          return_lattice=True)
+            L = r["lattice"].astype(np.float64)          # [H, W, nd, 2, ns, 2]
+            H, W = gb["depth"].shape
+            ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+            ctr = np.stack([xs, ys], -1)[:, :, None, None, None, :]
+            off = L - ctr                                   # texel minus centre texel
+            dist = np.linalg.norm(off, axis=-1)
+            z = gb["depth"].astype(np.float64)
+            rpx = np.where(z > 0, radius * f / np.where(z > 0, z, 1), 0)
+            step = np.maximum(rpx / (steps + 1), 1.0)
+            fg = z > 0
+            # inside the projected radius, or N_s + 1 shortest steps when that is longer
+            # (texel snapping adds at most one pixel diagonal)
+            reach = step * (steps + 1)
+            assert np.all(dist[fg] <= reach[fg][:, None, None, None] + 1.5)
+            # step j sits between (j + 1) and (j + 2) steps out, within snapping
+            j = np.arange(steps)[None, None, None, :]
+            lo = (j + 1) * step[fg][:, None, None, None] - 1.5
+            hi = (j + 2) * step[fg][:, None, None, None] + 1.5
+            assert np.all((dist[fg] >= lo) & (dist[fg] <= hi))
+            if noise == O.NOISE_FIXED:
+                hi0 = (j + 1) * step[fg][:, None, None, None] + 1.5
+                assert np.all(dist[fg] <= hi0)
+            # the two sides are mirror images through the pixel centre (within snapping)
+            assert np.all(np.abs(off[:, :, :, 0] + off[:, :, :, 1]) <= 1.0)
+            # every side runs along one straight line through the centre
+            far = off[:, :, :, :, -1, :]
+            u = far / np.maximum(np.linalg.norm(far, axis=-1, keepdims=True), 1e-9)
+            cross = np.abs(off[..., 0] * u[..., None, 1] - off[..., 1] * u[..., None, 0])
+            assert np.all(cross[fg] <= 1.5)
+
+
+def pin_noise_statistics(O):
+    """Rotations and jitters are uniform (chi-square) and the slices of one pixel are
+    spread evenly over pi; the R2 rotation is a low-discrepancy dither."""
+    H, W = 64, 64
+    ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    for noise in (O.NOISE_HASH, O.NOISE_R2):
+        rho, xi = O.slice_noise(xs.reshape(-1), ys.reshape(-1), 3, noise, 17)
+        assert rho.min() >= 0 and rho.max() < 65536 and xi.min() >= 0 and xi.max() < 256
+        for vals, top in ((rho, 65536), (xi[:, 1], 256)):
+            hist = np.bincount((vals * 16 // top).astype(np.int64), minlength=16)
+            exp = len(vals) / 16
+            chi2 = ((hist - exp) ** 2 / exp).sum()
+            assert chi2 < 40, (noise, chi2)
+        if noise == O.NOISE_R2:
+            # every 4x4 block holds rotations spread over the whole circle
+            blk = rho.reshape(H // 4, 4, W // 4, 4).transpose(0, 2, 1, 3).reshape(-1, 16)
+            srt = np.sort(blk, axis=1)
+            gaps = np.diff(np.concatenate([srt, srt[:, :1] + 65536], axis=1), axis=1)
+            assert gaps.max() <= 65536 * 0.25
+    # the direction table: endpoints, symmetry, unit length
+    dx, dy = O.direction_lut()
+    assert (dx[0], dy[0], dx[2048], dy[2048]) == (4096, 0, 0, 4096)
+    assert np.all(dx[1:] == -dx[:0:-1]) and np.all(dy[1:] == dy[:0:-1])
+    assert np.all(np.abs(np.hypot(dx, dy) - 4096) <= 0.71)
+    assert np.all(np.diff(dx) <= 0) and np.all(dy[:2049] == np.maximum.accumulate(dy[:2049]))
+    # R2 constants: 2^32 / a1 solves g^3 = g + 1 and a2 = 2^32 / g^2
+    a1, a2, a3 = O.r2_constants()
+    g = 2.0 ** 32 / a1
+    assert abs(g ** 3 - g - 1) < 1e-8 and abs(a2 - 2.0 ** 32 / g ** 2) < 2 and a3 == 0x9E3779B9
+    # steps: the march never reaches past the projected radius
+    cam = O.Camera(64, 64, 32.0, 32.0, 32.0, 32.0)
+    for ns in (1, 8, 31):
+        prm = O.Params(steps=ns, radius=1.7)
+        z = np.geomspace(0.05, 500, 2000).astype(np.float32)
+        q = O.step_q4(z, cam, prm)
+        rpx = 1.7 * 32.0 / z.astype(np.float64)
+        free = (q > 16) & (q < (16 * 16383) // (ns + 1))
+        assert np.all(q[free] * (ns + 1) / 16.0 <= rpx[free] * (1 + 1e-6))
+        assert np.all(q[free] * (ns + 1) / 16.0 >= rpx[free] - (ns + 1) / 16.0 - 1e-6)
+
+
+ALL_PINS = [
+    pin_plane_fronto,
+    pin_plane_tilted,
+    pin_plane_ambient_linear,
+    pin_horizon_infinite_thickness,
+    pin_horizon_uniform_integral,
+    pin_gtao_cosine_closed_form,
+    pin_wall_infinite_thickness,
+    pin_wall_finite_thickness,
+    pin_wall_indirect,
+    pin_wall_random_rotations,
+    pin_bruteforce_sound,
+    pin_bruteforce_converges,
+    pin_invariants,
+    pin_side_symmetry,
+    pin_lattice_geometry,
+    pin_noise_statistics,
+]

@@ -1,0 +1,78 @@
+"""Plant plausible mistakes in a copy of the oracle (on the CPU) and check that the pins
+catch every one: a dropped term, a wrong sign, index or operand must fail some pin.
+
+Two natural mutants are left out because they are equivalent, not wrong: widening the
+hemisphere clamp, and dropping the clamp of n_p . l at zero.  Sectors outside
+[0, N_b) do not exist, so an out-of-hemisphere endpoint sets nothing either way, and a
+sample with n_p . l < 0 lies below the tangent plane, where it can cover no sector."""
+import os
+import sys
+import types
+
+import pytest
+
+import oracle_pins as P
+
+ORACLE_SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                          "oracle", "ssvb_oracle.py")
+
+MUTATIONS = {
+    "back sample toward the camera": ("d_v - t_p", "d_v + t_p"),
+    "front angle ignores the projected normal": ("theta_f = np.arctan2(d_e, d_v) - gamma",
+                                                 "theta_f = np.arctan2(d_e, d_v)"),
+    "floor instead of round criterion": ("nb * u_lo + 0.5, nb * u_hi + 0.5", "nb * u_lo, nb * u_hi"),
+    "sample normal factor sign": ("np.maximum(0.0, -_dot(n_j, l_j))", "np.maximum(0.0, _dot(n_j, l_j))"),
+    "GI counts all covered sectors": ("new = b_j & ~b_i", "new = b_j"),
+    "ambient weight over the subregion": ("free / nb", "free / per"),
+    "first step at zero offset": ("o = q * (j + 1) +", "o = q * j +"),
+    "exact position ignores the side": ("X_e = xs + 0.5 + s * o * dx_i / 65536.0",
+                                        "X_e = xs + 0.5 + o * dx_i / 65536.0"),
+    "slice tangent sign": ("e = d3 - _dot(d3, v)[:, None] * v", "e = d3 + _dot(d3, v)[:, None] * v"),
+    "AO as occlusion": ("ao_sum += 1.0 - b_i.sum(axis=1) / nb", "ao_sum += b_i.sum(axis=1) / nb"),
+    "transposed view-to-world": ("a_k @ Rvw.T", "a_k @ Rvw"),
+    "image y not flipped": ("-(Y_e - cy) / fy", "(Y_e - cy) / fy"),
+    "hemisphere clamp too tight": ("theta_f = np.clip(theta_f, -np.pi / 2, np.pi / 2)",
+                                   "theta_f = np.clip(theta_f, -np.pi / 2.2, np.pi / 2.2)"),
+    "ambient direction at subregion edge": ("(k + 0.5) * np.pi / na", "k * np.pi / na"),
+    "view vector away from camera": ("v = -r_p / np.linalg.norm", "v = r_p / np.linalg.norm"),
+    "gamma operands swapped": ("np.arctan2(n_e, n_v)", "np.arctan2(n_v, n_e)"),
+    "GI weight ignores new-sector count": ("(cnt / nb) *", "(1.0 / nb) *"),
+    "centre normal factor dropped": ("np.maximum(0.0, _dot(n_p, l_j))", "1.0"),
+    "mask not accumulated": ("b_i |= b_j", "b_i = b_i | (b_j & False)"),
+    "slices cover half a turn": ("(i * 65536 + rho16) // (16 * nd)", "(i * 65536 + rho16) // (32 * nd)"),
+    "direction table sine": ("dy = np.floor(LUT_ONE * np.sin(phi) + 0.5)", "dy = np.floor(LUT_ONE * np.cos(phi) + 0.5)"),
+    "projected radius halved": ("16.0 * _f32(prm.radius)", "8.0 * _f32(prm.radius)"),
+    "lattice drops the half pixel": ("X = ((xs << 16) + 32768 + s * o * dx_i) >> 16",
+                                     "X = ((xs << 16) + s * o * dx_i) >> 16"),
+    "thickness slope sign": ("t0 + tk *", "t0 - tk *"),
+    "ambient counts occluded sectors": ("(~b_i[:, k * per:(k + 1) * per])", "(b_i[:, k * per:(k + 1) * per])"),
+    "GI reads the centre radiance": ("c_j = rad64[Yc, Xc]", "c_j = rad64[ys, xs]"),
+    "GI light direction reversed": ("l_j = delta / np.linalg.norm", "l_j = -delta / np.linalg.norm"),
+    "front/back not ordered": ("t_min, t_max = np.minimum(theta_f, theta_b), np.maximum(theta_f, theta_b)",
+                               "t_min, t_max = theta_f, theta_b"),
+    "jitter too large": ("((q * xi8[:, i]) >> 8)", "((q * xi8[:, i]) >> 5)"),
+    "background samples kept": ("ok &= np.isfinite(z_s) & (z_s > 0)", "ok &= np.isfinite(z_s)"),
+    "step floor not clamped": ("return np.clip(q, q_min, q_max)", "return np.clip(q, 1, q_max)"),
+}
+
+
+def _mutant(name, old, new):
+    src = open(ORACLE_SRC).read()
+    assert src.count(old) >= 1, f"mutation '{name}' does not apply"
+    modname = "oracle_mutant_" + str(abs(hash(name)))
+    mod = types.ModuleType(modname)
+    sys.modules[modname] = mod  # dataclasses look their module up here
+    exec(compile(src.replace(old, new), ORACLE_SRC + f" [{name}]", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(name):
+    old, new = MUTATIONS[name]
+    O = _mutant(name, old, new)
+    for pin in P.ALL_PINS:
+        try:
+            pin(O)
+        except Exception:
+            return
+    pytest.fail(f"no pin caught the planted mistake: {name}")
