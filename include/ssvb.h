@@ -1,0 +1,184 @@
+/*
+ * ssvb.h - C ABI of the screen-space visibility-bitmask gather on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The operation is the per-pixel gather of Therrien, Levesque and Gilet, "Screen Space
+ * Indirect Lighting with Visibility Bitmask" (arXiv 2301.11376): Algorithm 1 (ambient
+ * occlusion and indirect diffuse light from an N_b-sector visibility bitmask per
+ * hemisphere slice, Section 3.1 and Section 3.3) plus directionally occluded ambient
+ * light (Section 3.2).  Inputs are the single-layer G-buffer the paper assumes: linear
+ * view depth, view-space normals and an HDR buffer of direct light (Section 4.3).
+ *
+ * Conventions shared by every entry point
+ *  - Images are row-major, interleaved channels (HWC).  Pixel (x, y) has its centre at
+ *    (x + 0.5, y + 0.5); image y grows downward.  View space: x right, y up, camera
+ *    looking down -z.  The view ray through screen point (X, Y) is
+ *    ((X - cx)/fx, -(Y - cy)/fy, -1); a point at linear view depth z on it is z * ray.
+ *  - Depth <= 0 or non-finite marks background.  A background pixel outputs AO = 1,
+ *    GI = 0, ambient = 0 and empty masks; background samples are skipped.
+ *  - Normals must be unit view-space vectors (used as stored).  Radiance is RGB.
+ *  - Every image and output pointer is DEVICE memory owned by the caller.  The library
+ *    never frees, retains or writes through caller memory after the call's work on the
+ *    caller's stream has completed.
+ *  - Calls that launch work are asynchronous on the caller's HIP stream (NULL = the
+ *    legacy default stream).  Errors are returned, never thrown; arguments are validated
+ *    before anything is launched, so an error leaves the outputs untouched.
+ *  - A context may be used from one host thread at a time.
+ */
+#ifndef SSVB_H
+#define SSVB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSVB_OK = 0,
+    SSVB_ERR_INVALID_ARG = 1,   /* a pointer, size, pitch or parameter is out of range */
+    SSVB_ERR_UNSUPPORTED = 2,   /* valid request the GPU path does not implement (N_b != 32) */
+    SSVB_ERR_OUT_OF_MEMORY = 3, /* device allocation failed, or a request exceeds a budget */
+    SSVB_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+    SSVB_ERR_BUSY = 5,          /* the resource is in use (server slot or queue full) */
+    SSVB_ERR_TIMEOUT = 6,       /* a wait exceeded its deadline */
+    SSVB_ERR_NOT_FOUND = 7      /* unknown ticket or handle */
+} ssvb_status;
+
+typedef enum { SSVB_F32 = 0, SSVB_F16 = 1 } ssvb_dtype;
+
+/* Hit criterion (Section 3.1).  ROUND sets a sector iff its centre lies in the sample's
+ * angular interval ("at least half covered").  PSEUDOCODE takes the floor of the start
+ * and the ceiling of the width, as Algorithm 1 prints it. */
+typedef enum { SSVB_HIT_ROUND = 0, SSVB_HIT_PSEUDOCODE = 1 } ssvb_hit_criterion;
+
+/* Per-pixel slice rotation and per-slice step jitter (Algorithm 1: directions with a
+ * random offset; Section 4.3: jitter along the sampling direction).
+ *  HASH : rho = pcg(x + pcg(y + pcg(seed))) >> 16, the PCG hash of Jarzynski and Olano
+ *         (JCGT 2020);
+ *  R2   : rho = (x a1 + y a2 + seed a3 mod 2^32) >> 16, Roberts' R2 dither
+ *         (a1 = round(2^32/g), a2 = round(2^32/g^2), g the plastic number,
+ *          a3 = round(2^32/phi));
+ *  FIXED: rho = 0, no jitter.
+ * In HASH and R2 the jitter of slice i is pcg(x + pcg(y + pcg(seed + 1 + i))) >> 24. */
+typedef enum { SSVB_NOISE_HASH = 0, SSVB_NOISE_R2 = 1, SSVB_NOISE_FIXED = 2 } ssvb_noise;
+
+/* One image.  ptr: device pointer aligned to its element size.  pitch_bytes: bytes
+ * between rows, 0 = dense (width * channels * element size).  dtype: ssvb_dtype.
+ * channels: 1 for depth (F32 only), 3 or 4 for normals and radiance (the fourth
+ * channel is ignored). */
+typedef struct {
+    const void* ptr;
+    int64_t pitch_bytes;
+    int32_t dtype;
+    int32_t channels;
+} ssvb_image;
+
+/* Pinhole camera.  width, height in [0, 16384].  fx, fy > 0 in pixels.
+ * view_to_world: row-major rotation, world_dir = M * view_dir (used for the ambient
+ * probe, which lives in world space). */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float view_to_world[9];
+} ssvb_camera;
+
+/* Sampling parameters (Algorithm 1; Sections 3.1-3.3).
+ *  slices           N_d, hemisphere slices per pixel, 1..64
+ *  steps            N_s, depth samples per side of each slice, 1..1024
+ *  sectors          N_b, bits of the visibility mask; the GPU path requires 32
+ *  ambient_samples  N_a, ambient subregions per slice, divides 32
+ *  radius           world-space radius of the screen-aligned hemisphere, > 0
+ *  thickness        t0 >= 0 (+inf allowed: GTAO without falloff, Section 3.1)
+ *  thickness_slope  k >= 0: each pixel uses t = t0 + k * depth (Section 3.1)
+ *  max_radius_px    0, or a cap in pixels on the projected radius (hard cap 16383)
+ *  min_step_q4      shortest step in 1/16 pixel, 1..16 (16 keeps samples off the
+ *                   centre pixel)
+ *  hit_criterion    ssvb_hit_criterion
+ *  noise, seed      ssvb_noise and its 32-bit seed
+ *  ambient_sh       L2 real spherical-harmonic probe, world space, [9][3]
+ *                   coefficient-major RGB (the ambient light source of Section 3.2) */
+typedef struct {
+    int32_t slices, steps, sectors, ambient_samples;
+    float radius, thickness, thickness_slope, max_radius_px;
+    int32_t min_step_q4;
+    int32_t hit_criterion;
+    int32_t noise;
+    uint32_t seed;
+    float ambient_sh[27];
+} ssvb_params;
+
+/* Outputs, FP32, device memory.  ao [H][W]; gi and ambient [H][W][3]; masks, if not
+ * NULL, [H][W][N_d] uint32 with bit k = sector k (sector k spans angles
+ * [-pi/2 + k pi/32, -pi/2 + (k+1) pi/32] from the projected normal, k increasing toward
+ * the slice direction).  Pitches in bytes, 0 = dense.  AO is visibility (1 = open). */
+typedef struct {
+    float* ao;
+    float* gi;
+    float* ambient;
+    uint32_t* masks;
+    int64_t ao_pitch_bytes, gi_pitch_bytes, ambient_pitch_bytes, masks_pitch_bytes;
+} ssvb_outputs;
+
+typedef struct ssvb_ctx ssvb_ctx;
+
+/* Human-readable name of a status code.  Never NULL. */
+const char* ssvb_status_string(ssvb_status s);
+
+/* Detail of the most recent error raised on the calling host thread ("" if none). */
+const char* ssvb_last_error(void);
+
+/* Fill *p with the defaults: 4 slices, 16 steps, 32 sectors, 4 ambient samples,
+ * radius 1, thickness 0.5, slope 0, no pixel cap, min step 16, ROUND, HASH, seed 0,
+ * zero ambient probe. */
+void ssvb_default_params(ssvb_params* p);
+
+/* Create a context on HIP device `device`: uploads the slice-direction table.  The
+ * context owns only its own device buffers.  *out receives the handle. */
+ssvb_status ssvb_create(int32_t device, ssvb_ctx** out);
+
+/* Destroy a context created by ssvb_create (NULL is ignored).  Waits for nothing: the
+ * caller must have synchronised the streams it used with this context. */
+ssvb_status ssvb_destroy(ssvb_ctx* ctx);
+
+/* Host-only argument check of one frame, exactly as ssvb_compute performs it; touches
+ * no device and needs no context. */
+ssvb_status ssvb_validate(const ssvb_image* depth, const ssvb_image* normal,
+                          const ssvb_image* radiance, const ssvb_camera* camera,
+                          const ssvb_params* params, const ssvb_outputs* out);
+
+/* The visibility-bitmask gather of one frame (Algorithm 1 with the ambient term of
+ * Section 3.2): writes AO, GI (RGB indirect diffuse) and ambient (RGB), each divided by
+ * N_d, and optionally the N_d slice masks.  Asynchronous on `hip_stream`. */
+ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
+                         const ssvb_image* radiance, const ssvb_camera* camera,
+                         const ssvb_params* params, const ssvb_outputs* out, void* hip_stream);
+
+/* Test hook: the integer step lattice of ssvb_compute.  xy_out (device, int32) receives,
+ * for every pixel, slice, side (+ then -) and step, the sampled texel (X, Y), laid out
+ * [H][W][N_d][2][N_s][2] densely.  Same validation of depth/camera/params. */
+ssvb_status ssvb_debug_lattice(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_camera* camera,
+                               const ssvb_params* params, int32_t* xy_out, void* hip_stream);
+
+/* Test hook: the FP32 sector-boundary arguments of every sample, as ssvb_compute
+ * computes them before its FP64 re-decision near a boundary.  ep_out (device, float)
+ * receives [H][W][N_d][2][N_s][2]: for ROUND the two values whose floor gives the
+ * sample's sectors [a, b) (32 u + 1/2 at each end of its angular interval, u in [0, 1]
+ * across the hemisphere), for PSEUDOCODE the floor argument of the start and the ceiling
+ * argument of the width.  Skipped samples are NaN. */
+ssvb_status ssvb_debug_endpoints(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
+                                 const ssvb_camera* camera, const ssvb_params* params, float* ep_out,
+                                 void* hip_stream);
+
+/* Test hook: copy the 4096-entry slice-direction table (Dx, Dy pairs, fixed point
+ * 1 = 4096, direction pi k / 4096) to host memory `host_out` (8192 int32). */
+ssvb_status ssvb_debug_direction_table(ssvb_ctx* ctx, int32_t* host_out);
+
+/* Test hook: the R2 constants a1, a2, a3 (host memory, 3 uint32).  Host only. */
+void ssvb_debug_noise_constants(uint32_t* host_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSVB_H */

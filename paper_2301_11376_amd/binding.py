@@ -1,0 +1,271 @@
+"""ctypes binding of libssvb.so (the C ABI in include/ssvb.h).
+
+Argument marshalling only: every step of the gather runs in the HIP library.  Torch
+tensors supply device memory and the stream; nothing here computes on the data.  The
+library must have been built (``paper_2301_11376_amd.build_lib.build()``); loading
+fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libssvb.so")
+
+SSVB_OK = 0
+STATUS = {0: "SSVB_OK", 1: "SSVB_ERR_INVALID_ARG", 2: "SSVB_ERR_UNSUPPORTED", 3: "SSVB_ERR_OUT_OF_MEMORY",
+          4: "SSVB_ERR_DEVICE", 5: "SSVB_ERR_BUSY", 6: "SSVB_ERR_TIMEOUT", 7: "SSVB_ERR_NOT_FOUND"}
+F32, F16 = 0, 1
+HIT_ROUND, HIT_PSEUDOCODE = 0, 1
+NOISE_HASH, NOISE_R2, NOISE_FIXED = 0, 1, 2
+NOISE_NAMES = {"hash": NOISE_HASH, "r2": NOISE_R2, "fixed": NOISE_FIXED}
+
+# every symbol include/ssvb.h declares
+EXPORTED = [
+    "ssvb_status_string", "ssvb_last_error", "ssvb_default_params", "ssvb_create", "ssvb_destroy",
+    "ssvb_validate", "ssvb_compute", "ssvb_debug_lattice", "ssvb_debug_endpoints",
+    "ssvb_debug_direction_table", "ssvb_debug_noise_constants",
+]
+
+
+class ssvb_image(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("pitch_bytes", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("channels", ctypes.c_int32)]
+
+
+class ssvb_camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("view_to_world", ctypes.c_float * 9)]
+
+
+class ssvb_params(ctypes.Structure):
+    _fields_ = [("slices", ctypes.c_int32), ("steps", ctypes.c_int32), ("sectors", ctypes.c_int32),
+                ("ambient_samples", ctypes.c_int32), ("radius", ctypes.c_float), ("thickness", ctypes.c_float),
+                ("thickness_slope", ctypes.c_float), ("max_radius_px", ctypes.c_float),
+                ("min_step_q4", ctypes.c_int32), ("hit_criterion", ctypes.c_int32), ("noise", ctypes.c_int32),
+                ("seed", ctypes.c_uint32), ("ambient_sh", ctypes.c_float * 27)]
+
+
+class ssvb_outputs(ctypes.Structure):
+    _fields_ = [("ao", ctypes.c_void_p), ("gi", ctypes.c_void_p), ("ambient", ctypes.c_void_p),
+                ("masks", ctypes.c_void_p), ("ao_pitch_bytes", ctypes.c_int64), ("gi_pitch_bytes", ctypes.c_int64),
+                ("ambient_pitch_bytes", ctypes.c_int64), ("masks_pitch_bytes", ctypes.c_int64)]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libssvb.so and declare its signatures.  Raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, V = ctypes.POINTER, ctypes.c_int32, ctypes.c_void_p
+    L.ssvb_status_string.restype = ctypes.c_char_p
+    L.ssvb_status_string.argtypes = [I]
+    L.ssvb_last_error.restype = ctypes.c_char_p
+    L.ssvb_last_error.argtypes = []
+    L.ssvb_default_params.restype = None
+    L.ssvb_default_params.argtypes = [P(ssvb_params)]
+    L.ssvb_create.restype = I
+    L.ssvb_create.argtypes = [I, P(V)]
+    L.ssvb_destroy.restype = I
+    L.ssvb_destroy.argtypes = [V]
+    L.ssvb_validate.restype = I
+    L.ssvb_validate.argtypes = [P(ssvb_image), P(ssvb_image), P(ssvb_image), P(ssvb_camera), P(ssvb_params),
+                                P(ssvb_outputs)]
+    L.ssvb_compute.restype = I
+    L.ssvb_compute.argtypes = [V, P(ssvb_image), P(ssvb_image), P(ssvb_image), P(ssvb_camera), P(ssvb_params),
+                               P(ssvb_outputs), V]
+    L.ssvb_debug_lattice.restype = I
+    L.ssvb_debug_lattice.argtypes = [V, P(ssvb_image), P(ssvb_camera), P(ssvb_params), V, V]
+    L.ssvb_debug_endpoints.restype = I
+    L.ssvb_debug_endpoints.argtypes = [V, P(ssvb_image), P(ssvb_image), P(ssvb_camera), P(ssvb_params), V, V]
+    L.ssvb_debug_direction_table.restype = I
+    L.ssvb_debug_direction_table.argtypes = [V, P(ctypes.c_int32)]
+    L.ssvb_debug_noise_constants.restype = None
+    L.ssvb_debug_noise_constants.argtypes = [P(ctypes.c_uint32)]
+    _LIB = L
+    return L
+
+
+class SSVBError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        detail = lib().ssvb_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+
+
+def check(status: int, where: str) -> None:
+    if status != SSVB_OK:
+        raise SSVBError(status, where)
+
+
+# ---------------------------------------------------------------------------------------
+# plain-Python descriptions of a camera and of the sampling parameters
+# ---------------------------------------------------------------------------------------
+
+@dataclass
+class Camera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    view_to_world: tuple = (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0)
+
+    def to_c(self) -> ssvb_camera:
+        c = ssvb_camera(self.width, self.height, self.fx, self.fy, self.cx, self.cy)
+        for i, v in enumerate(self.view_to_world):
+            c.view_to_world[i] = v
+        return c
+
+
+@dataclass
+class Params:
+    slices: int = 4
+    steps: int = 16
+    sectors: int = 32
+    ambient_samples: int = 4
+    radius: float = 1.0
+    thickness: float = 0.5
+    thickness_slope: float = 0.0
+    max_radius_px: float = 0.0
+    min_step_q4: int = 16
+    hit_criterion: int = HIT_ROUND
+    noise: int = NOISE_HASH
+    seed: int = 0
+    ambient_sh: tuple = field(default_factory=lambda: tuple([0.0] * 27))
+
+    def to_c(self) -> ssvb_params:
+        p = ssvb_params(self.slices, self.steps, self.sectors, self.ambient_samples, self.radius, self.thickness,
+                        self.thickness_slope, self.max_radius_px, self.min_step_q4, self.hit_criterion,
+                        self.noise, self.seed & 0xFFFFFFFF)
+        for i, v in enumerate(self.ambient_sh):
+            p.ambient_sh[i] = v
+        return p
+
+
+def image_of(t, channels_expected=None) -> ssvb_image:
+    """Describe a torch tensor [H, W] (depth) or [H, W, C] (normal / radiance)."""
+    import torch
+    if t is None:
+        return ssvb_image(None, 0, F32, 3)
+    if t.dim() == 2:
+        ch = 1
+        if t.stride(1) != 1:
+            raise ValueError("image rows must be contiguous")
+    elif t.dim() == 3:
+        ch = t.shape[2]
+        if t.stride(2) != 1 or t.stride(1) != ch:
+            raise ValueError("image pixels must be contiguous HWC")
+    else:
+        raise ValueError("images are [H, W] or [H, W, C]")
+    if t.dtype == torch.float32:
+        dt, es = F32, 4
+    elif t.dtype == torch.float16:
+        dt, es = F16, 2
+    else:
+        raise ValueError(f"unsupported dtype {t.dtype}")
+    return ssvb_image(t.data_ptr(), t.stride(0) * es, dt, ch)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """An ssvb_ctx on one device (torch's current device by default)."""
+
+    def __init__(self, device: int | None = None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        check(lib().ssvb_create(self.device, ctypes.byref(h)), "ssvb_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ssvb_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compute(self, depth, normal, radiance, camera: Camera, params: Params, out=None, masks=False, stream=None):
+        """Run ssvb_compute on torch device tensors; returns dict(ao, gi, ambient[, masks])."""
+        import torch
+        H, W = depth.shape[:2]
+        dev = depth.device
+        if out is None:
+            out = {"ao": torch.empty((H, W), dtype=torch.float32, device=dev),
+                   "gi": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
+                   "ambient": torch.empty((H, W, 3), dtype=torch.float32, device=dev)}
+            if masks:
+                out["masks"] = torch.empty((H, W, params.slices), dtype=torch.int32, device=dev)
+        o = ssvb_outputs(out["ao"].data_ptr(), out["gi"].data_ptr(), out["ambient"].data_ptr(),
+                         out["masks"].data_ptr() if out.get("masks") is not None else None,
+                         out["ao"].stride(0) * 4, out["gi"].stride(0) * 4, out["ambient"].stride(0) * 4,
+                         out["masks"].stride(0) * 4 if out.get("masks") is not None else 0)
+        d, n, r = image_of(depth), image_of(normal), image_of(radiance)
+        c, p = camera.to_c(), params.to_c()
+        check(lib().ssvb_compute(self.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(r), ctypes.byref(c),
+                                 ctypes.byref(p), ctypes.byref(o), _stream_ptr(stream)), "ssvb_compute")
+        return out
+
+    def debug_lattice(self, depth, camera: Camera, params: Params, stream=None):
+        import torch
+        H, W = depth.shape[:2]
+        xy = torch.empty((H, W, params.slices, 2, params.steps, 2), dtype=torch.int32, device=depth.device)
+        d, c, p = image_of(depth), camera.to_c(), params.to_c()
+        check(lib().ssvb_debug_lattice(self.handle, ctypes.byref(d), ctypes.byref(c), ctypes.byref(p),
+                                       ctypes.c_void_p(xy.data_ptr()), _stream_ptr(stream)), "ssvb_debug_lattice")
+        return xy
+
+    def debug_endpoints(self, depth, normal, camera: Camera, params: Params, stream=None):
+        import torch
+        H, W = depth.shape[:2]
+        ep = torch.empty((H, W, params.slices, 2, params.steps, 2), dtype=torch.float32, device=depth.device)
+        d, n, c, p = image_of(depth), image_of(normal), camera.to_c(), params.to_c()
+        check(lib().ssvb_debug_endpoints(self.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(c),
+                                         ctypes.byref(p), ctypes.c_void_p(ep.data_ptr()), _stream_ptr(stream)),
+              "ssvb_debug_endpoints")
+        return ep
+
+    def direction_table(self):
+        buf = (ctypes.c_int32 * 8192)()
+        check(lib().ssvb_debug_direction_table(self.handle, buf), "ssvb_debug_direction_table")
+        return [(buf[2 * k], buf[2 * k + 1]) for k in range(4096)]
+
+
+def default_params() -> ssvb_params:
+    p = ssvb_params()
+    lib().ssvb_default_params(ctypes.byref(p))
+    return p
+
+
+def validate(depth: ssvb_image, normal: ssvb_image, radiance: ssvb_image, camera: ssvb_camera, params: ssvb_params,
+             out: ssvb_outputs) -> int:
+    """Host-only argument check (no device, no context); returns the status code."""
+    return lib().ssvb_validate(ctypes.byref(depth), ctypes.byref(normal), ctypes.byref(radiance),
+                               ctypes.byref(camera), ctypes.byref(params), ctypes.byref(out))
+
+
+def noise_constants():
+    buf = (ctypes.c_uint32 * 3)()
+    lib().ssvb_debug_noise_constants(buf)
+    return list(buf)

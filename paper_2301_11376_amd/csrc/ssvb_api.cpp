@@ -1,0 +1,365 @@
+// C ABI of the visibility-bitmask gather: argument validation, per-frame constants,
+// context management and kernel launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "ssvb_internal.h"
+
+namespace ssvb {
+hipError_t launch_plain(const FrameArgs& A, hipStream_t stream);
+hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream);
+hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t stream);
+}  // namespace ssvb
+
+using namespace ssvb;
+
+struct ssvb_ctx {
+    int device = 0;
+    int2* d_lut = nullptr;
+    int2 h_lut[kLutSize];
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ssvb_status fail(ssvb_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+ssvb_status hip_fail(hipError_t e, const char* what) {
+    return fail(SSVB_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite(float v) { return isfinite(v) != 0; }
+
+int64_t elem_size(int32_t dtype) { return dtype == SSVB_F16 ? 2 : 4; }
+
+ssvb_status check_image(const ssvb_image* im, const char* name, int32_t W, int32_t H, bool is_depth) {
+    if (!im) return fail(SSVB_ERR_INVALID_ARG, "%s: NULL image descriptor", name);
+    if (is_depth) {
+        if (im->dtype != SSVB_F32 || im->channels != 1)
+            return fail(SSVB_ERR_INVALID_ARG, "%s: depth must be F32 with 1 channel", name);
+    } else {
+        if (im->dtype != SSVB_F32 && im->dtype != SSVB_F16)
+            return fail(SSVB_ERR_INVALID_ARG, "%s: dtype %d is not F32 or F16", name, im->dtype);
+        if (im->channels != 3 && im->channels != 4)
+            return fail(SSVB_ERR_INVALID_ARG, "%s: %d channels (need 3 or 4)", name, im->channels);
+    }
+    if ((int64_t)W * H == 0) return SSVB_OK;
+    if (!im->ptr) return fail(SSVB_ERR_INVALID_ARG, "%s: NULL pointer", name);
+    const int64_t es = elem_size(im->dtype);
+    if ((uintptr_t)im->ptr % es) return fail(SSVB_ERR_INVALID_ARG, "%s: pointer not aligned to %lld bytes", name, (long long)es);
+    const int64_t row = (int64_t)W * im->channels * es;
+    if (im->pitch_bytes != 0 && (im->pitch_bytes < row || im->pitch_bytes % es))
+        return fail(SSVB_ERR_INVALID_ARG, "%s: pitch %lld bytes (row needs %lld, multiple of %lld)", name,
+                    (long long)im->pitch_bytes, (long long)row, (long long)es);
+    return SSVB_OK;
+}
+
+ssvb_status check_out_pitch(int64_t pitch, int64_t row, const char* name) {
+    if (pitch != 0 && (pitch < row || pitch % 4))
+        return fail(SSVB_ERR_INVALID_ARG, "%s: pitch %lld bytes (row needs %lld, multiple of 4)", name,
+                    (long long)pitch, (long long)row);
+    return SSVB_OK;
+}
+
+ssvb_status check_camera_params(const ssvb_camera* cam, const ssvb_params* p) {
+    if (!cam) return fail(SSVB_ERR_INVALID_ARG, "NULL camera");
+    if (!p) return fail(SSVB_ERR_INVALID_ARG, "NULL params");
+    if (cam->width < 0 || cam->height < 0 || cam->width > kMaxDim || cam->height > kMaxDim)
+        return fail(SSVB_ERR_INVALID_ARG, "image %dx%d outside [0, %d]", cam->width, cam->height, kMaxDim);
+    if (!(finite(cam->fx) && cam->fx > 0 && finite(cam->fy) && cam->fy > 0))
+        return fail(SSVB_ERR_INVALID_ARG, "focal lengths must be finite and > 0");
+    if (!(finite(cam->cx) && finite(cam->cy))) return fail(SSVB_ERR_INVALID_ARG, "principal point not finite");
+    for (int i = 0; i < 9; ++i)
+        if (!finite(cam->view_to_world[i])) return fail(SSVB_ERR_INVALID_ARG, "view_to_world not finite");
+    if (p->slices < 1 || p->slices > kMaxSlices)
+        return fail(SSVB_ERR_INVALID_ARG, "slices %d outside [1, %d]", p->slices, kMaxSlices);
+    if (p->steps < 1 || p->steps > kMaxSteps)
+        return fail(SSVB_ERR_INVALID_ARG, "steps %d outside [1, %d]", p->steps, kMaxSteps);
+    if (p->sectors <= 0) return fail(SSVB_ERR_INVALID_ARG, "sectors %d must be > 0", p->sectors);
+    if (p->sectors != kSectors) return fail(SSVB_ERR_UNSUPPORTED, "sectors %d: the GPU path implements 32", p->sectors);
+    const int na = p->ambient_samples;
+    if (na < 1 || na > 32 || (32 % na) != 0)
+        return fail(SSVB_ERR_INVALID_ARG, "ambient_samples %d must divide 32", na);
+    if (!(finite(p->radius) && p->radius > 0)) return fail(SSVB_ERR_INVALID_ARG, "radius must be finite and > 0");
+    if (!(p->thickness >= 0)) return fail(SSVB_ERR_INVALID_ARG, "thickness must be >= 0 (inf allowed)");
+    if (!(finite(p->thickness_slope) && p->thickness_slope >= 0))
+        return fail(SSVB_ERR_INVALID_ARG, "thickness_slope must be finite and >= 0");
+    if (!(finite(p->max_radius_px) && p->max_radius_px >= 0))
+        return fail(SSVB_ERR_INVALID_ARG, "max_radius_px must be finite and >= 0");
+    if (p->min_step_q4 < 1 || p->min_step_q4 > 16)
+        return fail(SSVB_ERR_INVALID_ARG, "min_step_q4 %d outside [1, 16]", p->min_step_q4);
+    if (p->hit_criterion != SSVB_HIT_ROUND && p->hit_criterion != SSVB_HIT_PSEUDOCODE)
+        return fail(SSVB_ERR_INVALID_ARG, "unknown hit criterion %d", p->hit_criterion);
+    if (p->noise != SSVB_NOISE_HASH && p->noise != SSVB_NOISE_R2 && p->noise != SSVB_NOISE_FIXED)
+        return fail(SSVB_ERR_INVALID_ARG, "unknown noise mode %d", p->noise);
+    for (int i = 0; i < 27; ++i)
+        if (!finite(p->ambient_sh[i])) return fail(SSVB_ERR_INVALID_ARG, "ambient_sh not finite");
+    return SSVB_OK;
+}
+
+void r2_constants(uint32_t out[3]) {
+    // Roberts' R2 sequence: g is the plastic number, the real root of g^3 = g + 1
+    long double g = 1.3L;
+    for (int i = 0; i < 100; ++i) g -= (g * g * g - g - 1.0L) / (3.0L * g * g - 1.0L);
+    const long double two32 = 4294967296.0L;
+    const long double phi = (1.0L + sqrtl(5.0L)) / 2.0L;
+    out[0] = (uint32_t)llroundl(two32 / g);
+    out[1] = (uint32_t)llroundl(two32 / (g * g));
+    out[2] = (uint32_t)llroundl(two32 / phi);
+}
+
+// Fill the frame constants: FP64 derivation, one rounding to FP32.
+void fill_frame(FrameArgs& A, const ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
+                const ssvb_image* radiance, const ssvb_camera* cam, const ssvb_params* p, const ssvb_outputs* out) {
+    memset(&A, 0, sizeof A);
+    const int W = cam->width, H = cam->height;
+    A.W = W;
+    A.H = H;
+    A.depth = (const float*)depth->ptr;
+    A.depth_pitch = depth->pitch_bytes ? depth->pitch_bytes : (int64_t)W * 4;
+    if (normal) {
+        A.normal = (const char*)normal->ptr;
+        A.normal_ch = normal->channels;
+        A.normal_f16 = normal->dtype == SSVB_F16;
+        A.normal_pitch = normal->pitch_bytes ? normal->pitch_bytes : (int64_t)W * normal->channels * elem_size(normal->dtype);
+    }
+    if (radiance) {
+        A.radiance = (const char*)radiance->ptr;
+        A.radiance_ch = radiance->channels;
+        A.radiance_f16 = radiance->dtype == SSVB_F16;
+        A.radiance_pitch =
+            radiance->pitch_bytes ? radiance->pitch_bytes : (int64_t)W * radiance->channels * elem_size(radiance->dtype);
+    }
+    if (out) {
+        A.ao = out->ao;
+        A.gi = out->gi;
+        A.amb = out->ambient;
+        A.masks = out->masks;
+        A.ao_pitch = out->ao_pitch_bytes ? out->ao_pitch_bytes : (int64_t)W * 4;
+        A.gi_pitch = out->gi_pitch_bytes ? out->gi_pitch_bytes : (int64_t)W * 12;
+        A.amb_pitch = out->ambient_pitch_bytes ? out->ambient_pitch_bytes : (int64_t)W * 12;
+        A.masks_pitch = out->masks_pitch_bytes ? out->masks_pitch_bytes : (int64_t)W * p->slices * 4;
+    }
+    A.fx = cam->fx;
+    A.fy = cam->fy;
+    A.cx = cam->cx;
+    A.cy = cam->cy;
+    A.inv_fx = (float)(1.0 / cam->fx);
+    A.inv_fy = (float)(1.0 / cam->fy);
+    A.d3x = (float)(1.0 / (4096.0 * cam->fx));
+    A.d3y = (float)(-1.0 / (4096.0 * cam->fy));
+    for (int i = 0; i < 9; ++i) A.Rvw[i] = cam->view_to_world[i];
+    A.nd = p->slices;
+    A.ns = p->steps;
+    A.na = p->ambient_samples;
+    A.criterion = p->hit_criterion;
+    A.noise = p->noise;
+    A.seed = p->seed;
+    uint32_t r2[3];
+    r2_constants(r2);
+    A.r2a1 = r2[0];
+    A.r2a2 = r2[1];
+    A.r2a3 = r2[2];
+    // step = r / (N_s + 1) with r = radius fy / z pixels; in 1/16 px: C / z
+    A.c_step = (float)(16.0 * (double)p->radius * (double)cam->fy / (double)(p->steps + 1));
+    const double rcap = p->max_radius_px > 0 ? fmin((double)p->max_radius_px, (double)kLatticeCapPx) : (double)kLatticeCapPx;
+    A.q_min = p->min_step_q4;
+    A.q_max = (int32_t)fmax((double)A.q_min, floor(16.0 * rcap / (double)(p->steps + 1)));
+    A.q_max_f = (float)A.q_max;
+    A.t0 = p->thickness;
+    A.tk = p->thickness_slope;
+    for (int i = 0; i < 27; ++i) A.sh[i] = p->ambient_sh[i];
+    for (int k = 0; k < p->ambient_samples; ++k) {
+        const double beta = -0.5 * M_PI + (k + 0.5) * M_PI / p->ambient_samples;
+        A.amb_cb[k] = (float)cos(beta);
+        A.amb_sb[k] = (float)sin(beta);
+    }
+    A.lut = ctx ? ctx->d_lut : nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ssvb_status_string(ssvb_status s) {
+    switch (s) {
+        case SSVB_OK: return "SSVB_OK";
+        case SSVB_ERR_INVALID_ARG: return "SSVB_ERR_INVALID_ARG";
+        case SSVB_ERR_UNSUPPORTED: return "SSVB_ERR_UNSUPPORTED";
+        case SSVB_ERR_OUT_OF_MEMORY: return "SSVB_ERR_OUT_OF_MEMORY";
+        case SSVB_ERR_DEVICE: return "SSVB_ERR_DEVICE";
+        case SSVB_ERR_BUSY: return "SSVB_ERR_BUSY";
+        case SSVB_ERR_TIMEOUT: return "SSVB_ERR_TIMEOUT";
+        case SSVB_ERR_NOT_FOUND: return "SSVB_ERR_NOT_FOUND";
+    }
+    return "SSVB_ERR_UNKNOWN";
+}
+
+const char* ssvb_last_error(void) { return g_last_error.c_str(); }
+
+void ssvb_default_params(ssvb_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof *p);
+    p->slices = 4;
+    p->steps = 16;
+    p->sectors = 32;
+    p->ambient_samples = 4;
+    p->radius = 1.0f;
+    p->thickness = 0.5f;
+    p->thickness_slope = 0.0f;
+    p->max_radius_px = 0.0f;
+    p->min_step_q4 = 16;
+    p->hit_criterion = SSVB_HIT_ROUND;
+    p->noise = SSVB_NOISE_HASH;
+    p->seed = 0;
+}
+
+ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
+    if (!out) return fail(SSVB_ERR_INVALID_ARG, "NULL output handle");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(SSVB_ERR_INVALID_ARG, "device %d of %d", device, count);
+    ssvb_ctx* ctx = new (std::nothrow) ssvb_ctx();
+    if (!ctx) return fail(SSVB_ERR_OUT_OF_MEMORY, "host allocation");
+    ctx->device = device;
+    for (int k = 0; k < kLutSize; ++k) {
+        const double phi = M_PI * k / kLutSize;
+        ctx->h_lut[k] = make_int2((int)floor(kLutOne * cos(phi) + 0.5), (int)floor(kLutOne * sin(phi) + 0.5));
+    }
+    int prev = 0;
+    hipGetDevice(&prev);
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "hipSetDevice");
+    }
+    e = hipMalloc((void**)&ctx->d_lut, sizeof ctx->h_lut);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_lut, ctx->h_lut, sizeof ctx->h_lut, hipMemcpyHostToDevice);
+    hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (ctx->d_lut) hipFree(ctx->d_lut);
+        delete ctx;
+        return e == hipErrorOutOfMemory ? fail(SSVB_ERR_OUT_OF_MEMORY, "direction table") : hip_fail(e, "direction table");
+    }
+    *out = ctx;
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_destroy(ssvb_ctx* ctx) {
+    if (!ctx) return SSVB_OK;
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    if (ctx->d_lut) hipFree(ctx->d_lut);
+    hipSetDevice(prev);
+    delete ctx;
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_validate(const ssvb_image* depth, const ssvb_image* normal, const ssvb_image* radiance,
+                          const ssvb_camera* camera, const ssvb_params* params, const ssvb_outputs* out) {
+    ssvb_status s = check_camera_params(camera, params);
+    if (s) return s;
+    const int W = camera->width, H = camera->height;
+    if ((s = check_image(depth, "depth", W, H, true))) return s;
+    if ((s = check_image(normal, "normal", W, H, false))) return s;
+    if ((s = check_image(radiance, "radiance", W, H, false))) return s;
+    if (!out) return fail(SSVB_ERR_INVALID_ARG, "NULL outputs");
+    if ((int64_t)W * H == 0) return SSVB_OK;
+    if (!out->ao || !out->gi || !out->ambient) return fail(SSVB_ERR_INVALID_ARG, "ao, gi and ambient are required");
+    if (((uintptr_t)out->ao | (uintptr_t)out->gi | (uintptr_t)out->ambient | (uintptr_t)out->masks) % 4)
+        return fail(SSVB_ERR_INVALID_ARG, "outputs must be 4-byte aligned");
+    if ((s = check_out_pitch(out->ao_pitch_bytes, (int64_t)W * 4, "ao"))) return s;
+    if ((s = check_out_pitch(out->gi_pitch_bytes, (int64_t)W * 12, "gi"))) return s;
+    if ((s = check_out_pitch(out->ambient_pitch_bytes, (int64_t)W * 12, "ambient"))) return s;
+    if (out->masks && (s = check_out_pitch(out->masks_pitch_bytes, (int64_t)W * params->slices * 4, "masks")))
+        return s;
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal, const ssvb_image* radiance,
+                         const ssvb_camera* camera, const ssvb_params* params, const ssvb_outputs* out,
+                         void* hip_stream) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    ssvb_status s = ssvb_validate(depth, normal, radiance, camera, params, out);
+    if (s) return s;
+    if ((int64_t)camera->width * camera->height == 0) return SSVB_OK;
+    FrameArgs A;
+    fill_frame(A, ctx, depth, normal, radiance, camera, params, out);
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    hipError_t e = launch_plain(A, (hipStream_t)hip_stream);
+    if (prev != ctx->device) hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "gather launch");
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_debug_lattice(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_camera* camera,
+                               const ssvb_params* params, int32_t* xy_out, void* hip_stream) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    ssvb_status s = check_camera_params(camera, params);
+    if (s) return s;
+    if ((s = check_image(depth, "depth", camera->width, camera->height, true))) return s;
+    if ((int64_t)camera->width * camera->height == 0) return SSVB_OK;
+    if (!xy_out) return fail(SSVB_ERR_INVALID_ARG, "NULL lattice output");
+    FrameArgs A;
+    fill_frame(A, ctx, depth, nullptr, nullptr, camera, params, nullptr);
+    hipError_t e = launch_debug_lattice(A, xy_out, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "lattice launch");
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_debug_endpoints(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
+                                 const ssvb_camera* camera, const ssvb_params* params, float* ep_out,
+                                 void* hip_stream) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    ssvb_status s = check_camera_params(camera, params);
+    if (s) return s;
+    const int W = camera->width, H = camera->height;
+    if ((s = check_image(depth, "depth", W, H, true))) return s;
+    if ((s = check_image(normal, "normal", W, H, false))) return s;
+    if ((int64_t)W * H == 0) return SSVB_OK;
+    if (!ep_out) return fail(SSVB_ERR_INVALID_ARG, "NULL endpoint output");
+    FrameArgs A;
+    fill_frame(A, ctx, depth, normal, nullptr, camera, params, nullptr);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t bytes = (size_t)W * H * params->slices * 2 * params->steps * 2 * sizeof(float);
+    hipError_t e = hipMemsetAsync(ep_out, 0xFF, bytes, st);  // all-ones = NaN for skipped samples
+    if (e == hipSuccess) e = launch_debug_endpoints(A, ep_out, st);
+    if (e != hipSuccess) return hip_fail(e, "endpoint launch");
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_debug_direction_table(ssvb_ctx* ctx, int32_t* host_out) {
+    if (!ctx || !host_out) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
+    int2 tmp[kLutSize];
+    hipError_t e = hipMemcpy(tmp, ctx->d_lut, sizeof tmp, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "direction table copy");
+    for (int k = 0; k < kLutSize; ++k) {
+        host_out[2 * k] = tmp[k].x;
+        host_out[2 * k + 1] = tmp[k].y;
+    }
+    return SSVB_OK;
+}
+
+void ssvb_debug_noise_constants(uint32_t* host_out) {
+    if (host_out) r2_constants(host_out);
+}
+
+}  // extern "C"

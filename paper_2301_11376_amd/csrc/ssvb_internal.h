@@ -1,0 +1,57 @@
+// Internal types shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ssvb.h"
+
+namespace ssvb {
+
+constexpr int kSectors = 32;          // N_b on the GPU: one 32-bit mask per slice
+constexpr int kLutSize = 4096;        // slice directions quantised to pi / 4096
+constexpr int kLutOne = 4096;         // fixed-point 1.0 of the direction table
+constexpr int kLatticeCapPx = 16383;  // hard cap on the projected radius, pixels
+constexpr int kMaxDim = 16384;        // widest / tallest image the int32 lattice allows
+constexpr int kMaxSlices = 64;
+constexpr int kMaxSteps = 1024;
+
+// Everything one frame's kernels need, by value in the kernel arguments.  Camera and
+// sampling constants are derived on the host in FP64 and rounded once to FP32.
+struct FrameArgs {
+    // inputs
+    const float* depth;
+    const char* normal;
+    const char* radiance;
+    int64_t depth_pitch, normal_pitch, radiance_pitch;  // bytes
+    int32_t normal_ch, radiance_ch;                     // 3 or 4
+    int32_t normal_f16, radiance_f16;                   // element type flags
+    // outputs
+    float* ao;
+    float* gi;
+    float* amb;
+    uint32_t* masks;
+    int64_t ao_pitch, gi_pitch, amb_pitch, masks_pitch;  // bytes
+    // image and camera
+    int32_t W, H;
+    float fx, fy, cx, cy;
+    float inv_fx, inv_fy;   // 1 / fx, 1 / fy
+    float d3x, d3y;         // 1 / (4096 fx), -1 / (4096 fy): view direction of one LUT unit
+    float Rvw[9];           // view -> world rotation (ambient probe)
+    // sampling
+    int32_t nd, ns, na;
+    int32_t criterion, noise;
+    uint32_t seed;
+    uint32_t r2a1, r2a2, r2a3;
+    float c_step;           // 16 radius fy / (N_s + 1), FP32
+    float q_max_f;          // q_max as float (exact)
+    int32_t q_min, q_max;   // step length bounds, 1/16 px
+    float t0, tk;           // thickness t = t0 + tk * z
+    float sh[27];           // ambient probe, [9][3]
+    float amb_cb[32];       // cos of the subregion centre offsets -pi/2 + (k + 1/2) pi / N_a
+    float amb_sb[32];       // sin of the same
+    // slice-direction table (device), (Dx, Dy) pairs
+    const int2* lut;
+};
+
+}  // namespace ssvb

@@ -1,0 +1,132 @@
+"""Helpers shared by the GPU parity tests: run the HIP path and the oracle on the same
+seeded inputs, compare element by element and trace every mismatch.
+
+Tolerances (from the target of the work): sector masks exact on >= 99.9 % of pixels,
+every mismatch explained by an endpoint within 1e-6 rad of a rounding boundary; AO,
+GI and ambient within 1e-3 absolute for FP32 inputs (the oracle reads the same FP32 /
+FP16 values the GPU reads, upcast exactly).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+import oracle as O
+
+TOL_FP32 = 1e-3
+MASK_AGREEMENT = 0.999
+TIE_RAD = 1e-6                       # a mismatch must come from an endpoint this close
+TIE_SECTORS = TIE_RAD * 32 / math.pi  # the same distance in sector units
+
+
+def cams(cam):
+    """(binding Camera, oracle Camera) of a gbuffer_scene CameraSpec."""
+    from paper_2301_11376_amd import Camera
+    return (Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(cam.view_to_world)),
+            O.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(cam.view_to_world)))
+
+
+def params(**kw):
+    """(binding Params, oracle Params) with identical values."""
+    from paper_2301_11376_amd import Params
+    return Params(**kw), O.Params(**kw)
+
+
+def to_device(gb, device="cuda"):
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(device) for k, v in gb.items()}
+
+
+def gpu_run(ctx, gb, cam, prm, masks=True):
+    import torch
+    t = to_device(gb)
+    out = ctx.compute(t["depth"], t["normal"], t["radiance"], cam, prm, masks=masks)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    if masks:
+        res["masks"] = res["masks"].view(np.uint32)
+    return res
+
+
+def compare(gpu, ref, gb, ocam, oprm, pixels=None, tol=TOL_FP32, report=None):
+    """Compare GPU outputs with the oracle's; explain every mismatch by flipping near-tie
+    roundings in an FP64 replay.  ``gpu`` holds full images, ``ref`` the oracle results at
+    ``pixels`` (or full images).  Returns a stats dict; raises AssertionError on failure."""
+    if pixels is None:
+        H, W = gb["depth"].shape
+        ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        ys, xs = ys.reshape(-1), xs.reshape(-1)
+        flat = lambda a: a.reshape((H * W,) + a.shape[2:])
+        ref = {k: flat(v) for k, v in ref.items() if k in ("ao", "gi", "ambient", "masks", "valid")}
+    else:
+        ys, xs = pixels
+    g = {k: gpu[k][ys, xs] for k in ("ao", "gi", "ambient", "masks") if k in gpu}
+    mask_eq = np.all(g["masks"] == ref["masks"], axis=-1) if "masks" in g else np.ones(len(ys), bool)
+    err_ao = np.abs(g["ao"] - ref["ao"])
+    err_gi = np.abs(g["gi"] - ref["gi"]).max(axis=-1)
+    err_amb = np.abs(g["ambient"] - ref["ambient"]).max(axis=-1)
+    bad = ~mask_eq | (err_ao > tol) | (err_gi > tol) | (err_amb > tol)
+    stats = {
+        "pixels": int(len(ys)),
+        "mask_agreement": float(mask_eq.mean()),
+        "mismatched_pixels": int(bad.sum()),
+        "max_err": {"ao": float(err_ao.max(initial=0)), "gi": float(err_gi.max(initial=0)),
+                    "ambient": float(err_amb.max(initial=0))},
+        "mean_err": {"ao": float(err_ao.mean()), "gi": float(err_gi.mean()), "ambient": float(err_amb.mean())},
+        "p99_err": {"ao": float(np.percentile(err_ao, 99)), "gi": float(np.percentile(err_gi, 99)),
+                    "ambient": float(np.percentile(err_amb, 99))},
+        "explained": 0,
+    }
+    unexplained = []
+    for idx in np.flatnonzero(bad)[:200]:
+        if explain_pixel(gpu, gb, ocam, oprm, int(ys[idx]), int(xs[idx]), tol):
+            stats["explained"] += 1
+        else:
+            unexplained.append((int(ys[idx]), int(xs[idx])))
+    if report is not None:
+        report.update(stats)
+    assert bad.sum() <= 200, f"{bad.sum()} mismatched pixels: {stats}"
+    assert not unexplained, f"unexplained mismatches at {unexplained[:10]}: {stats}"
+    assert stats["mask_agreement"] >= MASK_AGREEMENT, stats
+    return stats
+
+
+def explain_pixel(gpu, gb, ocam, oprm, y, x, tol):
+    """Replay pixel (y, x) in FP64 with every combination of flipped near-tie roundings;
+    True if one reproduces the GPU's masks exactly and its outputs within ``tol``."""
+    r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam, oprm, pixels=([y], [x]),
+                  return_endpoints=True)
+    ep = r["endpoints"][0]
+    dist = np.abs(ep - np.round(ep))
+    near = np.argwhere(np.isfinite(ep) & (dist < TIE_SECTORS))
+    if len(near) == 0 or len(near) > 10:
+        return False
+    for flips in itertools.product((0, 1), repeat=len(near)):
+        if not any(flips):
+            continue
+        bias = np.zeros((1,) + ep.shape, dtype=np.int64)
+        for f, pos in zip(flips, near):
+            if f:
+                v = ep[tuple(pos)]
+                bias[(0,) + tuple(pos)] = 1 if v < np.round(v) else -1
+        rr = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam, oprm, pixels=([y], [x]),
+                       return_masks=True, index_bias=bias)
+        if not np.array_equal(rr["masks"][0], gpu["masks"][y, x]):
+            continue
+        if (abs(rr["ao"][0] - gpu["ao"][y, x]) <= tol and np.abs(rr["gi"][0] - gpu["gi"][y, x]).max() <= tol
+                and np.abs(rr["ambient"][0] - gpu["ambient"][y, x]).max() <= tol):
+            return True
+    return False
+
+
+def sample_pixels(H, W, n, seed):
+    """A seeded sample of pixels: random ones plus the four corners and the last row
+    and column (ragged tails)."""
+    rng = np.random.default_rng(seed)
+    ys = rng.integers(0, H, n)
+    xs = rng.integers(0, W, n)
+    extra_y = np.array([0, 0, H - 1, H - 1] + [H - 1] * 8 + list(rng.integers(0, H, 8)))
+    extra_x = np.array([0, W - 1, 0, W - 1] + list(rng.integers(0, W, 8)) + [W - 1] * 8)
+    return np.concatenate([ys, extra_y]), np.concatenate([xs, extra_x])

@@ -1,0 +1,145 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol include/ssvb.h
+declares, and its host-side validation accepts and rejects what the header says.
+No compute call is made (there is no GPU here)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2301_11376_amd import binding, build_lib
+    if not os.path.exists(binding.LIB_PATH):
+        build_lib.build()
+    binding.lib()
+    return binding
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ssvb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssvb_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(B):
+    names = header_functions()
+    assert len(names) >= 10
+    lib = B.lib()
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in ssvb.h but not exported"
+    assert sorted(B.EXPORTED) == names
+
+
+def test_status_strings(B):
+    for code, name in B.STATUS.items():
+        assert B.lib().ssvb_status_string(code).decode() == name
+
+
+def test_default_params(B):
+    p = B.default_params()
+    assert (p.slices, p.steps, p.sectors, p.ambient_samples, p.min_step_q4) == (4, 16, 32, 4, 16)
+    assert (p.radius, p.thickness, p.hit_criterion, p.noise) == (1.0, 0.5, 0, 0)
+    d = B.Params()
+    assert (d.slices, d.steps, d.sectors, d.ambient_samples, d.min_step_q4) == (4, 16, 32, 4, 16)
+
+
+def test_noise_constants_match_oracle(B):
+    # independent derivations of Roberts' R2 constants (C++ long double vs Python Decimal)
+    assert B.noise_constants() == list(O.r2_constants())
+
+
+FAKE = 0x100000  # validation only inspects pointers for NULL and alignment
+
+
+def frame(B, W=64, H=48, **over):
+    d = B.ssvb_image(FAKE, 0, B.F32, 1)
+    n = B.ssvb_image(FAKE, 0, B.F32, 3)
+    r = B.ssvb_image(FAKE, 0, B.F16, 4)
+    c = B.Camera(W, H, 40.0, 40.0, W / 2, H / 2).to_c()
+    p = B.Params(slices=2, steps=8).to_c()
+    o = B.ssvb_outputs(FAKE, FAKE, FAKE, None, 0, 0, 0, 0)
+    parts = dict(d=d, n=n, r=r, c=c, p=p, o=o)
+    for k, fn in over.items():
+        fn(parts[k])
+    return parts
+
+
+def status(B, parts):
+    return B.validate(parts["d"], parts["n"], parts["r"], parts["c"], parts["p"], parts["o"])
+
+
+def setter(attr, value):
+    def fn(obj):
+        setattr(obj, attr, value)
+    return fn
+
+
+def test_validate_accepts_good_frames(B):
+    assert status(B, frame(B)) == 0
+    assert status(B, frame(B, p=setter("thickness", math.inf))) == 0
+    assert status(B, frame(B, W=16384, H=1)) == 0
+    assert status(B, frame(B, W=0, H=0, d=setter("ptr", None), n=setter("ptr", None),
+                           o=setter("ao", None))) == 0
+    assert status(B, frame(B, d=setter("pitch_bytes", 64 * 4 + 256))) == 0
+    assert status(B, frame(B, o=setter("masks", FAKE))) == 0
+
+
+BAD = {
+    "null depth": dict(d=setter("ptr", None)),
+    "misaligned normal": dict(n=setter("ptr", FAKE + 2)),
+    "depth pitch too small": dict(d=setter("pitch_bytes", 4 * 63)),
+    "pitch not a multiple": dict(n=setter("pitch_bytes", 64 * 12 + 2)),
+    "depth as F16": dict(d=setter("dtype", 1)),
+    "two channels": dict(n=setter("channels", 2)),
+    "unknown dtype": dict(r=setter("dtype", 9)),
+    "zero slices": dict(p=setter("slices", 0)),
+    "too many slices": dict(p=setter("slices", 65)),
+    "too many steps": dict(p=setter("steps", 1025)),
+    "zero sectors": dict(p=setter("sectors", 0)),
+    "ambient 3": dict(p=setter("ambient_samples", 3)),
+    "nan radius": dict(p=setter("radius", math.nan)),
+    "negative radius": dict(p=setter("radius", -1.0)),
+    "negative thickness": dict(p=setter("thickness", -0.1)),
+    "nan thickness": dict(p=setter("thickness", math.nan)),
+    "inf slope": dict(p=setter("thickness_slope", math.inf)),
+    "min step 0": dict(p=setter("min_step_q4", 0)),
+    "min step 17": dict(p=setter("min_step_q4", 17)),
+    "criterion 2": dict(p=setter("hit_criterion", 2)),
+    "noise 5": dict(p=setter("noise", 5)),
+    "wide image": dict(c=setter("width", 16385)),
+    "zero focal": dict(c=setter("fx", 0.0)),
+    "null ao": dict(o=setter("ao", None)),
+    "gi pitch too small": dict(o=setter("gi_pitch_bytes", 64 * 12 - 4)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BAD))
+def test_validate_rejects(B, case):
+    assert status(B, frame(B, **BAD[case])) == 1, case
+    assert B.lib().ssvb_last_error().decode() != ""
+
+
+def test_validate_unsupported_sectors(B):
+    assert status(B, frame(B, p=setter("sectors", 64))) == 2
+
+
+def test_validate_nan_probe(B):
+    def bad_sh(p):
+        p.ambient_sh[4] = math.nan
+    assert status(B, frame(B, p=bad_sh)) == 1
+
+
+def test_create_without_gpu_fails_cleanly(B):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert B.lib().ssvb_create(0, ctypes.byref(h)) != 0
+    assert not h.value

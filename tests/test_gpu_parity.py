@@ -1,0 +1,279 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
+
+Bars: integer lattice and direction table bit-exact; sector masks equal on >= 99.9 %
+of pixels with every mismatch traced to an endpoint within 1e-6 rad of a rounding
+boundary; AO / GI / ambient within 1e-3 absolute (FP32 inputs; FP16 inputs are compared
+with the oracle on the same FP16 values, and with the oracle on the FP32 originals
+within 2e-2).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import parity as PY
+from gbuffer_scene import make_camera, make_scene, render_gbuffer, workload
+
+pytestmark = pytest.mark.gpu
+
+INF = float("inf")
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_11376_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+_SCENES = {}
+
+
+def tiny(width=64, height=48, fp16=False, channels=3, seed=7):
+    key = (width, height, fp16, channels, seed)
+    if key not in _SCENES:
+        sc = make_scene(seed, 40, 20)
+        cam = make_camera(width, height, fov_y_deg=60, pitch_deg=-25)
+        dt = np.float16 if fp16 else np.float32
+        gb = render_gbuffer(sc, cam, normal_dtype=dt, radiance_dtype=dt, channels=channels, cache=False)
+        _SCENES[key] = (gb, cam, sc)
+    return _SCENES[key]
+
+
+def run_case(ctx, gb, cam, report=None, pixels=None, **kw):
+    bc, oc = PY.cams(cam)
+    bp, op = PY.params(**kw)
+    gpu = PY.gpu_run(ctx, gb, bc, bp)
+    ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, pixels=pixels, return_masks=True)
+    return PY.compare(gpu, ref, gb, oc, op, pixels=pixels, report=report), gpu
+
+
+def test_direction_table(ctx):
+    dx, dy = O.direction_lut()
+    assert ctx.direction_table() == list(zip(dx.tolist(), dy.tolist()))
+
+
+LATTICE_CASES = [
+    dict(slices=2, steps=8, radius=2.0, noise=O.NOISE_HASH, seed=1),
+    dict(slices=4, steps=16, radius=3.0, noise=O.NOISE_R2, seed=2),
+    dict(slices=3, steps=5, radius=0.3, noise=O.NOISE_FIXED),
+    dict(slices=8, steps=3, radius=5.0, noise=O.NOISE_HASH, seed=0xFFFFFFFF, max_radius_px=20.0),
+    dict(slices=1, steps=40, radius=1.0, noise=O.NOISE_R2, seed=9, min_step_q4=1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(LATTICE_CASES)))
+def test_lattice_bit_exact(ctx, case):
+    import torch
+    kw = LATTICE_CASES[case]
+    gb, cam, _ = tiny()
+    log(f"lattice case {case}: {kw}")
+    bc, oc = PY.cams(cam)
+    bp, op = PY.params(**kw)
+    xy = ctx.debug_lattice(PY.to_device(gb)["depth"], bc, bp)
+    torch.cuda.synchronize()
+    ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, return_lattice=True)["lattice"]
+    assert np.array_equal(xy.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("shape", [(16384, 1), (1, 16384), (3, 4099)])
+def test_lattice_extreme_sizes(ctx, shape):
+    """Largest images the int32 lattice allows, with the longest reach."""
+    import torch
+    W, H = shape
+    log(f"lattice extreme {W}x{H}")
+    depth = np.full((H, W), 0.5, np.float32)
+    cam = make_camera(W, H, fov_y_deg=90, pitch_deg=0)
+    bc, oc = PY.cams(cam)
+    kw = dict(slices=3, steps=2, radius=1e9, noise=O.NOISE_HASH, seed=5)
+    bp, op = PY.params(**kw)
+    xy = ctx.debug_lattice(torch.from_numpy(depth).cuda(), bc, bp)
+    torch.cuda.synchronize()
+    nrm = np.zeros((H, W, 3), np.float32)
+    ref = O.compute(depth, nrm, nrm, oc, op, return_lattice=True)["lattice"]
+    got = xy.cpu().numpy()
+    assert np.array_equal(got, ref)
+    assert np.abs(got).max() > 8000  # the reach really is extreme
+
+
+def test_endpoint_error_within_guard(ctx):
+    """FP32 sector-boundary arguments against FP64: the error stays well inside the
+    band where the kernel re-decides in FP64 (2^-15 sectors)."""
+    import torch
+    gb, cam, _ = tiny()
+    for kw in (dict(slices=4, steps=12, radius=1.5, thickness=0.4, noise=O.NOISE_HASH, seed=3),
+               dict(slices=2, steps=8, radius=3.0, thickness=INF, noise=O.NOISE_R2, seed=4),
+               dict(slices=2, steps=8, radius=1.0, thickness=0.2, noise=O.NOISE_HASH, seed=5, hit_criterion=1)):
+        log(f"endpoints {kw}")
+        bc, oc = PY.cams(cam)
+        bp, op = PY.params(**kw)
+        t = PY.to_device(gb)
+        ep = ctx.debug_endpoints(t["depth"], t["normal"], bc, bp)
+        torch.cuda.synchronize()
+        got = ep.cpu().numpy()
+        ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, return_endpoints=True)["endpoints"]
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        ok = np.isfinite(ref)
+        err = np.abs(got[ok] - ref[ok]).max()
+        log(f"  max endpoint error {err:.3e} sectors ({err * math.pi / 32:.3e} rad) over {ok.sum()} values")
+        assert err < 2.0 ** -16, err
+
+
+def test_parity_c1_full_frame(ctx):
+    gb, cam, w, sc = workload("c1_128")
+    log("parity c1 128x128")
+    rep = {}
+    run_case(ctx, gb, cam, report=rep, slices=2, steps=8, radius=2.0, thickness=0.5, noise=O.NOISE_HASH, seed=1,
+             ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    log(f"  {rep}")
+
+
+VARIANTS = {
+    "hash_t04": dict(slices=3, steps=6, radius=1.2, thickness=0.4, noise=O.NOISE_HASH, seed=11),
+    "r2_tinf": dict(slices=4, steps=10, radius=2.5, thickness=INF, noise=O.NOISE_R2, seed=12),
+    "fixed_thin": dict(slices=2, steps=9, radius=0.8, thickness=0.05, noise=O.NOISE_FIXED),
+    "slope": dict(slices=2, steps=7, radius=1.5, thickness=0.1, thickness_slope=0.05, noise=O.NOISE_HASH, seed=13),
+    "pseudocode": dict(slices=3, steps=6, radius=1.5, thickness=0.3, noise=O.NOISE_HASH, seed=14, hit_criterion=1),
+    "one_slice_one_step": dict(slices=1, steps=1, radius=1.0, noise=O.NOISE_HASH, seed=15),
+    "many_slices": dict(slices=16, steps=3, radius=1.0, noise=O.NOISE_R2, seed=16, ambient_samples=32),
+    "ambient1": dict(slices=2, steps=4, radius=1.0, noise=O.NOISE_HASH, seed=17, ambient_samples=1),
+    "capped_subpixel": dict(slices=2, steps=20, radius=4.0, noise=O.NOISE_HASH, seed=18, max_radius_px=6.0,
+                            min_step_q4=2),
+    "zero_thickness": dict(slices=2, steps=6, radius=1.5, thickness=0.0, noise=O.NOISE_HASH, seed=19),
+}
+
+
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_parity_variants(ctx, name):
+    gb, cam, sc = tiny()
+    log(f"variant {name}")
+    rep = {}
+    run_case(ctx, gb, cam, report=rep, ambient_sh=tuple(sc.ambient_sh.reshape(-1)), **VARIANTS[name])
+    log(f"  {rep}")
+
+
+@pytest.mark.parametrize("shape", [(67, 45), (1, 1), (1, 37), (37, 1), (129, 3)])
+def test_parity_ragged_shapes(ctx, shape):
+    W, H = shape
+    log(f"ragged {W}x{H}")
+    sc = make_scene(21, 40, 20)
+    cam = make_camera(W, H, fov_y_deg=60, pitch_deg=-25)
+    gb = render_gbuffer(sc, cam, cache=False)
+    run_case(ctx, gb, cam, slices=3, steps=5, radius=1.0, noise=O.NOISE_HASH, seed=3,
+             ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+
+
+@pytest.mark.parametrize("fp16,channels", [(False, 4), (True, 3), (True, 4)])
+def test_parity_formats(ctx, fp16, channels):
+    gb, cam, sc = tiny(fp16=fp16, channels=channels)
+    log(f"formats fp16={fp16} channels={channels}")
+    run_case(ctx, gb, cam, slices=3, steps=6, radius=1.3, thickness=0.3, noise=O.NOISE_R2, seed=2,
+             ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+
+
+def test_all_background_and_empty(ctx):
+    import torch
+    log("background / empty")
+    cam = make_camera(20, 10)
+    gb = {"depth": np.zeros((10, 20), np.float32), "normal": np.zeros((10, 20, 3), np.float32),
+          "radiance": np.zeros((10, 20, 3), np.float32)}
+    gb["depth"][3, 4] = np.nan
+    gb["depth"][5, 6] = np.inf
+    gb["depth"][7, 8] = -1.0
+    bc, _ = PY.cams(cam)
+    bp, _ = PY.params(slices=2, steps=4)
+    out = PY.gpu_run(ctx, gb, bc, bp)
+    assert np.all(out["ao"] == 1) and np.all(out["gi"] == 0) and np.all(out["ambient"] == 0)
+    assert np.all(out["masks"] == 0)
+    # an empty image launches nothing and succeeds
+    from paper_2301_11376_amd import Camera
+    e = torch.zeros((0, 0), dtype=torch.float32, device="cuda")
+    e3 = torch.zeros((0, 0, 3), dtype=torch.float32, device="cuda")
+    ctx.compute(e, e3, e3, Camera(0, 0, 1.0, 1.0, 0.0, 0.0), bp)
+    torch.cuda.synchronize()
+
+
+def test_pitched_buffers(ctx):
+    """Row pitches larger than the row, on inputs and outputs."""
+    import torch
+    gb, cam, sc = tiny()
+    log("pitched buffers")
+    H, W = gb["depth"].shape
+    bc, oc = PY.cams(cam)
+    kw = dict(slices=2, steps=6, radius=1.2, noise=O.NOISE_HASH, seed=8, ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    bp, op = PY.params(**kw)
+    pad = 13
+    d = torch.zeros((H, W + pad), device="cuda")[:, :W]
+    d.copy_(torch.from_numpy(gb["depth"]))
+    n = torch.zeros((H, W + pad, 3), device="cuda")[:, :W]
+    n.copy_(torch.from_numpy(gb["normal"]))
+    r = torch.zeros((H, W + pad, 3), device="cuda")[:, :W]
+    r.copy_(torch.from_numpy(gb["radiance"]))
+    out = {"ao": torch.zeros((H, W + 7), device="cuda")[:, :W],
+           "gi": torch.zeros((H, W + 5, 3), device="cuda")[:, :W],
+           "ambient": torch.zeros((H, W + 3, 3), device="cuda")[:, :W],
+           "masks": torch.zeros((H, W + 2, 2), dtype=torch.int32, device="cuda")[:, :W]}
+    ctx.compute(d, n, r, bc, bp, out=out)
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in out.items()}
+    gpu["masks"] = gpu["masks"].view(np.uint32)
+    ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, return_masks=True)
+    PY.compare(gpu, ref, gb, oc, op)
+
+
+def test_deterministic(ctx):
+    gb, cam, sc = tiny()
+    log("determinism")
+    bc, _ = PY.cams(cam)
+    bp, _ = PY.params(slices=4, steps=8, radius=1.5, noise=O.NOISE_HASH, seed=1)
+    a = PY.gpu_run(ctx, gb, bc, bp)
+    b = PY.gpu_run(ctx, gb, bc, bp)
+    for k in a:
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+
+
+def test_parity_c2_1080p_sampled(ctx):
+    """Full 1920x1080 frame as the benchmark runs it; the oracle checks a seeded sample."""
+    gb, cam, w, sc = workload("c2_1080p")
+    log("parity c2 1080p (sampled)")
+    H, W = gb["depth"].shape
+    pix = PY.sample_pixels(H, W, 3000, 2)
+    rep = {}
+    run_case(ctx, gb, cam, report=rep, pixels=pix, slices=4, steps=16, radius=3.0, thickness=0.5,
+             noise=O.NOISE_R2, seed=2, ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    log(f"  {rep}")
+
+
+def test_parity_c3_4k_fp16_sampled(ctx):
+    """3840x2160, FP16 normals and radiance: against the oracle on the same FP16 values
+    (1e-3), and against the oracle on the FP32 originals (2e-2)."""
+    gb, cam, w, sc = workload("c3_4k_fp16")
+    log("parity c3 4k fp16 (sampled)")
+    H, W = gb["depth"].shape
+    pix = PY.sample_pixels(H, W, 800, 3)
+    kw = dict(slices=8, steps=32, radius=8.0, thickness=w["thickness"], noise=O.NOISE_R2, seed=3,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    rep = {}
+    _, gpu = run_case(ctx, gb, cam, report=rep, pixels=pix, **kw)
+    log(f"  vs FP16 inputs: {rep}")
+    scene = make_scene(3, 64, 32)
+    gb32 = render_gbuffer(scene, cam)
+    _, oc = PY.cams(cam)
+    _, op = PY.params(**kw)
+    ref32 = O.compute(gb32["depth"], gb32["normal"], gb32["radiance"], oc, op, pixels=pix)
+    ys, xs = pix
+    errs = {k: np.abs(gpu[k][ys, xs] - ref32[k]).reshape(len(ys), -1).max(axis=1) for k in ("ao", "gi", "ambient")}
+    stats = {k: (float(np.percentile(v, 99.9)), float(v.max()), float(v.mean())) for k, v in errs.items()}
+    log(f"  vs FP32 originals (p99.9, max, mean): {stats}")
+    for k, (p999, mx, _) in stats.items():
+        assert p999 <= 2e-2 and mx <= 2e-2, (k, stats)
