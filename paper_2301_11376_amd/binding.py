@@ -12,7 +12,8 @@ import os
 from dataclasses import dataclass, field
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libssvb.so")
+# SSVB_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SSVB_LIBRARY") or os.path.join(PKG, "libssvb.so")
 
 SSVB_OK = 0
 STATUS = {0: "SSVB_OK", 1: "SSVB_ERR_INVALID_ARG", 2: "SSVB_ERR_UNSUPPORTED", 3: "SSVB_ERR_OUT_OF_MEMORY",

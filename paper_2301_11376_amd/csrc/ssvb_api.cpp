@@ -22,6 +22,9 @@ struct ssvb_ctx {
     int device = 0;
     int2* d_lut = nullptr;
     int2 h_lut[kLutSize];
+    // scratch: fix-up list of the plain path, grown on demand (count + one entry per pixel)
+    uint32_t* d_fix = nullptr;
+    int64_t fix_cap = 0;
 };
 
 namespace {
@@ -65,6 +68,9 @@ ssvb_status check_image(const ssvb_image* im, const char* name, int32_t W, int32
     if (im->pitch_bytes != 0 && (im->pitch_bytes < row || im->pitch_bytes % es))
         return fail(SSVB_ERR_INVALID_ARG, "%s: pitch %lld bytes (row needs %lld, multiple of %lld)", name,
                     (long long)im->pitch_bytes, (long long)row, (long long)es);
+    const int64_t pitch = im->pitch_bytes ? im->pitch_bytes : row;
+    if (is_depth && pitch * (H - 1) + row > ((int64_t)1 << 32))
+        return fail(SSVB_ERR_INVALID_ARG, "%s: the image must span less than 4 GiB", name);
     return SSVB_OK;
 }
 
@@ -266,6 +272,7 @@ ssvb_status ssvb_destroy(ssvb_ctx* ctx) {
     hipGetDevice(&prev);
     hipSetDevice(ctx->device);
     if (ctx->d_lut) hipFree(ctx->d_lut);
+    if (ctx->d_fix) hipFree(ctx->d_fix);
     hipSetDevice(prev);
     delete ctx;
     return SSVB_OK;
@@ -304,8 +311,22 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     int prev = 0;
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
-    hipError_t e = launch_plain(A, (hipStream_t)hip_stream);
+    hipError_t e = hipSuccess;
+    const int64_t need = 1 + (int64_t)camera->width * camera->height;
+    if (need > ctx->fix_cap) {
+        // hipFree waits for the device, so an older, smaller list is never freed under a kernel
+        if (ctx->d_fix) hipFree(ctx->d_fix);
+        ctx->d_fix = nullptr;
+        ctx->fix_cap = 0;
+        e = hipMalloc((void**)&ctx->d_fix, need * sizeof(uint32_t));
+        if (e == hipSuccess) ctx->fix_cap = need;
+    }
+    if (e == hipSuccess) {
+        A.fix = ctx->d_fix;
+        e = launch_plain(A, (hipStream_t)hip_stream);
+    }
     if (prev != ctx->device) hipSetDevice(prev);
+    if (e == hipErrorOutOfMemory) return fail(SSVB_ERR_OUT_OF_MEMORY, "fix-up list of %lld entries", (long long)need);
     if (e != hipSuccess) return hip_fail(e, "gather launch");
     return SSVB_OK;
 }

@@ -52,6 +52,8 @@ struct FrameArgs {
     float amb_sb[32];       // sin of the same
     // slice-direction table (device), (Dx, Dy) pairs
     const int2* lut;
+    // fix-up list (device): [0] = count, then y * W + x of each flagged pixel
+    uint32_t* fix;
 };
 
 }  // namespace ssvb

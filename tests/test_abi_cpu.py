@@ -143,3 +143,10 @@ def test_create_without_gpu_fails_cleanly(B):
     h = ctypes.c_void_p()
     assert B.lib().ssvb_create(0, ctypes.byref(h)) != 0
     assert not h.value
+
+
+def test_validate_depth_span_limit(B):
+    # the depth image is addressed with 32-bit byte offsets
+    assert status(B, frame(B, W=16384, H=16384, d=setter("pitch_bytes", 65536))) == 0
+    assert status(B, frame(B, W=16384, H=16384, d=setter("pitch_bytes", 4 * 65536))) == 0
+    assert status(B, frame(B, W=16384, H=16384, d=setter("pitch_bytes", 4 * 65536 + 64))) == 1
