@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -195,6 +196,23 @@ void fill_frame(FrameArgs& A, const ssvb_ctx* ctx, const ssvb_image* depth, cons
         A.amb_sb[k] = (float)sin(beta);
     }
     A.lut = ctx ? ctx->d_lut : nullptr;
+    // launch shape (tuned defaults; SSVB_TILE=WxH, SSVB_STRIP=n, SSVB_XCD=0|1 override)
+    A.tile_w = 32;
+    A.tile_h = 8;
+    A.strip = 4;
+    A.xcd_remap = 1;
+    if (const char* e = getenv("SSVB_TILE")) {
+        int tw = 0, th = 0;
+        if (sscanf(e, "%dx%d", &tw, &th) == 2 && tw > 0 && th > 0 && tw * th <= 256 && (tw * th) % 64 == 0) {
+            A.tile_w = tw;
+            A.tile_h = th;
+        }
+    }
+    if (const char* e = getenv("SSVB_STRIP")) A.strip = atoi(e) > 0 ? atoi(e) : A.strip;
+    if (const char* e = getenv("SSVB_XCD")) A.xcd_remap = atoi(e) != 0;
+    A.tiles_x = (W + A.tile_w - 1) / A.tile_w;
+    A.tiles_y = (H + A.tile_h - 1) / A.tile_h;
+    A.strip = A.strip < A.tiles_x ? A.strip : (A.tiles_x > 0 ? A.tiles_x : 1);
 }
 
 }  // namespace

@@ -54,6 +54,35 @@ struct FrameArgs {
     const int2* lut;
     // fix-up list (device): [0] = count, then y * W + x of each flagged pixel
     uint32_t* fix;
+    // launch shape: tile_w x tile_h pixels per workgroup; tiles are walked in vertical
+    // strips of `strip` tiles, and with xcd_remap each XCD takes a contiguous run of that
+    // walk (workgroup i runs on XCD i mod kXcds)
+    int32_t tile_w, tile_h, tiles_x, tiles_y, strip, xcd_remap;
 };
+
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Workgroup index -> tile (tx, ty); false for the padding workgroups past the end.
+__device__ __forceinline__ bool tile_of(const FrameArgs& A, uint32_t bid, int& tx, int& ty) {
+    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+    uint32_t ord = bid;
+    if (A.xcd_remap) {
+        const uint32_t per = (nt + kXcds - 1) / kXcds;
+        ord = (bid % kXcds) * per + bid / kXcds;
+    }
+    if (ord >= nt) return false;
+    const uint32_t S = (uint32_t)A.strip, TY = (uint32_t)A.tiles_y;
+    const uint32_t full = (uint32_t)A.tiles_x / S;
+    if (ord < full * S * TY) {
+        const uint32_t st = ord / (S * TY), r = ord % (S * TY);
+        ty = (int)(r / S);
+        tx = (int)(st * S + r % S);
+    } else {
+        const uint32_t wl = (uint32_t)A.tiles_x - full * S, r = ord - full * S * TY;
+        ty = (int)(r / wl);
+        tx = (int)(full * S + r % wl);
+    }
+    return true;
+}
 
 }  // namespace ssvb

@@ -477,8 +477,10 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, int x, int y, i
 
 template <int CRIT, bool TINF, int FMT>
 __global__ __launch_bounds__(256) SSVB_OCCUPANCY void gather_plain(FrameArgs A) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    int tx, ty;
+    if (!tile_of(A, blockIdx.x, tx, ty)) return;
+    const int x = tx * A.tile_w + (int)(threadIdx.x % (unsigned)A.tile_w);
+    const int y = ty * A.tile_h + (int)(threadIdx.x / (unsigned)A.tile_w);
     if (x >= A.W || y >= A.H) return;
     gather_pixel<CRIT, MODE_COMPUTE, false, TINF, FMT>(A, x, y, nullptr, nullptr);
 }
@@ -522,9 +524,10 @@ static dim3 plain_grid(const FrameArgs& A, dim3 block) {
 
 template <int CRIT, bool TINF, int FMT>
 static void launch_pair(const FrameArgs& A, hipStream_t stream) {
-    const dim3 block(16, 16);
+    const uint32_t nt = (uint32_t)A.tiles_x * A.tiles_y;
+    const uint32_t nwg = A.xcd_remap ? kXcds * ((nt + kXcds - 1) / kXcds) : nt;
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, A.fix);
-    hipLaunchKernelGGL((gather_plain<CRIT, TINF, FMT>), plain_grid(A, block), block, 0, stream, A);
+    hipLaunchKernelGGL((gather_plain<CRIT, TINF, FMT>), dim3(nwg), dim3(A.tile_w * A.tile_h), 0, stream, A);
     const int64_t px = (int64_t)A.W * A.H;
     const int fix_blocks = (int)std::min<int64_t>(std::max<int64_t>((px / 64 + 15) / 16, 64), 4096);
     hipLaunchKernelGGL((gather_fixup<CRIT, TINF, FMT>), dim3(fix_blocks), dim3(64), 0, stream, A);
