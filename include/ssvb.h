@@ -66,8 +66,8 @@ typedef enum { SSVB_NOISE_HASH = 0, SSVB_NOISE_R2 = 1, SSVB_NOISE_FIXED = 2 } ss
 /* One image.  ptr: device pointer aligned to its element size.  pitch_bytes: bytes
  * between rows, 0 = dense (width * channels * element size).  dtype: ssvb_dtype.
  * channels: 1 for depth (F32 only), 3 or 4 for normals and radiance (the fourth
- * channel is ignored).  The depth image (pitch * (height - 1) + row) must span less
- * than 4 GiB. */
+ * channel is ignored).  Every image (pitch * (height - 1) + row bytes) must span at
+ * most 4 GiB. */
 typedef struct {
     const void* ptr;
     int64_t pitch_bytes;

@@ -21,11 +21,9 @@ using namespace ssvb;
 
 struct ssvb_ctx {
     int device = 0;
-    int2* d_lut = nullptr;
+    int2* d_lut = nullptr;     // slice directions
+    double2* d_half = nullptr; // cos, sin of h pi / 64, h = -64..64
     int2 h_lut[kLutSize];
-    // scratch: fix-up list of the plain path, grown on demand (count + one entry per pixel)
-    uint32_t* d_fix = nullptr;
-    int64_t fix_cap = 0;
 };
 
 namespace {
@@ -70,8 +68,8 @@ ssvb_status check_image(const ssvb_image* im, const char* name, int32_t W, int32
         return fail(SSVB_ERR_INVALID_ARG, "%s: pitch %lld bytes (row needs %lld, multiple of %lld)", name,
                     (long long)im->pitch_bytes, (long long)row, (long long)es);
     const int64_t pitch = im->pitch_bytes ? im->pitch_bytes : row;
-    if (is_depth && pitch * (H - 1) + row > ((int64_t)1 << 32))
-        return fail(SSVB_ERR_INVALID_ARG, "%s: the image must span less than 4 GiB", name);
+    if (pitch * (H - 1) + row > ((int64_t)1 << 32))
+        return fail(SSVB_ERR_INVALID_ARG, "%s: the image must span at most 4 GiB", name);
     return SSVB_OK;
 }
 
@@ -196,6 +194,7 @@ void fill_frame(FrameArgs& A, const ssvb_ctx* ctx, const ssvb_image* depth, cons
         A.amb_sb[k] = (float)sin(beta);
     }
     A.lut = ctx ? ctx->d_lut : nullptr;
+    A.half_sector = ctx ? ctx->d_half : nullptr;
     // launch shape (tuned defaults; SSVB_TILE=WxH, SSVB_STRIP=n, SSVB_XCD=0|1 override)
     A.tile_w = 32;
     A.tile_h = 8;
@@ -272,11 +271,16 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
         delete ctx;
         return hip_fail(e, "hipSetDevice");
     }
+    double2 half[129];
+    for (int h = -64; h <= 64; ++h) half[h + 64] = make_double2(cos(M_PI * h / 64.0), sin(M_PI * h / 64.0));
     e = hipMalloc((void**)&ctx->d_lut, sizeof ctx->h_lut);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_lut, ctx->h_lut, sizeof ctx->h_lut, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_half, sizeof half);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_half, half, sizeof half, hipMemcpyHostToDevice);
     hipSetDevice(prev);
     if (e != hipSuccess) {
         if (ctx->d_lut) hipFree(ctx->d_lut);
+        if (ctx->d_half) hipFree(ctx->d_half);
         delete ctx;
         return e == hipErrorOutOfMemory ? fail(SSVB_ERR_OUT_OF_MEMORY, "direction table") : hip_fail(e, "direction table");
     }
@@ -290,7 +294,7 @@ ssvb_status ssvb_destroy(ssvb_ctx* ctx) {
     hipGetDevice(&prev);
     hipSetDevice(ctx->device);
     if (ctx->d_lut) hipFree(ctx->d_lut);
-    if (ctx->d_fix) hipFree(ctx->d_fix);
+    if (ctx->d_half) hipFree(ctx->d_half);
     hipSetDevice(prev);
     delete ctx;
     return SSVB_OK;
@@ -329,22 +333,8 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     int prev = 0;
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
-    hipError_t e = hipSuccess;
-    const int64_t need = 1 + (int64_t)camera->width * camera->height;
-    if (need > ctx->fix_cap) {
-        // hipFree waits for the device, so an older, smaller list is never freed under a kernel
-        if (ctx->d_fix) hipFree(ctx->d_fix);
-        ctx->d_fix = nullptr;
-        ctx->fix_cap = 0;
-        e = hipMalloc((void**)&ctx->d_fix, need * sizeof(uint32_t));
-        if (e == hipSuccess) ctx->fix_cap = need;
-    }
-    if (e == hipSuccess) {
-        A.fix = ctx->d_fix;
-        e = launch_plain(A, (hipStream_t)hip_stream);
-    }
+    const hipError_t e = launch_plain(A, (hipStream_t)hip_stream);
     if (prev != ctx->device) hipSetDevice(prev);
-    if (e == hipErrorOutOfMemory) return fail(SSVB_ERR_OUT_OF_MEMORY, "fix-up list of %lld entries", (long long)need);
     if (e != hipSuccess) return hip_fail(e, "gather launch");
     return SSVB_OK;
 }

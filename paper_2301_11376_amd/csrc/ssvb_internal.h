@@ -52,8 +52,8 @@ struct FrameArgs {
     float amb_sb[32];       // sin of the same
     // slice-direction table (device), (Dx, Dy) pairs
     const int2* lut;
-    // fix-up list (device): [0] = count, then y * W + x of each flagged pixel
-    uint32_t* fix;
+    // cos and sin of h pi / 64 for h = -64..64 (device, FP64), index h + 64
+    const double2* half_sector;
     // launch shape: tile_w x tile_h pixels per workgroup; tiles are walked in vertical
     // strips of `strip` tiles, and with xcd_remap each XCD takes a contiguous run of that
     // walk (workgroup i runs on XCD i mod kXcds)

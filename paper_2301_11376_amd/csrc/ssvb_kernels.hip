@@ -1,18 +1,21 @@
 // gfx950 kernels of the visibility-bitmask gather.
 //
-// One thread owns one pixel and walks its N_d slices, both sides of each slice and N_s
-// steps per side (Algorithm 1).  The hot loop per step: integer lattice -> depth gather
-// -> slice-plane coordinates (c, h) of the sample -> front and back angles -> sector
-// range -> newly covered sectors -> (rarely) normal + radiance gather for the indirect
-// term -> OR into the slice mask.
+// One thread owns one pixel and walks its N_d slices; each step advances both sides of
+// the slice (Algorithm 1).  Per step and side: integer lattice -> depth gather ->
+// slice-plane coordinates (c, h) of the sample -> front and back angles -> sector range
+// -> newly covered sectors -> (when there are any) normal + radiance gather for the
+// indirect term -> OR into the slice mask.
 //
-// Numerics.  The slice frame (view vector, in-slice tangent, projected-normal angle) is
-// built once per slice in FP64 and rounded to FP32; the per-sample angle-to-sector step
-// runs in FP32.  A sector decision depends on which side of a boundary an endpoint
-// falls.  When an FP32 endpoint lies within kGuard sectors of a boundary, that sample's
-// decision is taken again in FP64 from the same FP32 inputs, so the kernel's masks are
-// those of the FP64 definition unless an endpoint sits within FP64 rounding of a
-// boundary.
+// Numerics.  The slice frame (view vector, in-slice tangent, projected normal) is built
+// once per slice in FP64 and rounded to FP32; the per-sample angle-to-sector step runs in
+// FP32.  A sector decision only depends on which side of a boundary direction an
+// endpoint lies.  When an FP32 endpoint is within kGuard sectors of a boundary, the
+// kernel decides it exactly: in FP64, from the same FP32 inputs, as the sign of the cross
+// product between the sample direction and the boundary direction (boundary angles are
+// multiples of pi/64 from the projected normal, whose cosine and sine come from a table
+// and from the normal itself, so no transcendental function is evaluated).  The masks
+// are therefore those of the FP64 definition unless an endpoint sits within FP64
+// rounding of a boundary.
 #include <math.h>
 
 #include <algorithm>
@@ -22,16 +25,12 @@
 namespace ssvb {
 
 constexpr float kInvPi32 = 10.185916357881302f;  // 32 / pi
-constexpr double kInvPi32d = 10.185916357881301489;
-constexpr double kPi = 3.141592653589793238;
 constexpr float kGuard = 1.0f / 32768.0f;       // sectors; ~3e-6 rad
 #ifndef SSVB_BATCH
-#define SSVB_BATCH 4
-#endif
-#ifndef SSVB_WAVES
-#define SSVB_WAVES 0
+#define SSVB_BATCH 1
 #endif
 constexpr int kBatch = SSVB_BATCH;              // steps whose depth loads are issued together
+constexpr int kBlock = 256;                     // threads per workgroup
 
 // ---------------------------------------------------------------------------------------
 // counter-based noise: PCG-RXS-M-XS hash (Jarzynski and Olano, JCGT 2020) and the R2
@@ -60,21 +59,24 @@ __device__ __forceinline__ uint32_t jitter8(const FrameArgs& A, int x, int y, in
 }
 
 // ---------------------------------------------------------------------------------------
-// G-buffer access
+// G-buffer access (every image spans less than 4 GiB: 32-bit byte offsets)
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ float depth_at(const FrameArgs& A, int x, int y) {
-    const float* row = (const float*)((const char*)A.depth + (int64_t)y * A.depth_pitch);
-    return row[x];
+__device__ __forceinline__ uint32_t depth_off(const FrameArgs& A, int X, int Y) {
+    return (uint32_t)Y * (uint32_t)A.depth_pitch + (uint32_t)X * 4u;
+}
+
+__device__ __forceinline__ float depth_load(const FrameArgs& A, uint32_t off) {
+    return *(const float*)((const char*)A.depth + off);
 }
 
 template <bool F16>
 __device__ __forceinline__ float3 load3(const char* base, int64_t pitch, int ch, int x, int y) {
-    const char* row = base + (int64_t)y * pitch;
+    const uint32_t off = (uint32_t)y * (uint32_t)pitch + (uint32_t)(x * ch) * (F16 ? 2u : 4u);
     if (F16) {
-        const _Float16* p = (const _Float16*)row + (int64_t)x * ch;
+        const _Float16* p = (const _Float16*)(base + off);
         return make_float3((float)p[0], (float)p[1], (float)p[2]);
     }
-    const float* p = (const float*)row + (int64_t)x * ch;
+    const float* p = (const float*)(base + off);
     return make_float3(p[0], p[1], p[2]);
 }
 
@@ -86,90 +88,125 @@ __device__ __forceinline__ uint32_t low_bits(int k) { return k >= 32 ? 0xFFFFFFF
 // bits [a, b) of a 32-bit mask; empty when b <= a
 __device__ __forceinline__ uint32_t range_bits(int a, int b) { return low_bits(b) & ~low_bits(a); }
 
-// ---------------------------------------------------------------------------------------
-// FP64 slice frame
-// ---------------------------------------------------------------------------------------
-struct Frame64 {
-    double R, vx, vy, vz;      // |r_p| and v = -r_p / |r_p|
-    double ex, ey, ez;         // unit in-slice tangent toward the slice direction
-    double av, ae;             // D3 . v and D3 . e (D3: view direction of one LUT unit)
-    double nv, ne, gamma;      // projected normal in (v, e) and its angle from v
-};
-
-__device__ __forceinline__ void pixel_ray64(const FrameArgs& A, int x, int y, Frame64& F) {
-    const double rpx = ((double)x + 0.5 - (double)A.cx) / (double)A.fx;
-    const double rpy = -((double)y + 0.5 - (double)A.cy) / (double)A.fy;
-    F.R = sqrt(rpx * rpx + rpy * rpy + 1.0);
-    F.vx = -rpx / F.R;
-    F.vy = -rpy / F.R;
-    F.vz = 1.0 / F.R;
-}
-
-__device__ __forceinline__ void slice_frame64(const FrameArgs& A, int Dx, int Dy, float3 n, Frame64& F) {
-    const double d3x = (double)Dx / (4096.0 * (double)A.fx);
-    const double d3y = -(double)Dy / (4096.0 * (double)A.fy);
-    F.av = d3x * F.vx + d3y * F.vy;
-    double ex = d3x - F.av * F.vx, ey = d3y - F.av * F.vy, ez = -F.av * F.vz;
-    F.ae = sqrt(ex * ex + ey * ey + ez * ez);
-    F.ex = ex / F.ae;
-    F.ey = ey / F.ae;
-    F.ez = ez / F.ae;
-    F.nv = (double)n.x * F.vx + (double)n.y * F.vy + (double)n.z * F.vz;
-    F.ne = (double)n.x * F.ex + (double)n.y * F.ey + (double)n.z * F.ez;
-    F.gamma = (F.nv * F.nv + F.ne * F.ne < 1e-12) ? 0.0 : atan2(F.ne, F.nv);
-}
-
-// Sector range [a, b) of one sample decided in FP64 (used near a boundary).
-template <int CRIT>
-__device__ __noinline__ int2 decide64(const FrameArgs& A, int x, int y, float zp, float zs, int so,
-                                      int Dx, int Dy, float3 n) {
-    Frame64 F;
-    pixel_ray64(A, x, y, F);
-    slice_frame64(A, Dx, Dy, n, F);
-    const double lam = (double)so / 16.0;
-    const double zpd = zp, zsd = zs;
-    const double tp = (double)A.t0 + (double)A.tk * zpd;
-    const double c = -(zsd - zpd) * F.R + zsd * lam * F.av;
-    const double h = fabs(zsd * lam * F.ae);
-    const double sgn = so > 0 ? 1.0 : -1.0;
-    double tf = sgn * atan2(h, c) - F.gamma;
-    double tb = sgn * atan2(h, c - tp) - F.gamma;
-    tf = fmin(fmax(tf, -0.5 * kPi), 0.5 * kPi);
-    tb = fmin(fmax(tb, -0.5 * kPi), 0.5 * kPi);
-    const double ulo = (fmin(tf, tb) + 0.5 * kPi) / kPi;
-    const double uhi = (fmax(tf, tb) + 0.5 * kPi) / kPi;
-    if (CRIT == SSVB_HIT_ROUND) {
-        return make_int2((int)floor(32.0 * ulo + 0.5), (int)floor(32.0 * uhi + 0.5));
-    } else {
-        const int a = (int)floor(32.0 * ulo);
-        const int w = (int)ceil(32.0 * (uhi - ulo));
-        return make_int2(a, min(a + w, 32));
-    }
-}
-
 __device__ __forceinline__ bool near_integer(float v) { return fabsf(v - rintf(v)) < kGuard; }
 
-// atan2(y, x) for y > 0 and any x (including -inf), in (0, pi].  Octant reduction to
-// r = min / max in [0, 1] and an odd minimax polynomial of degree 17 for atan(r) on
-// [0, 1] (fitted offline; |error| < 1e-7 rad in FP32 evaluation).
+// atan2(y, x) for y >= 0 and any x (including -inf), in [0, pi].  Octant reduction to
+// r = min / max in [0, 1] and an odd minimax polynomial of degree 13 for atan(r) on
+// [0, 1] (fitted offline; |error| < 3.3e-7 rad in FP32 evaluation).
 __device__ __forceinline__ float atan2_pos(float y, float x) {
     const float ax = fabsf(x);
     const float mx = fmaxf(ax, y), mn = fminf(ax, y);
     const float r = mn * __builtin_amdgcn_rcpf(mx);
     const float r2 = r * r;
-    float p = 0.0024567244108766317f;
-    p = fmaf(p, r2, -0.014401358552277088f);
-    p = fmaf(p, r2, 0.039781227707862854f);
-    p = fmaf(p, r2, -0.07234857976436615f);
-    p = fmaf(p, r2, 0.10498946905136108f);
-    p = fmaf(p, r2, -0.14161229133605957f);
-    p = fmaf(p, r2, 0.19985906779766083f);
-    p = fmaf(p, r2, -0.33332598209381104f);
-    p = fmaf(p, r2, 0.9999998807907104f);
+    float p = 0.006811789236962795f;
+    p = fmaf(p, r2, -0.0336042121052742f);
+    p = fmaf(p, r2, 0.07962366938591003f);
+    p = fmaf(p, r2, -0.1323334276676178f);
+    p = fmaf(p, r2, 0.19807815551757812f);
+    p = fmaf(p, r2, -0.3331736922264099f);
+    p = fmaf(p, r2, 0.9999961256980896f);
     float a = p * r;
     if (y > ax) a = 1.57079632679489662f - a;
     if (x < 0.0f) a = 3.14159265358979324f - a;
     return a;
+}
+
+// ---------------------------------------------------------------------------------------
+// slice frame
+// ---------------------------------------------------------------------------------------
+// Per-slice constants of the hot loop (FP32, rounded from FP64).
+struct SliceF {
+    float ex, ey, ez;   // unit tangent of the slice toward +d
+    float nv, ne;       // centre normal in (v, e)
+    float K;            // sector coordinate of the direction v: 16.5 - gamma * 32 / pi
+    float avq, aeq;     // (D3 . v) / 16 and (D3 . e) / 16: per 1/16-px offset unit
+    float cg, sg;       // unit projected normal (cos gamma, sin gamma)
+};
+
+// FP64 constants the exact decision needs, one slot per thread in LDS (struct of arrays)
+struct ExactLds {
+    double R[kBlock], tp[kBlock], av[kBlock], ae[kBlock], cg[kBlock], sg[kBlock];
+};
+
+__device__ __forceinline__ SliceF slice_constants(const FrameArgs& A, double rpx, double rpy, int2 D, float3 n,
+                                                  ExactLds& L, int t) {
+    const double R = sqrt(rpx * rpx + rpy * rpy + 1.0);
+    const double vx = -rpx / R, vy = -rpy / R, vz = 1.0 / R;
+    const double d3x = (double)D.x / (4096.0 * (double)A.fx);
+    const double d3y = -(double)D.y / (4096.0 * (double)A.fy);
+    const double av = d3x * vx + d3y * vy;
+    const double ex = d3x - av * vx, ey = d3y - av * vy, ez = -av * vz;
+    const double ae = sqrt(ex * ex + ey * ey + ez * ez);
+    const double ie = 1.0 / ae;
+    SliceF S;
+    S.ex = (float)(ex * ie);
+    S.ey = (float)(ey * ie);
+    S.ez = (float)(ez * ie);
+    const double nv = (double)n.x * vx + (double)n.y * vy + (double)n.z * vz;
+    const double ne = ((double)n.x * ex + (double)n.y * ey + (double)n.z * ez) * ie;
+    S.nv = (float)nv;
+    S.ne = (float)ne;
+    const double g2 = nv * nv + ne * ne;
+    float gamma = 0.0f;
+    double cg = 1.0, sg = 0.0;
+    if (g2 >= 1e-12) {
+        const float gm = atan2_pos(fabsf(S.ne), S.nv);
+        gamma = S.ne < 0.0f ? -gm : gm;
+        const double ig = 1.0 / sqrt(g2);
+        cg = nv * ig;
+        sg = ne * ig;
+    }
+    S.cg = (float)cg;
+    S.sg = (float)sg;
+    S.K = fmaf(-gamma, kInvPi32, 16.5f);
+    S.avq = (float)(av * 0.0625);
+    S.aeq = (float)(ae * 0.0625);
+    L.av[t] = av;
+    L.ae[t] = ae;
+    L.cg[t] = cg;
+    L.sg[t] = sg;
+    return S;
+}
+
+// ---------------------------------------------------------------------------------------
+// exact decisions near a sector boundary
+// ---------------------------------------------------------------------------------------
+// Is the direction (sv, se) (in the slice, from v toward e) at or counter-clockwise of
+// the direction at angle h pi / 64 from the projected normal (cg, sg)?
+// Products are rounded separately (no contraction), so a cross product of two identical
+// directions is exactly zero.
+__device__ __forceinline__ bool at_or_above(const FrameArgs& A, int h, double cg, double sg, double sv, double se) {
+#pragma clang fp contract(off)
+    const double2 cs = A.half_sector[h + 64];  // cos, sin of h pi / 64
+    const double dv = cs.x * cg - cs.y * sg, de = cs.y * cg + cs.x * sg;
+    return dv * se - de * sv >= 0.0;
+}
+
+// Exact floor of the FP32 sector coordinate `y` (ROUND: y = 32 u + 1/2; PSEUDOCODE: y =
+// 32 u) of an endpoint with direction (sv, se), given that y is near the integer m.  The
+// angle is clamped to the hemisphere first, so the floor never drops below 0.
+template <int CRIT>
+__device__ __forceinline__ int exact_floor(const FrameArgs& A, float y, double cg, double sg, double sv, double se) {
+    const int m = (int)rintf(y);
+    // boundary y = m sits at theta = (m - 16.5) pi / 32 (ROUND) or (m - 16) pi / 32
+    const int h = CRIT == SSVB_HIT_ROUND ? 2 * m - 33 : 2 * m - 32;
+    return at_or_above(A, h, cg, sg, sv, se) ? m : max(m - 1, 0);
+}
+
+// Direction of an endpoint given its FP32 sector coordinate: the sample's own direction,
+// or the hemisphere edge when the coordinate was clamped there.
+__device__ __forceinline__ void endpoint_dir(float y, float lo_clamp, float hi_clamp, double cg, double sg, double sv,
+                                             double se, double& dv, double& de) {
+    if (y <= lo_clamp) {  // theta = -pi/2
+        dv = sg;
+        de = -cg;
+    } else if (y >= hi_clamp) {  // theta = +pi/2
+        dv = -sg;
+        de = cg;
+    } else {
+        dv = sv;
+        de = se;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -189,64 +226,12 @@ __device__ __forceinline__ void store_background(const FrameArgs& A, int x, int 
     }
 }
 
-// Per-slice constants of the hot loop (FP32, derived from the FP64 frame).
-struct SliceF {
-    float ex, ey, ez;   // unit tangent of the slice toward +d
-    float nv, ne;       // centre normal in (v, e)
-    float K;            // sector coordinate of the direction v: 16.5 - gamma * 32 / pi
-    float avq, aeq;     // (D3 . v) / 16 and (D3 . e) / 16: per 1/16-px offset unit
-    float cg, sg;       // unit projected normal (cos gamma, sin gamma)
-};
-
-__device__ __forceinline__ SliceF slice_constants(const FrameArgs& A, int x, int y, int2 D, float3 n) {
-    Frame64 F;
-    pixel_ray64(A, x, y, F);
-    const double d3x = (double)D.x / (4096.0 * (double)A.fx);
-    const double d3y = -(double)D.y / (4096.0 * (double)A.fy);
-    const double av = d3x * F.vx + d3y * F.vy;
-    const double ex = d3x - av * F.vx, ey = d3y - av * F.vy, ez = -av * F.vz;
-    const double ae = sqrt(ex * ex + ey * ey + ez * ez);
-    const double ie = 1.0 / ae;
-    SliceF S;
-    S.ex = (float)(ex * ie);
-    S.ey = (float)(ey * ie);
-    S.ez = (float)(ez * ie);
-    const double nv = (double)n.x * F.vx + (double)n.y * F.vy + (double)n.z * F.vz;
-    const double ne = ((double)n.x * ex + (double)n.y * ey + (double)n.z * ez) * ie;
-    S.nv = (float)nv;
-    S.ne = (float)ne;
-    const double g2 = nv * nv + ne * ne;
-    float gamma = 0.0f;
-    S.cg = 1.0f;
-    S.sg = 0.0f;
-    if (g2 >= 1e-12) {
-        const float gm = atan2_pos(fabsf(S.ne), S.nv);
-        gamma = S.ne < 0.0f ? -gm : gm;
-        const double ig = 1.0 / sqrt(g2);
-        S.cg = (float)(nv * ig);
-        S.sg = (float)(ne * ig);
-    }
-    S.K = fmaf(-gamma, kInvPi32, 16.5f);
-    S.avq = (float)(av * 0.0625);
-    S.aeq = (float)(ae * 0.0625);
-    return S;
-}
-
-// 32-bit byte offset of texel (X, Y) in the depth image (the image spans < 4 GiB)
-__device__ __forceinline__ uint32_t depth_off(const FrameArgs& A, int X, int Y) {
-    return (uint32_t)Y * (uint32_t)A.depth_pitch + (uint32_t)X * 4u;
-}
-
-__device__ __forceinline__ float depth_load(const FrameArgs& A, uint32_t off) {
-    return *(const float*)((const char*)A.depth + off);
-}
-
 // One sample of the march: sector range, newly covered sectors, indirect light.
-template <int CRIT, bool EXACT, bool TINF, int FMT>
-__device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S, int x, int y, float zp, float R,
-                                             float vx, float vy, float vz, float tp, float3 n, int2 D, int s,
-                                             int o, int X, int Y, bool ok, float zs, uint32_t& B, float& gir,
-                                             float& gig, float& gib, bool& flagged) {
+template <int CRIT, bool TINF, int FMT>
+__device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S, const ExactLds& L, int t, float zp,
+                                             float R, float vx, float vy, float vz, float tp, int s, int o, int X,
+                                             int Y, bool ok, float zs, uint32_t& B, float& gir, float& gig,
+                                             float& gib) {
     ok = ok && is_geometry(zs);
     const float of = (float)o;
     const float sk = s > 0 ? kInvPi32 : -kInvPi32;
@@ -258,45 +243,76 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
     const float ab = TINF ? 3.14159265358979324f : atan2_pos(h, c - tp);
     const float yf = fminf(fmaxf(fmaf(af, sk, S.K), 0.5f), 32.5f);
     const float yb = fminf(fmaxf(fmaf(ab, sk, S.K), 0.5f), 32.5f);
-    const float lo = fminf(yf, yb), hi = fmaxf(yf, yb);
     int a, b;
-    bool near;
     if (CRIT == SSVB_HIT_ROUND) {
-        a = (int)floorf(lo);
-        b = (int)floorf(hi);
-        near = near_integer(lo) | near_integer(hi);
-    } else {
-        a = (int)floorf(lo - 0.5f);
-        const float wf = hi - lo;
-        b = min(a + (int)ceilf(wf), 32);
-        near = near_integer(lo - 0.5f) | near_integer(wf);
-    }
-    near = near && ok;
-    if (near) {
-        if (EXACT) {
-            const int2 ab64 = decide64<CRIT>(A, x, y, zp, zs, s * o, D.x, D.y, n);
-            a = ab64.x;
-            b = ab64.y;
-        } else {
-            flagged = true;
+        int kf = (int)floorf(yf), kb = (int)floorf(yb);
+        if ((near_integer(yf) | near_integer(yb)) && ok) {
+            // FP64 decision of the endpoint(s) next to a boundary
+            const double zsd = zs, zpd = zp;
+            const double lam = (double)(s * o) * 0.0625;
+            const double cd = -(zsd - zpd) * L.R[t] + zsd * lam * L.av[t];
+            const double he = zsd * lam * L.ae[t];
+            const double cg = L.cg[t], sg = L.sg[t];
+            if (near_integer(yf)) kf = exact_floor<CRIT>(A, yf, cg, sg, cd, he);
+            if (near_integer(yb)) {
+                if (TINF || isinf(L.tp[t])) kb = exact_floor<CRIT>(A, yb, cg, sg, -1.0, 0.0);
+                else kb = exact_floor<CRIT>(A, yb, cg, sg, cd - L.tp[t], he);
+            }
         }
+        a = min(kf, kb);
+        b = max(kf, kb);
+    } else {
+        const float lo = fminf(yf, yb), hi = fmaxf(yf, yb);
+        int kf = (int)floorf(yf - 0.5f), kb = (int)floorf(yb - 0.5f);
+        const float wf = hi - lo;
+        int w = (int)ceilf(wf);
+        if ((near_integer(yf - 0.5f) | near_integer(yb - 0.5f) | near_integer(wf)) && ok) {
+            const double zsd = zs, zpd = zp;
+            const double lam = (double)(s * o) * 0.0625;
+            const double cd = -(zsd - zpd) * L.R[t] + zsd * lam * L.av[t];
+            const double he = zsd * lam * L.ae[t];
+            const double cg = L.cg[t], sg = L.sg[t];
+            const bool binf = TINF || isinf(L.tp[t]);
+            const double bv = binf ? -1.0 : cd - L.tp[t], be = binf ? 0.0 : he;
+            if (near_integer(yf - 0.5f)) kf = exact_floor<CRIT>(A, yf - 0.5f, cg, sg, cd, he);
+            if (near_integer(yb - 0.5f)) kb = exact_floor<CRIT>(A, yb - 0.5f, cg, sg, bv, be);
+            if (near_integer(wf) && !((yf <= 0.5f && yb <= 0.5f) || (yf >= 32.5f && yb >= 32.5f))) {
+#pragma clang fp contract(off)
+                // width = ceil of the angle between the two (clamped) endpoint directions;
+                // two endpoints clamped to the same edge have width 0 (ceilf(0) above)
+                double fv, fe, bv2, be2;
+                endpoint_dir(yf, 0.5f, 32.5f, cg, sg, cd, he, fv, fe);
+                endpoint_dir(yb, 0.5f, 32.5f, cg, sg, bv, be, bv2, be2);
+                const bool f_hi = yf >= yb;
+                const double lv = f_hi ? bv2 : fv, le = f_hi ? be2 : fe;
+                const double hv = f_hi ? fv : bv2, hev = f_hi ? fe : be2;
+                const int m = (int)rintf(wf);
+                const double2 cs = A.half_sector[2 * m + 64];  // rotate the low end by m pi / 32
+                const double rv = cs.x * lv - cs.y * le, re = cs.y * lv + cs.x * le;
+                w = (rv * hev - re * hv <= 0.0) ? m : m + 1;
+            }
+        }
+        a = min(kf, kb);
+        b = min(a + w, 32);
     }
     const uint32_t m = ok ? range_bits(a, b) : 0u;
     const uint32_t fresh = m & ~B;
     if (fresh) {
         // indirect light from the newly covered sectors (Algorithm 1; Section 3.3)
         const float3 nj = load3<(FMT & 1) != 0>(A.normal, A.normal_pitch, A.normal_ch, X, Y);
-        const float3 cj = load3<(FMT & 2) != 0>(A.radiance, A.radiance_pitch, A.radiance_ch, X, Y);
         const float hs = s > 0 ? h : -h;
         const float ndp = fmaf(S.nv, c, S.ne * hs);
         const float njv = nj.x * vx + nj.y * vy + nj.z * vz;
         const float nje = nj.x * S.ex + nj.y * S.ey + nj.z * S.ez;
         const float ndj = fmaf(njv, c, nje * hs);
-        const float w =
-            (float)__popc(fresh) * (1.0f / 32.0f) * fmaxf(ndp, 0.0f) * fmaxf(-ndj, 0.0f) / fmaf(c, c, h * h);
-        gir = fmaf(w, cj.x, gir);
-        gig = fmaf(w, cj.y, gig);
-        gib = fmaf(w, cj.z, gib);
+        const float w = (float)__popc(fresh) * (1.0f / 32.0f) * fmaxf(ndp, 0.0f) * fmaxf(-ndj, 0.0f) *
+                        __builtin_amdgcn_rcpf(fmaf(c, c, h * h));
+        if (w > 0.0f) {
+            const float3 cj = load3<(FMT & 2) != 0>(A.radiance, A.radiance_pitch, A.radiance_ch, X, Y);
+            gir = fmaf(w, cj.x, gir);
+            gig = fmaf(w, cj.y, gig);
+            gib = fmaf(w, cj.z, gib);
+        }
     }
     B |= m;
 }
@@ -304,16 +320,17 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
 // One pixel of the gather.
 //  CRIT   hit criterion
 //  MODE   compute, or dump the lattice / the FP32 endpoint arguments (test hooks)
-//  EXACT  false: FP32 decisions; a pixel with an endpoint within kGuard of a boundary
-//         is appended to the fix-up list.  true: such samples are decided in FP64.
 //  TINF   thickness is +inf: every back angle is pi, no second atan2
+//  FMT    bit 0: normals FP16, bit 1: radiance FP16
 // Both sides of a slice advance together, one step per iteration: the + side only
 // covers sectors at or above the direction v and the - side only sectors below it, so
-// the two never compete for a sector and the interleaving leaves every mask, and
-// every newly covered count, as a side-by-side march would produce it.
-template <int CRIT, int MODE, bool EXACT, bool TINF, int FMT>
-__device__ __forceinline__ void gather_pixel(const FrameArgs& A, int x, int y, int32_t* dbg_i, float* dbg_f) {
-    const float zp = depth_at(A, x, y);
+// the two never compete for a sector and the interleaving leaves every mask, and every
+// newly covered count, as a side-by-side march would produce it.
+template <int CRIT, int MODE, bool TINF, int FMT>
+__device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int32_t* dbg_i,
+                                             float* dbg_f) {
+    const int t = (int)threadIdx.x;
+    const float zp = *(const float*)((const char*)A.depth + depth_off(A, x, y));
     const bool geom = is_geometry(zp);
     if (MODE == MODE_COMPUTE && !geom) {
         store_background(A, x, y);
@@ -329,20 +346,23 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, int x, int y, i
     const int q = max((int)floorf(quot), A.q_min);
     const float tp = fmaf(A.tk, zp, A.t0);
 
+    // view ray of the pixel centre (FP64), its length and the unit vector v to the camera
+    const double rpx = ((double)x + 0.5 - (double)A.cx) / (double)A.fx;
+    const double rpy = -((double)y + 0.5 - (double)A.cy) / (double)A.fy;
     float R, vx, vy, vz;
     {
-        Frame64 F;
-        pixel_ray64(A, x, y, F);
-        R = (float)F.R;
-        vx = (float)F.vx;
-        vy = (float)F.vy;
-        vz = (float)F.vz;
+        const double Rd = sqrt(rpx * rpx + rpy * rpy + 1.0);
+        R = (float)Rd;
+        vx = (float)(-rpx / Rd);
+        vy = (float)(-rpy / Rd);
+        vz = (float)(1.0 / Rd);
+        L.R[t] = Rd;
+        L.tp[t] = (double)A.t0 + (double)A.tk * (double)zp;
     }
 
     float ao_acc = 0.0f;
     float gir = 0.0f, gig = 0.0f, gib = 0.0f;
     float amr = 0.0f, amg = 0.0f, amb = 0.0f;
-    bool flagged = false;
     const int x16 = (x << 16) + 32768, y16 = (y << 16) + 32768;
     const uint32_t own = depth_off(A, x, y);
 
@@ -362,7 +382,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, int x, int y, i
             }
             continue;
         }
-        const SliceF S = slice_constants(A, x, y, D, n);
+        const SliceF S = slice_constants(A, rpx, rpy, D, n, L, t);
         uint32_t B = 0u;
 
         // steps are taken kBatch at a time: the depth loads of the whole batch (both
@@ -409,8 +429,8 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, int x, int y, i
                         d[0] = CRIT == SSVB_HIT_ROUND ? lo : lo - 0.5f;
                         d[1] = CRIT == SSVB_HIT_ROUND ? hi : hi - lo;
                     } else {
-                        march_sample<CRIT, EXACT, TINF, FMT>(A, S, x, y, zp, R, vx, vy, vz, tp, n, D, s, o, X, Y, ok,
-                                                        zs[u][side], B, gir, gig, gib, flagged);
+                        march_sample<CRIT, TINF, FMT>(A, S, L, t, zp, R, vx, vy, vz, tp, s, o, X, Y, ok,
+                                                      zs[u][side], B, gir, gig, gib);
                     }
                 }
             }
@@ -463,83 +483,57 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, int x, int y, i
     m[0] = amr * inv_nd;
     m[1] = amg * inv_nd;
     m[2] = amb * inv_nd;
-    if (!EXACT && flagged) {
-        const uint32_t slot = atomicAdd(A.fix, 1u);
-        A.fix[1 + slot] = (uint32_t)y * (uint32_t)A.W + (uint32_t)x;
-    }
 }
 
-#if SSVB_WAVES > 0
-#define SSVB_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SSVB_WAVES, 8)))
-#else
-#define SSVB_OCCUPANCY
-#endif
-
 template <int CRIT, bool TINF, int FMT>
-__global__ __launch_bounds__(256) SSVB_OCCUPANCY void gather_plain(FrameArgs A) {
+__global__ __launch_bounds__(kBlock) void gather_plain(FrameArgs A) {
+    __shared__ ExactLds L;
     int tx, ty;
     if (!tile_of(A, blockIdx.x, tx, ty)) return;
     const int x = tx * A.tile_w + (int)(threadIdx.x % (unsigned)A.tile_w);
     const int y = ty * A.tile_h + (int)(threadIdx.x / (unsigned)A.tile_w);
     if (x >= A.W || y >= A.H) return;
-    gather_pixel<CRIT, MODE_COMPUTE, false, TINF, FMT>(A, x, y, nullptr, nullptr);
+    gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT>(A, L, x, y, nullptr, nullptr);
 }
 
-// Re-run the pixels the main pass flagged, deciding near-boundary samples in FP64.
-template <int CRIT, bool TINF, int FMT>
-__global__ __launch_bounds__(64) void gather_fixup(FrameArgs A) {
-    const uint32_t count = A.fix[0];
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-        const uint32_t p = A.fix[1 + t];
-        const int y = (int)(p / (uint32_t)A.W), x = (int)(p % (uint32_t)A.W);
-        gather_pixel<CRIT, MODE_COMPUTE, true, TINF, FMT>(A, x, y, nullptr, nullptr);
-    }
-}
-
-__global__ void reset_counter(uint32_t* c) { *c = 0u; }
-
-__global__ __launch_bounds__(256) void debug_lattice(FrameArgs A, int32_t* out) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+__global__ __launch_bounds__(kBlock) void debug_lattice(FrameArgs A, int32_t* out) {
+    __shared__ ExactLds L;
+    const int x = blockIdx.x * 16 + (int)(threadIdx.x % 16u);
+    const int y = blockIdx.y * 16 + (int)(threadIdx.x / 16u);
     if (x >= A.W || y >= A.H) return;
     int32_t* d = out + ((int64_t)y * A.W + x) * (int64_t)A.nd * 2 * A.ns * 2;
-    gather_pixel<SSVB_HIT_ROUND, MODE_LATTICE, false, false, 0>(A, x, y, d, nullptr);
+    gather_pixel<SSVB_HIT_ROUND, MODE_LATTICE, false, 0>(A, L, x, y, d, nullptr);
 }
 
 template <int CRIT, int FMT>
-__global__ __launch_bounds__(256) void debug_endpoints(FrameArgs A, float* out) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+__global__ __launch_bounds__(kBlock) void debug_endpoints(FrameArgs A, float* out) {
+    __shared__ ExactLds L;
+    const int x = blockIdx.x * 16 + (int)(threadIdx.x % 16u);
+    const int y = blockIdx.y * 16 + (int)(threadIdx.x / 16u);
     if (x >= A.W || y >= A.H) return;
     float* d = out + ((int64_t)y * A.W + x) * (int64_t)A.nd * 2 * A.ns * 2;
-    gather_pixel<CRIT, MODE_ENDPOINTS, false, false, FMT>(A, x, y, nullptr, d);
+    gather_pixel<CRIT, MODE_ENDPOINTS, false, FMT>(A, L, x, y, nullptr, d);
 }
 
 // ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
-static dim3 plain_grid(const FrameArgs& A, dim3 block) {
-    return dim3((A.W + block.x - 1) / block.x, (A.H + block.y - 1) / block.y);
-}
+static dim3 grid16(const FrameArgs& A) { return dim3((A.W + 15) / 16, (A.H + 15) / 16); }
 
 template <int CRIT, bool TINF, int FMT>
-static void launch_pair(const FrameArgs& A, hipStream_t stream) {
+static void launch_main(const FrameArgs& A, hipStream_t stream) {
     const uint32_t nt = (uint32_t)A.tiles_x * A.tiles_y;
     const uint32_t nwg = A.xcd_remap ? kXcds * ((nt + kXcds - 1) / kXcds) : nt;
-    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, A.fix);
     hipLaunchKernelGGL((gather_plain<CRIT, TINF, FMT>), dim3(nwg), dim3(A.tile_w * A.tile_h), 0, stream, A);
-    const int64_t px = (int64_t)A.W * A.H;
-    const int fix_blocks = (int)std::min<int64_t>(std::max<int64_t>((px / 64 + 15) / 16, 64), 4096);
-    hipLaunchKernelGGL((gather_fixup<CRIT, TINF, FMT>), dim3(fix_blocks), dim3(64), 0, stream, A);
 }
 
 template <int CRIT, bool TINF>
 static void launch_fmt(const FrameArgs& A, hipStream_t stream) {
     switch (A.normal_f16 | (A.radiance_f16 << 1)) {
-        case 0: launch_pair<CRIT, TINF, 0>(A, stream); break;
-        case 1: launch_pair<CRIT, TINF, 1>(A, stream); break;
-        case 2: launch_pair<CRIT, TINF, 2>(A, stream); break;
-        default: launch_pair<CRIT, TINF, 3>(A, stream); break;
+        case 0: launch_main<CRIT, TINF, 0>(A, stream); break;
+        case 1: launch_main<CRIT, TINF, 1>(A, stream); break;
+        case 2: launch_main<CRIT, TINF, 2>(A, stream); break;
+        default: launch_main<CRIT, TINF, 3>(A, stream); break;
     }
 }
 
@@ -556,17 +550,15 @@ hipError_t launch_plain(const FrameArgs& A, hipStream_t stream) {
 }
 
 hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream) {
-    const dim3 block(16, 16);
-    hipLaunchKernelGGL(debug_lattice, plain_grid(A, block), block, 0, stream, A, out);
+    hipLaunchKernelGGL(debug_lattice, grid16(A), dim3(kBlock), 0, stream, A, out);
     return hipGetLastError();
 }
 
 template <int CRIT>
 static void launch_endpoints_fmt(const FrameArgs& A, float* out, hipStream_t stream) {
-    const dim3 block(16, 16);
     switch (A.normal_f16) {
-        case 0: hipLaunchKernelGGL((debug_endpoints<CRIT, 0>), plain_grid(A, block), block, 0, stream, A, out); break;
-        default: hipLaunchKernelGGL((debug_endpoints<CRIT, 1>), plain_grid(A, block), block, 0, stream, A, out); break;
+        case 0: hipLaunchKernelGGL((debug_endpoints<CRIT, 0>), grid16(A), dim3(kBlock), 0, stream, A, out); break;
+        default: hipLaunchKernelGGL((debug_endpoints<CRIT, 1>), grid16(A), dim3(kBlock), 0, stream, A, out); break;
     }
 }
 

@@ -146,7 +146,12 @@ def test_create_without_gpu_fails_cleanly(B):
 
 
 def test_validate_depth_span_limit(B):
-    # the depth image is addressed with 32-bit byte offsets
+    # images are addressed with 32-bit byte offsets
     assert status(B, frame(B, W=16384, H=16384, d=setter("pitch_bytes", 65536))) == 0
     assert status(B, frame(B, W=16384, H=16384, d=setter("pitch_bytes", 4 * 65536))) == 0
     assert status(B, frame(B, W=16384, H=16384, d=setter("pitch_bytes", 4 * 65536 + 64))) == 1
+    # 16384 x 16384 x 4 channels x FP32 is exactly 4 GiB; one more row of pitch is not
+    assert status(B, frame(B, W=16384, H=16384, n=setter("channels", 4))) == 0
+    assert status(B, frame(B, W=16384, H=16384, n=setter("channels", 4),
+                           d=setter("pitch_bytes", 0))) == 0
+    assert status(B, frame(B, W=16384, H=16384, n=setter("pitch_bytes", 16384 * 16 + 16))) == 1
