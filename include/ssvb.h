@@ -121,6 +121,22 @@ typedef struct {
     int64_t ao_pitch_bytes, gi_pitch_bytes, ambient_pitch_bytes, masks_pitch_bytes;
 } ssvb_outputs;
 
+/* One frame of a batch: inputs, camera, parameters and outputs (as for ssvb_compute). */
+typedef struct {
+    ssvb_image depth, normal, radiance;
+    ssvb_camera camera;
+    ssvb_params params;
+    ssvb_outputs out;
+} ssvb_frame;
+
+/* Launch shape of the gather: workgroups of tile_w x tile_h pixels with lanes_per_pixel
+ * lanes each (tile_w * tile_h * lanes_per_pixel = 256; lanes_per_pixel in {1, 2, 4, 8}
+ * splits a pixel's slices over adjacent lanes), tiles walked in vertical strips of
+ * `strip` tiles.  Shapes change speed only, never results beyond FP32 summation order. */
+typedef struct {
+    int32_t tile_w, tile_h, strip, lanes_per_pixel;
+} ssvb_launch;
+
 typedef struct ssvb_ctx ssvb_ctx;
 
 /* Human-readable name of a status code.  Never NULL. */
@@ -154,6 +170,31 @@ ssvb_status ssvb_validate(const ssvb_image* depth, const ssvb_image* normal,
 ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
                          const ssvb_image* radiance, const ssvb_camera* camera,
                          const ssvb_params* params, const ssvb_outputs* out, void* hip_stream);
+
+/* Many frames of mixed size, slice/step counts, criteria and element types in one
+ * replay of a captured HIP graph (descriptor upload + one persistent kernel), asynchronous
+ * on `hip_stream`.  Each frame's outputs equal what ssvb_compute writes for it with the
+ * same launch shape.  Frames are processed in chunks of 64.  The library keeps two
+ * descriptor slots, so a call may block until the batch submitted two calls earlier has
+ * been uploaded.  Returns SSVB_ERR_INVALID_ARG naming the first invalid frame. */
+ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t n, void* hip_stream);
+
+/* Force one launch shape for every later frame of this context (NULL: back to the
+ * autotuned shape of the frame's class, else the default 32 x 8, strip 4, 1 lane). */
+ssvb_status ssvb_set_launch(ssvb_ctx* ctx, const ssvb_launch* shape);
+
+/* The launch shape ssvb_compute would use for this camera / parameter / element-type
+ * class (fp16_mask: bit 0 normals FP16, bit 1 radiance FP16). */
+ssvb_status ssvb_get_launch(ssvb_ctx* ctx, const ssvb_camera* camera, const ssvb_params* params,
+                            int32_t fp16_mask, ssvb_launch* out);
+
+/* Time candidate launch shapes on `frame` (its outputs are overwritten; synchronises
+ * `hip_stream`), remember the fastest for the frame's class (width, height, slices,
+ * steps, element types) and return it with its time in ms.  If the environment variable
+ * SSVB_TUNE_CACHE names a file, tuned shapes are loaded from it by ssvb_create and
+ * appended to it here. */
+ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stream, ssvb_launch* best,
+                          float* best_ms);
 
 /* Test hook: the integer step lattice of ssvb_compute.  xy_out (device, int32) receives,
  * for every pixel, slice, side (+ then -) and step, the sampled texel (X, Y), laid out

@@ -26,8 +26,9 @@ NOISE_NAMES = {"hash": NOISE_HASH, "r2": NOISE_R2, "fixed": NOISE_FIXED}
 # every symbol include/ssvb.h declares
 EXPORTED = [
     "ssvb_status_string", "ssvb_last_error", "ssvb_default_params", "ssvb_create", "ssvb_destroy",
-    "ssvb_validate", "ssvb_compute", "ssvb_debug_lattice", "ssvb_debug_endpoints",
-    "ssvb_debug_direction_table", "ssvb_debug_noise_constants",
+    "ssvb_validate", "ssvb_compute", "ssvb_compute_batch", "ssvb_set_launch", "ssvb_get_launch",
+    "ssvb_autotune", "ssvb_debug_lattice", "ssvb_debug_endpoints", "ssvb_debug_direction_table",
+    "ssvb_debug_noise_constants",
 ]
 
 
@@ -54,6 +55,19 @@ class ssvb_outputs(ctypes.Structure):
     _fields_ = [("ao", ctypes.c_void_p), ("gi", ctypes.c_void_p), ("ambient", ctypes.c_void_p),
                 ("masks", ctypes.c_void_p), ("ao_pitch_bytes", ctypes.c_int64), ("gi_pitch_bytes", ctypes.c_int64),
                 ("ambient_pitch_bytes", ctypes.c_int64), ("masks_pitch_bytes", ctypes.c_int64)]
+
+
+class ssvb_frame(ctypes.Structure):
+    _fields_ = [("depth", ssvb_image), ("normal", ssvb_image), ("radiance", ssvb_image), ("camera", ssvb_camera),
+                ("params", ssvb_params), ("out", ssvb_outputs)]
+
+
+class ssvb_launch(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("strip", ctypes.c_int32),
+                ("lanes_per_pixel", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.tile_w, self.tile_h, self.strip, self.lanes_per_pixel)
 
 
 _LIB = None
@@ -85,6 +99,14 @@ def lib() -> ctypes.CDLL:
     L.ssvb_compute.restype = I
     L.ssvb_compute.argtypes = [V, P(ssvb_image), P(ssvb_image), P(ssvb_image), P(ssvb_camera), P(ssvb_params),
                                P(ssvb_outputs), V]
+    L.ssvb_compute_batch.restype = I
+    L.ssvb_compute_batch.argtypes = [V, P(ssvb_frame), I, V]
+    L.ssvb_set_launch.restype = I
+    L.ssvb_set_launch.argtypes = [V, P(ssvb_launch)]
+    L.ssvb_get_launch.restype = I
+    L.ssvb_get_launch.argtypes = [V, P(ssvb_camera), P(ssvb_params), I, P(ssvb_launch)]
+    L.ssvb_autotune.restype = I
+    L.ssvb_autotune.argtypes = [V, P(ssvb_frame), V, P(ssvb_launch), P(ctypes.c_float)]
     L.ssvb_debug_lattice.restype = I
     L.ssvb_debug_lattice.argtypes = [V, P(ssvb_image), P(ssvb_camera), P(ssvb_params), V, V]
     L.ssvb_debug_endpoints.restype = I
@@ -227,6 +249,59 @@ class Context:
         check(lib().ssvb_compute(self.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(r), ctypes.byref(c),
                                  ctypes.byref(p), ctypes.byref(o), _stream_ptr(stream)), "ssvb_compute")
         return out
+
+    @staticmethod
+    def alloc_outputs(H, W, slices, device, masks=False):
+        import torch
+        out = {"ao": torch.empty((H, W), dtype=torch.float32, device=device),
+               "gi": torch.empty((H, W, 3), dtype=torch.float32, device=device),
+               "ambient": torch.empty((H, W, 3), dtype=torch.float32, device=device)}
+        if masks:
+            out["masks"] = torch.empty((H, W, slices), dtype=torch.int32, device=device)
+        return out
+
+    @staticmethod
+    def outputs_of(out) -> ssvb_outputs:
+        m = out.get("masks")
+        return ssvb_outputs(out["ao"].data_ptr(), out["gi"].data_ptr(), out["ambient"].data_ptr(),
+                            m.data_ptr() if m is not None else None, out["ao"].stride(0) * 4,
+                            out["gi"].stride(0) * 4, out["ambient"].stride(0) * 4,
+                            m.stride(0) * 4 if m is not None else 0)
+
+    def frame(self, depth, normal, radiance, camera: Camera, params: Params, out) -> ssvb_frame:
+        return ssvb_frame(image_of(depth), image_of(normal), image_of(radiance), camera.to_c(), params.to_c(),
+                          self.outputs_of(out))
+
+    def compute_batch(self, items, stream=None):
+        """items: list of (depth, normal, radiance, camera, params, out) with torch device
+        tensors; runs ssvb_compute_batch (one graph replay per 64 frames)."""
+        arr = (ssvb_frame * max(len(items), 1))()
+        for i, it in enumerate(items):
+            arr[i] = self.frame(*it)
+        check(lib().ssvb_compute_batch(self.handle, arr, len(items), _stream_ptr(stream)), "ssvb_compute_batch")
+
+    def set_launch(self, shape=None):
+        """Force a launch shape (tile_w, tile_h, strip, lanes_per_pixel); None: automatic."""
+        if shape is None:
+            check(lib().ssvb_set_launch(self.handle, None), "ssvb_set_launch")
+        else:
+            L = ssvb_launch(*shape)
+            check(lib().ssvb_set_launch(self.handle, ctypes.byref(L)), "ssvb_set_launch")
+
+    def get_launch(self, camera: Camera, params: Params, fp16_mask=0):
+        L = ssvb_launch()
+        check(lib().ssvb_get_launch(self.handle, ctypes.byref(camera.to_c()), ctypes.byref(params.to_c()),
+                                    fp16_mask, ctypes.byref(L)), "ssvb_get_launch")
+        return L.as_tuple()
+
+    def autotune(self, depth, normal, radiance, camera: Camera, params: Params, out, stream=None):
+        """Time candidate launch shapes on this frame; returns (shape tuple, ms)."""
+        F = self.frame(depth, normal, radiance, camera, params, out)
+        L = ssvb_launch()
+        ms = ctypes.c_float()
+        check(lib().ssvb_autotune(self.handle, ctypes.byref(F), _stream_ptr(stream), ctypes.byref(L),
+                                  ctypes.byref(ms)), "ssvb_autotune")
+        return L.as_tuple(), ms.value
 
     def debug_lattice(self, depth, camera: Camera, params: Params, stream=None):
         import torch

@@ -6,8 +6,12 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "ssvb_internal.h"
 
@@ -15,15 +19,40 @@ namespace ssvb {
 hipError_t launch_plain(const FrameArgs& A, hipStream_t stream);
 hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream);
 hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t stream);
+hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, int grid,
+                         hipStream_t s);
+int batch_blocks_per_cu();
 }  // namespace ssvb
 
 using namespace ssvb;
 
+// frame class for tuned launch shapes: width, height, slices, steps, FP16 mask
+using ShapeKey = std::tuple<int, int, int, int, int>;
+
+constexpr int kBatchSlots = 2;  // descriptor slots of the batched path (double buffering)
+
 struct ssvb_ctx {
     int device = 0;
-    int2* d_lut = nullptr;     // slice directions
-    double2* d_half = nullptr; // cos, sin of h pi / 64, h = -64..64
+    int2* d_lut = nullptr;      // slice directions
+    double2* d_half = nullptr;  // cos, sin of h pi / 64, h = -64..64
     int2 h_lut[kLutSize];
+    // launch shapes
+    bool forced = false;
+    LaunchShape force{32, 8, 4, 1};
+    std::map<ShapeKey, LaunchShape> tuned;
+    std::string tune_cache;
+    // batched path: pinned + device descriptor tables, queue counters, captured graphs
+    bool batch_ready = false;
+    int batch_grid = 0;
+    hipStream_t cap_stream = nullptr;
+    BatchDesc* h_desc[kBatchSlots] = {};
+    BatchDesc* d_desc[kBatchSlots] = {};
+    uint32_t* d_queues[kBatchSlots] = {};
+    hipGraph_t graph[kBatchSlots] = {};
+    hipGraphExec_t exec[kBatchSlots] = {};
+    hipEvent_t done[kBatchSlots] = {};
+    bool pending[kBatchSlots] = {};
+    uint64_t next_slot = 0;
 };
 
 namespace {
@@ -127,6 +156,29 @@ void r2_constants(uint32_t out[3]) {
     out[2] = (uint32_t)llroundl(two32 / phi);
 }
 
+}  // namespace
+
+namespace ssvb {
+// Apply a launch shape to a frame (clamped to valid values).
+void set_launch(FrameArgs& A, LaunchShape L) {
+    if (!(L.lp == 1 || L.lp == 2 || L.lp == 4 || L.lp == 8)) L.lp = 1;
+    if (L.tile_w < 1 || L.tile_h < 1 || L.tile_w * L.tile_h * L.lp != 256) {
+        L.tile_w = 32 / L.lp > 0 ? 32 / L.lp : 1;
+        L.tile_h = 256 / L.lp / L.tile_w;
+    }
+    A.tile_w = L.tile_w;
+    A.tile_h = L.tile_h;
+    A.lp = L.lp;
+    A.xcd_remap = 1;
+    A.tiles_x = (A.W + A.tile_w - 1) / A.tile_w;
+    A.tiles_y = (A.H + A.tile_h - 1) / A.tile_h;
+    A.strip = L.strip > 0 ? L.strip : 1;
+    if (A.strip > A.tiles_x) A.strip = A.tiles_x > 0 ? A.tiles_x : 1;
+}
+}  // namespace ssvb
+
+namespace {
+
 // Fill the frame constants: FP64 derivation, one rounding to FP32.
 void fill_frame(FrameArgs& A, const ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
                 const ssvb_image* radiance, const ssvb_camera* cam, const ssvb_params* p, const ssvb_outputs* out) {
@@ -195,23 +247,113 @@ void fill_frame(FrameArgs& A, const ssvb_ctx* ctx, const ssvb_image* depth, cons
     }
     A.lut = ctx ? ctx->d_lut : nullptr;
     A.half_sector = ctx ? ctx->d_half : nullptr;
-    // launch shape (tuned defaults; SSVB_TILE=WxH, SSVB_STRIP=n, SSVB_XCD=0|1 override)
-    A.tile_w = 32;
-    A.tile_h = 8;
-    A.strip = 4;
-    A.xcd_remap = 1;
-    if (const char* e = getenv("SSVB_TILE")) {
-        int tw = 0, th = 0;
-        if (sscanf(e, "%dx%d", &tw, &th) == 2 && tw > 0 && th > 0 && tw * th <= 256 && (tw * th) % 64 == 0) {
-            A.tile_w = tw;
-            A.tile_h = th;
+    LaunchShape shape{32, 8, 4, 1};
+    if (ctx) {
+        if (ctx->forced) {
+            shape = ctx->force;
+        } else {
+            const int fmt = (normal && normal->dtype == SSVB_F16 ? 1 : 0) | (radiance && radiance->dtype == SSVB_F16 ? 2 : 0);
+            auto it = ctx->tuned.find(ShapeKey{W, H, p->slices, p->steps, fmt});
+            if (it != ctx->tuned.end()) shape = it->second;
         }
     }
-    if (const char* e = getenv("SSVB_STRIP")) A.strip = atoi(e) > 0 ? atoi(e) : A.strip;
-    if (const char* e = getenv("SSVB_XCD")) A.xcd_remap = atoi(e) != 0;
-    A.tiles_x = (W + A.tile_w - 1) / A.tile_w;
-    A.tiles_y = (H + A.tile_h - 1) / A.tile_h;
-    A.strip = A.strip < A.tiles_x ? A.strip : (A.tiles_x > 0 ? A.tiles_x : 1);
+    set_launch(A, shape);
+}
+
+bool valid_shape(const ssvb_launch* L) {
+    if (!L) return false;
+    const int lp = L->lanes_per_pixel;
+    return (lp == 1 || lp == 2 || lp == 4 || lp == 8) && L->tile_w > 0 && L->tile_h > 0 &&
+           L->tile_w * L->tile_h * lp == 256 && L->strip > 0;
+}
+
+void load_tune_cache(ssvb_ctx* ctx) {
+    const char* path = getenv("SSVB_TUNE_CACHE");
+    if (!path || !*path) return;
+    ctx->tune_cache = path;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    int W, H, nd, ns, fmt, tw, th, st, lp;
+    float ms;
+    while (fscanf(f, "%d %d %d %d %d %d %d %d %d %f", &W, &H, &nd, &ns, &fmt, &tw, &th, &st, &lp, &ms) == 10) {
+        ssvb_launch L{tw, th, st, lp};
+        if (valid_shape(&L)) ctx->tuned[ShapeKey{W, H, nd, ns, fmt}] = LaunchShape{tw, th, st, lp};
+    }
+    fclose(f);
+}
+
+ssvb_status init_batch(ssvb_ctx* ctx) {
+    if (ctx->batch_ready) return SSVB_OK;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    const int per_cu = batch_blocks_per_cu();
+    ctx->batch_grid = ((prop.multiProcessorCount * per_cu + kXcds - 1) / kXcds) * kXcds;
+    e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    for (int k = 0; k < kBatchSlots && e == hipSuccess; ++k) {
+        e = hipHostMalloc((void**)&ctx->h_desc[k], sizeof(BatchDesc), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_desc[k], sizeof(BatchDesc));
+        if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_queues[k], 64 * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->done[k], hipEventDisableTiming);
+        if (e != hipSuccess) break;
+        memset(ctx->h_desc[k], 0, sizeof(BatchDesc));
+        // one graph per slot: descriptor upload, queue reset, persistent kernel
+        e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) break;
+        hipError_t ce = capture_batch(ctx->d_desc[k], ctx->h_desc[k], ctx->d_queues[k], ctx->batch_grid,
+                                      ctx->cap_stream);
+        e = hipStreamEndCapture(ctx->cap_stream, &ctx->graph[k]);
+        if (ce != hipSuccess) e = ce;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ctx->exec[k], ctx->graph[k], nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(SSVB_ERR_OUT_OF_MEMORY, "batch buffers")
+                                                          : hip_fail(e, "batch set-up");
+    ctx->batch_ready = true;
+    return SSVB_OK;
+}
+
+void free_batch(ssvb_ctx* ctx) {
+    for (int k = 0; k < kBatchSlots; ++k) {
+        if (ctx->exec[k]) hipGraphExecDestroy(ctx->exec[k]);
+        if (ctx->graph[k]) hipGraphDestroy(ctx->graph[k]);
+        if (ctx->done[k]) hipEventDestroy(ctx->done[k]);
+        if (ctx->d_queues[k]) hipFree(ctx->d_queues[k]);
+        if (ctx->d_desc[k]) hipFree(ctx->d_desc[k]);
+        if (ctx->h_desc[k]) hipHostFree(ctx->h_desc[k]);
+    }
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+}
+
+// Build one descriptor table: frame constants and, per XCD, the cost-ordered segments.
+void build_batch(ssvb_ctx* ctx, BatchDesc* D, const ssvb_frame* frames, int n) {
+    D->n_frames = n;
+    std::vector<int> order(n);
+    std::vector<double> cost(n);
+    for (int f = 0; f < n; ++f) {
+        const ssvb_frame& F = frames[f];
+        fill_frame(D->frames[f], ctx, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
+        order[f] = f;
+        // work of one tile: its pixels times the samples of a pixel
+        const FrameArgs& A = D->frames[f];
+        cost[f] = (double)A.tile_w * A.tile_h * A.nd * A.ns;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int k = 0; k < kXcds; ++k) {
+        uint32_t start = 0;
+        int ns = 0;
+        for (int f : order) {
+            const FrameArgs& A = D->frames[f];
+            const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+            const uint32_t per = (nt + kXcds - 1) / kXcds;
+            const uint32_t first = (uint32_t)k * per;
+            if (first >= nt) continue;
+            const uint32_t count = std::min(per, nt - first);
+            D->seg[k][ns++] = BatchSegment{f, first, count, start};
+            start += count;
+        }
+        D->n_seg[k] = ns;
+        D->total[k] = start;
+    }
 }
 
 }  // namespace
@@ -271,6 +413,7 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
         delete ctx;
         return hip_fail(e, "hipSetDevice");
     }
+    load_tune_cache(ctx);
     double2 half[129];
     for (int h = -64; h <= 64; ++h) half[h + 64] = make_double2(cos(M_PI * h / 64.0), sin(M_PI * h / 64.0));
     e = hipMalloc((void**)&ctx->d_lut, sizeof ctx->h_lut);
@@ -293,6 +436,7 @@ ssvb_status ssvb_destroy(ssvb_ctx* ctx) {
     int prev = 0;
     hipGetDevice(&prev);
     hipSetDevice(ctx->device);
+    free_batch(ctx);
     if (ctx->d_lut) hipFree(ctx->d_lut);
     if (ctx->d_half) hipFree(ctx->d_half);
     hipSetDevice(prev);
@@ -336,6 +480,127 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     const hipError_t e = launch_plain(A, (hipStream_t)hip_stream);
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) return hip_fail(e, "gather launch");
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t n, void* hip_stream) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    if (n < 0 || (n > 0 && !frames)) return fail(SSVB_ERR_INVALID_ARG, "bad frame array");
+    for (int f = 0; f < n; ++f) {
+        const ssvb_frame& F = frames[f];
+        ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
+        if (s) return fail(s, "frame %d: %s", f, g_last_error.c_str());
+    }
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    ssvb_status st = init_batch(ctx);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    for (int f0 = 0; st == SSVB_OK && f0 < n; f0 += kMaxBatch) {
+        // frames with no pixels launch nothing
+        std::vector<ssvb_frame> chunk;
+        for (int f = f0; f < std::min(n, f0 + kMaxBatch); ++f)
+            if ((int64_t)frames[f].camera.width * frames[f].camera.height > 0) chunk.push_back(frames[f]);
+        if (chunk.empty()) continue;
+        const int slot = (int)(ctx->next_slot++ % kBatchSlots);
+        hipError_t e = hipSuccess;
+        if (ctx->pending[slot]) e = hipEventSynchronize(ctx->done[slot]);  // the slot's last upload is done
+        if (e == hipSuccess) {
+            build_batch(ctx, ctx->h_desc[slot], chunk.data(), (int)chunk.size());
+            e = hipGraphLaunch(ctx->exec[slot], stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(ctx->done[slot], stream);
+        if (e != hipSuccess) st = hip_fail(e, "batch launch");
+        else ctx->pending[slot] = true;
+    }
+    if (prev != ctx->device) hipSetDevice(prev);
+    return st;
+}
+
+ssvb_status ssvb_set_launch(ssvb_ctx* ctx, const ssvb_launch* shape) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    if (!shape) {
+        ctx->forced = false;
+        return SSVB_OK;
+    }
+    if (!valid_shape(shape)) return fail(SSVB_ERR_INVALID_ARG, "launch shape needs tile_w*tile_h*lanes = 256, lanes 1/2/4/8, strip > 0");
+    ctx->forced = true;
+    ctx->force = LaunchShape{shape->tile_w, shape->tile_h, shape->strip, shape->lanes_per_pixel};
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_get_launch(ssvb_ctx* ctx, const ssvb_camera* camera, const ssvb_params* params, int32_t fp16_mask,
+                            ssvb_launch* out) {
+    if (!ctx || !camera || !params || !out) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
+    ssvb_image n{nullptr, 0, (fp16_mask & 1) ? SSVB_F16 : SSVB_F32, 3};
+    ssvb_image r{nullptr, 0, (fp16_mask & 2) ? SSVB_F16 : SSVB_F32, 3};
+    ssvb_image d{nullptr, 0, SSVB_F32, 1};
+    FrameArgs A;
+    fill_frame(A, ctx, &d, &n, &r, camera, params, nullptr);
+    *out = ssvb_launch{A.tile_w, A.tile_h, A.strip, A.lp};
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stream, ssvb_launch* best, float* best_ms) {
+    if (!ctx || !frame) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
+    const ssvb_frame& F = *frame;
+    ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
+    if (s) return s;
+    if ((int64_t)F.camera.width * F.camera.height == 0) return fail(SSVB_ERR_INVALID_ARG, "empty frame");
+    static const int kTiles[][3] = {{32, 8, 1}, {16, 16, 1}, {64, 4, 1}, {8, 32, 1}, {16, 8, 2}, {8, 16, 2},
+                                    {32, 4, 2}, {8, 8, 4},   {16, 4, 4}, {8, 4, 8},  {4, 8, 8}};
+    static const int kStrips[] = {2, 4, 8};
+    hipStream_t stream = (hipStream_t)hip_stream;
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    const bool was_forced = ctx->forced;
+    const LaunchShape was = ctx->force;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best_t = 1e30f;
+    LaunchShape best_s{32, 8, 4, 1};
+    for (const auto& tl : kTiles) {
+        for (int st : kStrips) {
+            if (e != hipSuccess) break;
+            ctx->forced = true;
+            ctx->force = LaunchShape{tl[0], tl[1], st, tl[2]};
+            float times[3];
+            for (int rep = -1; rep < 3 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, stream);
+                if (e == hipSuccess && (s = ssvb_compute(ctx, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params,
+                                                         &F.out, hip_stream)) != SSVB_OK)
+                    e = hipErrorUnknown;
+                if (e == hipSuccess) e = hipEventRecord(e1, stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess && rep >= 0) e = hipEventElapsedTime(&times[rep], e0, e1);
+            }
+            if (e != hipSuccess) break;
+            std::sort(times, times + 3);
+            if (times[1] < best_t) {
+                best_t = times[1];
+                best_s = ctx->force;
+            }
+        }
+    }
+    ctx->forced = was_forced;
+    ctx->force = was;
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (prev != ctx->device) hipSetDevice(prev);
+    if (e != hipSuccess) return s != SSVB_OK ? s : hip_fail(e, "autotune");
+    const int fmt = (F.normal.dtype == SSVB_F16 ? 1 : 0) | (F.radiance.dtype == SSVB_F16 ? 2 : 0);
+    ctx->tuned[ShapeKey{F.camera.width, F.camera.height, F.params.slices, F.params.steps, fmt}] = best_s;
+    if (!ctx->tune_cache.empty()) {
+        if (FILE* f = fopen(ctx->tune_cache.c_str(), "a")) {
+            fprintf(f, "%d %d %d %d %d %d %d %d %d %.4f\n", F.camera.width, F.camera.height, F.params.slices,
+                    F.params.steps, fmt, best_s.tile_w, best_s.tile_h, best_s.strip, best_s.lp, best_t);
+            fclose(f);
+        }
+    }
+    if (best) *best = ssvb_launch{best_s.tile_w, best_s.tile_h, best_s.strip, best_s.lp};
+    if (best_ms) *best_ms = best_t;
     return SSVB_OK;
 }
 

@@ -58,19 +58,21 @@ struct FrameArgs {
     // strips of `strip` tiles, and with xcd_remap each XCD takes a contiguous run of that
     // walk (workgroup i runs on XCD i mod kXcds)
     int32_t tile_w, tile_h, tiles_x, tiles_y, strip, xcd_remap;
+    // lanes per pixel: the N_d slices of a pixel are split over lp adjacent lanes;
+    // tile_w * tile_h * lp = 256 threads per workgroup
+    int32_t lp;
 };
 
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
 
-// Workgroup index -> tile (tx, ty); false for the padding workgroups past the end.
-__device__ __forceinline__ bool tile_of(const FrameArgs& A, uint32_t bid, int& tx, int& ty) {
-    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
-    uint32_t ord = bid;
-    if (A.xcd_remap) {
-        const uint32_t per = (nt + kXcds - 1) / kXcds;
-        ord = (bid % kXcds) * per + bid / kXcds;
-    }
-    if (ord >= nt) return false;
+// A launch shape: tile of tile_w x tile_h pixels, strip width in tiles, lanes per pixel.
+struct LaunchShape {
+    int32_t tile_w, tile_h, strip, lp;
+};
+void set_launch(FrameArgs& A, LaunchShape L);
+
+// Position `ord` of the strip walk over the frame's tiles -> tile (tx, ty).
+__device__ __forceinline__ void walk_tile(const FrameArgs& A, uint32_t ord, int& tx, int& ty) {
     const uint32_t S = (uint32_t)A.strip, TY = (uint32_t)A.tiles_y;
     const uint32_t full = (uint32_t)A.tiles_x / S;
     if (ord < full * S * TY) {
@@ -82,7 +84,39 @@ __device__ __forceinline__ bool tile_of(const FrameArgs& A, uint32_t bid, int& t
         ty = (int)(r / wl);
         tx = (int)(full * S + r % wl);
     }
+}
+
+// Workgroup index -> tile (tx, ty); false for the padding workgroups past the end.
+__device__ __forceinline__ bool tile_of(const FrameArgs& A, uint32_t bid, int& tx, int& ty) {
+    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+    uint32_t ord = bid;
+    if (A.xcd_remap) {
+        const uint32_t per = (nt + kXcds - 1) / kXcds;
+        ord = (bid % kXcds) * per + bid / kXcds;
+    }
+    if (ord >= nt) return false;
+    walk_tile(A, ord, tx, ty);
     return true;
 }
+
+// ---------------------------------------------------------------------------------------
+// batched persistent path
+// ---------------------------------------------------------------------------------------
+constexpr int kMaxBatch = 64;  // frames per descriptor table (larger batches are chunked)
+
+// A run of one frame's tile walk in one XCD's queue: queue items [start, start + count)
+// are the frame's walk positions [first, first + count).
+struct BatchSegment {
+    int32_t frame;
+    uint32_t first, count, start;
+};
+
+struct BatchDesc {
+    int32_t n_frames;
+    int32_t n_seg[kXcds];
+    uint32_t total[kXcds];
+    BatchSegment seg[kXcds][kMaxBatch];
+    FrameArgs frames[kMaxBatch];
+};
 
 }  // namespace ssvb

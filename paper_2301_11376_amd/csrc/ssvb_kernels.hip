@@ -69,10 +69,12 @@ __device__ __forceinline__ float depth_load(const FrameArgs& A, uint32_t off) {
     return *(const float*)((const char*)A.depth + off);
 }
 
-template <bool F16>
-__device__ __forceinline__ float3 load3(const char* base, int64_t pitch, int ch, int x, int y) {
-    const uint32_t off = (uint32_t)y * (uint32_t)pitch + (uint32_t)(x * ch) * (F16 ? 2u : 4u);
-    if (F16) {
+// F: 0 = FP32, 1 = FP16, -1 = given at run time by `f16`
+template <int F>
+__device__ __forceinline__ float3 load3(const char* base, int64_t pitch, int ch, int f16, int x, int y) {
+    const bool h = F < 0 ? f16 != 0 : F == 1;
+    const uint32_t off = (uint32_t)y * (uint32_t)pitch + (uint32_t)(x * ch) * (h ? 2u : 4u);
+    if (h) {
         const _Float16* p = (const _Float16*)(base + off);
         return make_float3((float)p[0], (float)p[1], (float)p[2]);
     }
@@ -185,22 +187,22 @@ __device__ __forceinline__ bool at_or_above(const FrameArgs& A, int h, double cg
 // Exact floor of the FP32 sector coordinate `y` (ROUND: y = 32 u + 1/2; PSEUDOCODE: y =
 // 32 u) of an endpoint with direction (sv, se), given that y is near the integer m.  The
 // angle is clamped to the hemisphere first, so the floor never drops below 0.
-template <int CRIT>
-__device__ __forceinline__ int exact_floor(const FrameArgs& A, float y, double cg, double sg, double sv, double se) {
+__device__ __forceinline__ int exact_floor(const FrameArgs& A, bool round, float y, double cg, double sg, double sv,
+                                           double se) {
     const int m = (int)rintf(y);
     // boundary y = m sits at theta = (m - 16.5) pi / 32 (ROUND) or (m - 16) pi / 32
-    const int h = CRIT == SSVB_HIT_ROUND ? 2 * m - 33 : 2 * m - 32;
+    const int h = round ? 2 * m - 33 : 2 * m - 32;
     return at_or_above(A, h, cg, sg, sv, se) ? m : max(m - 1, 0);
 }
 
-// Direction of an endpoint given its FP32 sector coordinate: the sample's own direction,
-// or the hemisphere edge when the coordinate was clamped there.
-__device__ __forceinline__ void endpoint_dir(float y, float lo_clamp, float hi_clamp, double cg, double sg, double sv,
-                                             double se, double& dv, double& de) {
-    if (y <= lo_clamp) {  // theta = -pi/2
+// Direction of a clamped endpoint: the hemisphere edge it was clamped to (side -1 below
+// -pi/2, +1 above +pi/2), else the sample's own direction.
+__device__ __forceinline__ void endpoint_dir(int side, double cg, double sg, double sv, double se, double& dv,
+                                             double& de) {
+    if (side < 0) {  // theta = -pi/2
         dv = sg;
         de = -cg;
-    } else if (y >= hi_clamp) {  // theta = +pi/2
+    } else if (side > 0) {  // theta = +pi/2
         dv = -sg;
         de = cg;
     } else {
@@ -214,7 +216,8 @@ __device__ __forceinline__ void endpoint_dir(float y, float lo_clamp, float hi_c
 // ---------------------------------------------------------------------------------------
 enum { MODE_COMPUTE = 0, MODE_LATTICE = 1, MODE_ENDPOINTS = 2 };
 
-__device__ __forceinline__ void store_background(const FrameArgs& A, int x, int y) {
+__device__ __forceinline__ void store_background(const FrameArgs& A, int x, int y, int li) {
+    if (li != 0) return;
     *(float*)((char*)A.ao + (int64_t)y * A.ao_pitch + (int64_t)x * 4) = 1.0f;
     float* g = (float*)((char*)A.gi + (int64_t)y * A.gi_pitch) + 3 * (int64_t)x;
     float* m = (float*)((char*)A.amb + (int64_t)y * A.amb_pitch) + 3 * (int64_t)x;
@@ -243,8 +246,9 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
     const float ab = TINF ? 3.14159265358979324f : atan2_pos(h, c - tp);
     const float yf = fminf(fmaxf(fmaf(af, sk, S.K), 0.5f), 32.5f);
     const float yb = fminf(fmaxf(fmaf(ab, sk, S.K), 0.5f), 32.5f);
+    const bool round = CRIT < 0 ? A.criterion == SSVB_HIT_ROUND : CRIT == SSVB_HIT_ROUND;
     int a, b;
-    if (CRIT == SSVB_HIT_ROUND) {
+    if (round) {
         int kf = (int)floorf(yf), kb = (int)floorf(yb);
         if ((near_integer(yf) | near_integer(yb)) && ok) {
             // FP64 decision of the endpoint(s) next to a boundary
@@ -253,20 +257,23 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
             const double cd = -(zsd - zpd) * L.R[t] + zsd * lam * L.av[t];
             const double he = zsd * lam * L.ae[t];
             const double cg = L.cg[t], sg = L.sg[t];
-            if (near_integer(yf)) kf = exact_floor<CRIT>(A, yf, cg, sg, cd, he);
+            if (near_integer(yf)) kf = exact_floor(A, round, yf, cg, sg, cd, he);
             if (near_integer(yb)) {
-                if (TINF || isinf(L.tp[t])) kb = exact_floor<CRIT>(A, yb, cg, sg, -1.0, 0.0);
-                else kb = exact_floor<CRIT>(A, yb, cg, sg, cd - L.tp[t], he);
+                if (TINF || isinf(L.tp[t])) kb = exact_floor(A, round, yb, cg, sg, -1.0, 0.0);
+                else kb = exact_floor(A, round, yb, cg, sg, cd - L.tp[t], he);
             }
         }
         a = min(kf, kb);
         b = max(kf, kb);
     } else {
-        const float lo = fminf(yf, yb), hi = fmaxf(yf, yb);
+        // the angular order of the endpoints is fixed by geometry: on the + side the back
+        // angle is at or above the front one, on the - side at or below it
+        const float lo = s > 0 ? yf : yb, hi = s > 0 ? yb : yf;
         int kf = (int)floorf(yf - 0.5f), kb = (int)floorf(yb - 0.5f);
         const float wf = hi - lo;
-        int w = (int)ceilf(wf);
+        int w = (int)ceilf(fmaxf(wf, 0.0f));
         if ((near_integer(yf - 0.5f) | near_integer(yb - 0.5f) | near_integer(wf)) && ok) {
+#pragma clang fp contract(off)
             const double zsd = zs, zpd = zp;
             const double lam = (double)(s * o) * 0.0625;
             const double cd = -(zsd - zpd) * L.R[t] + zsd * lam * L.av[t];
@@ -274,22 +281,30 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
             const double cg = L.cg[t], sg = L.sg[t];
             const bool binf = TINF || isinf(L.tp[t]);
             const double bv = binf ? -1.0 : cd - L.tp[t], be = binf ? 0.0 : he;
-            if (near_integer(yf - 0.5f)) kf = exact_floor<CRIT>(A, yf - 0.5f, cg, sg, cd, he);
-            if (near_integer(yb - 0.5f)) kb = exact_floor<CRIT>(A, yb - 0.5f, cg, sg, bv, be);
-            if (near_integer(wf) && !((yf <= 0.5f && yb <= 0.5f) || (yf >= 32.5f && yb >= 32.5f))) {
-#pragma clang fp contract(off)
-                // width = ceil of the angle between the two (clamped) endpoint directions;
-                // two endpoints clamped to the same edge have width 0 (ceilf(0) above)
-                double fv, fe, bv2, be2;
-                endpoint_dir(yf, 0.5f, 32.5f, cg, sg, cd, he, fv, fe);
-                endpoint_dir(yb, 0.5f, 32.5f, cg, sg, bv, be, bv2, be2);
-                const bool f_hi = yf >= yb;
-                const double lv = f_hi ? bv2 : fv, le = f_hi ? be2 : fe;
-                const double hv = f_hi ? fv : bv2, hev = f_hi ? fe : be2;
-                const int m = (int)rintf(wf);
-                const double2 cs = A.half_sector[2 * m + 64];  // rotate the low end by m pi / 32
-                const double rv = cs.x * lv - cs.y * le, re = cs.y * lv + cs.x * le;
-                w = (rv * hev - re * hv <= 0.0) ? m : m + 1;
+            if (near_integer(yf - 0.5f)) kf = exact_floor(A, round, yf - 0.5f, cg, sg, cd, he);
+            if (near_integer(yb - 0.5f)) kb = exact_floor(A, round, yb - 0.5f, cg, sg, bv, be);
+            if (near_integer(wf)) {
+                // width = ceil of the angle between the two clamped endpoint directions; an
+                // endpoint near a hemisphere edge is clamped (or not) exactly
+                const float yfr = fmaf(af, sk, S.K), ybr = TINF ? yb : fmaf(ab, sk, S.K);
+                int sf = 0, sb = 0;  // +1 above the +pi/2 edge, -1 below the -pi/2 edge
+                if (yfr >= 32.5f + kGuard || (yfr > 32.5f - kGuard && at_or_above(A, 32, cg, sg, cd, he))) sf = 1;
+                if (yfr <= 0.5f - kGuard || (yfr < 0.5f + kGuard && !at_or_above(A, -32, cg, sg, cd, he))) sf = -1;
+                if (ybr >= 32.5f + kGuard || (ybr > 32.5f - kGuard && at_or_above(A, 32, cg, sg, bv, be))) sb = 1;
+                if (ybr <= 0.5f - kGuard || (ybr < 0.5f + kGuard && !at_or_above(A, -32, cg, sg, bv, be))) sb = -1;
+                if (sf != 0 && sf == sb) {
+                    w = 0;  // both endpoints on the same edge
+                } else {
+                    double fv, fe, bv2, be2;
+                    endpoint_dir(sf, cg, sg, cd, he, fv, fe);
+                    endpoint_dir(sb, cg, sg, bv, be, bv2, be2);
+                    const double lv = s > 0 ? fv : bv2, le = s > 0 ? fe : be2;
+                    const double hv = s > 0 ? bv2 : fv, hev = s > 0 ? be2 : fe;
+                    const int m = max((int)rintf(wf), 0);
+                    const double2 cs = A.half_sector[2 * m + 64];  // rotate the low end by m pi / 32
+                    const double rv = cs.x * lv - cs.y * le, re = cs.y * lv + cs.x * le;
+                    w = (rv * hev - re * hv <= 0.0) ? m : m + 1;
+                }
             }
         }
         a = min(kf, kb);
@@ -299,7 +314,7 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
     const uint32_t fresh = m & ~B;
     if (fresh) {
         // indirect light from the newly covered sectors (Algorithm 1; Section 3.3)
-        const float3 nj = load3<(FMT & 1) != 0>(A.normal, A.normal_pitch, A.normal_ch, X, Y);
+        const float3 nj = load3<FMT < 0 ? -1 : (FMT & 1)>(A.normal, A.normal_pitch, A.normal_ch, A.normal_f16, X, Y);
         const float hs = s > 0 ? h : -h;
         const float ndp = fmaf(S.nv, c, S.ne * hs);
         const float njv = nj.x * vx + nj.y * vy + nj.z * vz;
@@ -308,7 +323,8 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
         const float w = (float)__popc(fresh) * (1.0f / 32.0f) * fmaxf(ndp, 0.0f) * fmaxf(-ndj, 0.0f) *
                         __builtin_amdgcn_rcpf(fmaf(c, c, h * h));
         if (w > 0.0f) {
-            const float3 cj = load3<(FMT & 2) != 0>(A.radiance, A.radiance_pitch, A.radiance_ch, X, Y);
+            const float3 cj = load3<FMT < 0 ? -1 : (FMT >> 1)>(A.radiance, A.radiance_pitch, A.radiance_ch,
+                                                              A.radiance_f16, X, Y);
             gir = fmaf(w, cj.x, gir);
             gig = fmaf(w, cj.y, gig);
             gib = fmaf(w, cj.z, gib);
@@ -326,18 +342,21 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
 // covers sectors at or above the direction v and the - side only sectors below it, so
 // the two never compete for a sector and the interleaving leaves every mask, and every
 // newly covered count, as a side-by-side march would produce it.
+//  li/lp  this lane's index among the lp lanes that share the pixel (adjacent lanes, lp a
+//         power of two); lane li takes slices li, li + lp, ...
 template <int CRIT, int MODE, bool TINF, int FMT>
-__device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int32_t* dbg_i,
-                                             float* dbg_f) {
+__device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int li, int lp,
+                                             int32_t* dbg_i, float* dbg_f) {
     const int t = (int)threadIdx.x;
     const float zp = *(const float*)((const char*)A.depth + depth_off(A, x, y));
     const bool geom = is_geometry(zp);
     if (MODE == MODE_COMPUTE && !geom) {
-        store_background(A, x, y);
+        store_background(A, x, y, li);
         return;
     }
     const float3 n = MODE == MODE_LATTICE ? make_float3(0.0f, 0.0f, 1.0f)
-                                          : load3<(FMT & 1) != 0>(A.normal, A.normal_pitch, A.normal_ch, x, y);
+                                          : load3<FMT < 0 ? -1 : (FMT & 1)>(A.normal, A.normal_pitch, A.normal_ch,
+                                                                            A.normal_f16, x, y);
     const uint32_t rho = rotation16(A, x, y);
 
     // step length in 1/16 px: floor(C / z_p) from one IEEE FP32 division, clamped
@@ -366,7 +385,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
     const int x16 = (x << 16) + 32768, y16 = (y << 16) + 32768;
     const uint32_t own = depth_off(A, x, y);
 
-    for (int i = 0; i < A.nd; ++i) {
+    for (int i = li; i < A.nd; i += lp) {
         const int k = (int)(((uint32_t)i * 65536u + rho) / (uint32_t)(16 * A.nd));
         const int2 D = A.lut[k];
         const int jit = (q * (int)jitter8(A, x, y, i)) >> 8;
@@ -426,8 +445,9 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
                         const float yb = fminf(fmaxf(fmaf(ab, sk, S.K), 0.5f), 32.5f);
                         const float lo = fminf(yf, yb), hi = fmaxf(yf, yb);
                         float* d = dbg_f + ((((int64_t)i * 2 + side) * A.ns + j) * 2);
-                        d[0] = CRIT == SSVB_HIT_ROUND ? lo : lo - 0.5f;
-                        d[1] = CRIT == SSVB_HIT_ROUND ? hi : hi - lo;
+                        const bool round = CRIT < 0 ? A.criterion == SSVB_HIT_ROUND : CRIT == SSVB_HIT_ROUND;
+                        d[0] = round ? lo : lo - 0.5f;
+                        d[1] = round ? hi : hi - lo;
                     } else {
                         march_sample<CRIT, TINF, FMT>(A, S, L, t, zp, R, vx, vy, vz, tp, s, o, X, Y, ok,
                                                       zs[u][side], B, gir, gig, gib);
@@ -473,6 +493,17 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
         }
     }
     if (MODE != MODE_COMPUTE) return;
+    // sum the lanes of the pixel (butterfly: every lane ends with the same value)
+    for (int off = 1; off < lp; off <<= 1) {
+        ao_acc += __shfl_xor(ao_acc, off);
+        gir += __shfl_xor(gir, off);
+        gig += __shfl_xor(gig, off);
+        gib += __shfl_xor(gib, off);
+        amr += __shfl_xor(amr, off);
+        amg += __shfl_xor(amg, off);
+        amb += __shfl_xor(amb, off);
+    }
+    if (li != 0) return;
     const float inv_nd = 1.0f / (float)A.nd;
     *(float*)((char*)A.ao + (int64_t)y * A.ao_pitch + (int64_t)x * 4) = ao_acc * inv_nd;
     float* g = (float*)((char*)A.gi + (int64_t)y * A.gi_pitch) + 3 * (int64_t)x;
@@ -490,10 +521,11 @@ __global__ __launch_bounds__(kBlock) void gather_plain(FrameArgs A) {
     __shared__ ExactLds L;
     int tx, ty;
     if (!tile_of(A, blockIdx.x, tx, ty)) return;
-    const int x = tx * A.tile_w + (int)(threadIdx.x % (unsigned)A.tile_w);
-    const int y = ty * A.tile_h + (int)(threadIdx.x / (unsigned)A.tile_w);
+    const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
+    const int x = tx * A.tile_w + px % A.tile_w;
+    const int y = ty * A.tile_h + px / A.tile_w;
     if (x >= A.W || y >= A.H) return;
-    gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT>(A, L, x, y, nullptr, nullptr);
+    gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT>(A, L, x, y, li, lp, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(kBlock) void debug_lattice(FrameArgs A, int32_t* out) {
@@ -502,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void debug_lattice(FrameArgs A, int32_t* ou
     const int y = blockIdx.y * 16 + (int)(threadIdx.x / 16u);
     if (x >= A.W || y >= A.H) return;
     int32_t* d = out + ((int64_t)y * A.W + x) * (int64_t)A.nd * 2 * A.ns * 2;
-    gather_pixel<SSVB_HIT_ROUND, MODE_LATTICE, false, 0>(A, L, x, y, d, nullptr);
+    gather_pixel<SSVB_HIT_ROUND, MODE_LATTICE, false, 0>(A, L, x, y, 0, 1, d, nullptr);
 }
 
 template <int CRIT, int FMT>
@@ -512,19 +544,71 @@ __global__ __launch_bounds__(kBlock) void debug_endpoints(FrameArgs A, float* ou
     const int y = blockIdx.y * 16 + (int)(threadIdx.x / 16u);
     if (x >= A.W || y >= A.H) return;
     float* d = out + ((int64_t)y * A.W + x) * (int64_t)A.nd * 2 * A.ns * 2;
-    gather_pixel<CRIT, MODE_ENDPOINTS, false, FMT>(A, L, x, y, nullptr, d);
+    gather_pixel<CRIT, MODE_ENDPOINTS, false, FMT>(A, L, x, y, 0, 1, nullptr, d);
+}
+
+// Persistent kernel over a batch of frames.  Workgroup b runs on XCD b mod 8 and takes
+// tiles from that XCD's queue until it is empty; each frame's strip walk is split into 8
+// contiguous parts, one per XCD, so every XCD works on compact regions (its L2), and the
+// queues list expensive frames first so that the tail is short.  Criterion, element types
+// and thickness are taken per frame at run time.
+__global__ __launch_bounds__(kBlock) void gather_batch(const BatchDesc* __restrict__ D, uint32_t* __restrict__ queues) {
+    __shared__ ExactLds L;
+    __shared__ uint32_t s_item;
+    const int xcd = (int)(blockIdx.x % kXcds);
+    const uint32_t total = D->total[xcd];
+    const int nseg = D->n_seg[xcd];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&queues[xcd], 1u);
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (item >= total) break;
+        int lo = 0, hi = nseg - 1;  // last segment whose start <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (D->seg[xcd][mid].start <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchSegment sg = D->seg[xcd][lo];
+        const FrameArgs& A = D->frames[sg.frame];
+        int tx, ty;
+        walk_tile(A, sg.first + (item - sg.start), tx, ty);
+        const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
+        const int x = tx * A.tile_w + px % A.tile_w;
+        const int y = ty * A.tile_h + px / A.tile_w;
+        if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1>(A, L, x, y, li, lp, nullptr, nullptr);
+    }
+}
+
+__global__ void reset_queues(uint32_t* q) {
+    if (threadIdx.x < kXcds) q[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
+hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, int grid,
+                         hipStream_t s) {
+    hipError_t e = hipMemcpyAsync((void*)d_desc, h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_queues, dim3(1), dim3(64), 0, s, d_queues);
+    hipLaunchKernelGGL(gather_batch, dim3(grid), dim3(kBlock), 0, s, d_desc, d_queues);
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gather_batch, kBlock, 0) != hipSuccess || nb < 1) nb = 2;
+    return nb;
+}
 static dim3 grid16(const FrameArgs& A) { return dim3((A.W + 15) / 16, (A.H + 15) / 16); }
 
 template <int CRIT, bool TINF, int FMT>
 static void launch_main(const FrameArgs& A, hipStream_t stream) {
     const uint32_t nt = (uint32_t)A.tiles_x * A.tiles_y;
     const uint32_t nwg = A.xcd_remap ? kXcds * ((nt + kXcds - 1) / kXcds) : nt;
-    hipLaunchKernelGGL((gather_plain<CRIT, TINF, FMT>), dim3(nwg), dim3(A.tile_w * A.tile_h), 0, stream, A);
+    hipLaunchKernelGGL((gather_plain<CRIT, TINF, FMT>), dim3(nwg), dim3(kBlock), 0, stream, A);
 }
 
 template <int CRIT, bool TINF>
