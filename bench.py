@@ -35,6 +35,28 @@ def algorithmic_bytes(W, H, nd, ns, fp16):
     return samples, samples * per_sample + px * per_px
 
 
+def device_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ssvb_kernels.hip", "ssvb_internal.h"):
+        with open(os.path.join(ROOT, "paper_2301_11376_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+    (scaled by the copy calibration), or None when the device code has changed since."""
+    path = os.path.join(ROOT, "profiles", f"gather_plain_{workload_name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("device_source_sha256") != device_source_sha256() or rec.get("workload") != workload_name:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(gb, cam, kw):
     """The FP64 oracle, as it stands, on a 128-row band of the frame (single process)."""
     import oracle as O
@@ -138,7 +160,7 @@ def main():
         "kernel_ms": {"mean": kernel_ms, "p50": float(np.percentile(per_launch_ms, 50)),
                       "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload), "traffic_unit": "B per launch",
                      "algorithmic_bytes_per_launch": abytes},
     }
     if not args.no_cpu_baseline:
