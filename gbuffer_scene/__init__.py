@@ -19,6 +19,12 @@ from .procedural import (
     crease_gbuffer,
     workload,
     WORKLOADS,
+    mixed_batch,
+    request_stream,
+    render_pool,
+    as_format,
+    BATCH_RESOLUTIONS,
+    SERVE_RESOLUTIONS,
 )
 
 __all__ = [
@@ -31,4 +37,10 @@ __all__ = [
     "crease_gbuffer",
     "workload",
     "WORKLOADS",
+    "mixed_batch",
+    "request_stream",
+    "render_pool",
+    "as_format",
+    "BATCH_RESOLUTIONS",
+    "SERVE_RESOLUTIONS",
 ]

@@ -347,3 +347,78 @@ def workload(name: str, channels: int = 3):
     if w["thickness"] is None:
         w["thickness"] = float(np.float32(np.random.default_rng(w["seed"]).uniform(0.1, 1.0)))
     return gb, cam, w, scene
+
+
+# ----------------------------------------------------------------------------------------
+# mixed-resolution batches and request streams
+# ----------------------------------------------------------------------------------------
+
+BATCH_RESOLUTIONS = [(1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
+SERVE_RESOLUTIONS = [(960, 540), (1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
+POOL_SEED0 = 100  # scene seeds of the frame pools: 100, 101, ...
+
+
+def mixed_batch(seed: int = 4, n_frames: int = 64, pool: int = 4):
+    """Draws of a batch of mixed frames: resolution uniform over BATCH_RESOLUTIONS,
+    slices uniform over {2, 4, 8}, steps over {8, 16, 32}, FP32 G-buffers, the scene
+    one of ``pool`` seeds per resolution, noise seed = frame index; radius 3, t 0.5, R2."""
+    rng = np.random.default_rng(seed)
+    frames = []
+    for i in range(n_frames):
+        W, H = BATCH_RESOLUTIONS[int(rng.integers(len(BATCH_RESOLUTIONS)))]
+        nd = int(rng.choice([2, 4, 8]))
+        ns = int(rng.choice([8, 16, 32]))
+        sc = POOL_SEED0 + int(rng.integers(pool))
+        frames.append(dict(width=W, height=H, scene_seed=sc, slices=nd, steps=ns, noise_seed=i, fp16=False,
+                           radius=3.0, thickness=0.5, noise="r2"))
+    return frames
+
+
+def request_stream(seed: int = 5, n_requests: int = 2000, pool: int = 2):
+    """Draws of a served request stream: resolution uniform over SERVE_RESOLUTIONS, slices
+    uniform over 2..8, steps over {8, 16, 32}, FP16 or FP32 normals and radiance with
+    probability 1/2, scene one of ``pool`` seeds per resolution, noise seed = request
+    index, and a unit-rate exponential gap before each arrival (divide by the rate)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_requests):
+        W, H = SERVE_RESOLUTIONS[int(rng.integers(len(SERVE_RESOLUTIONS)))]
+        nd = int(rng.integers(2, 9))
+        ns = int(rng.choice([8, 16, 32]))
+        fp16 = bool(rng.integers(2))
+        sc = POOL_SEED0 + int(rng.integers(pool))
+        gap = float(rng.exponential(1.0))
+        reqs.append(dict(width=W, height=H, scene_seed=sc, slices=nd, steps=ns, noise_seed=i, fp16=fp16,
+                         radius=3.0, thickness=0.5, noise="r2", gap=gap))
+    return reqs
+
+
+def _render_one(key):
+    seed, W, H = key
+    render_gbuffer(make_scene(seed, 64, 32), make_camera(W, H), cache=True)
+    return key
+
+
+def render_pool(keys, workers: int = 8):
+    """Render (scene_seed, W, H) keys of the 64-box / 32-plane generator with the default
+    camera, in parallel through the file cache; returns key -> (FP32 G-buffer, scene).
+    Call it before the process touches a GPU (the workers are forked)."""
+    keys = sorted(set(keys))
+    if workers > 1 and len(keys) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, len(keys))) as p:
+            # largest first, so the 4K renders do not trail
+            list(p.imap_unordered(_render_one, sorted(keys, key=lambda k: -k[1] * k[2])))
+    out = {}
+    for seed, W, H in keys:
+        sc = make_scene(seed, 64, 32)
+        out[(seed, W, H)] = (render_gbuffer(sc, make_camera(W, H), cache=True), sc)
+    return out
+
+
+def as_format(gb, fp16: bool):
+    """The same G-buffer with normal and radiance cast to FP16 (round to nearest even)."""
+    if not fp16:
+        return gb
+    return {"depth": gb["depth"], "normal": gb["normal"].astype(np.float16),
+            "radiance": gb["radiance"].astype(np.float16)}

@@ -196,6 +196,72 @@ ssvb_status ssvb_get_launch(ssvb_ctx* ctx, const ssvb_camera* camera, const ssvb
 ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stream, ssvb_launch* best,
                           float* best_ms);
 
+/* ---------------------------------------------------------------------------------
+ * Request loop.  A server owns an arena of device memory (its HBM budget) and a
+ * scheduler thread.  Submitted frames wait in arrival order until their footprint fits
+ * in the arena:
+ *     W * H * (4 + normal bytes/px + radiance bytes/px + 28), each part 256-aligned
+ * (depth FP32, the normal and radiance buffers as given, AO + GI + ambient FP32).
+ * Admitted frames are copied into the arena on a copy stream and stay resident there
+ * until their result has been copied out.  As soon as one of the server's compute
+ * streams is idle, every admitted frame not yet started (at most 64) runs as one round
+ * of the persistent batch kernel, so frames that arrive while a round is on the device
+ * join the next one and rounds on different streams overlap.  Each frame's results are
+ * those ssvb_compute writes for it with the launch shape of its class.
+ * Ownership: the frame's input and output pointers (device memory, or host memory that
+ * should be pinned for the copies to be asynchronous) must stay valid, and the inputs
+ * unchanged, until the request has finished; the outputs are written before `done` is
+ * reported.  A server keeps the context's device tables and a snapshot of its launch
+ * shapes: the context must outlive it.  Server calls are thread-safe; one thread must
+ * not release a ticket another thread is waiting on.
+ * --------------------------------------------------------------------------------- */
+typedef struct ssvb_server ssvb_server;
+
+/* Counters of a server since its creation (current values where noted). */
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t rounds;                  /* rounds started */
+    uint64_t frames_in_rounds;        /* frames over all rounds */
+    uint64_t admitted_while_running;  /* frames admitted while a round was on the device */
+    uint64_t arena_bytes, arena_in_use, arena_peak; /* in_use: current */
+    int32_t queued;                   /* current: waiting for memory */
+    int32_t resident;                 /* current: in the arena */
+    int32_t running_rounds;           /* current */
+    int32_t max_running_rounds;       /* most rounds on the device at once */
+    int32_t max_round_frames;         /* largest round */
+    int32_t reserved;
+} ssvb_server_counters;
+
+/* Create a server on ctx's device with an arena of hbm_budget_bytes (allocated here;
+ * SSVB_ERR_OUT_OF_MEMORY if it cannot be) and `streams` compute streams (1..8, 0 = 2). */
+ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t streams, ssvb_server** out);
+
+/* Queue one frame (validated as by ssvb_compute; masks must be NULL) and return its
+ * ticket.  Never blocks on the device.  SSVB_ERR_OUT_OF_MEMORY if its footprint exceeds
+ * the whole arena; SSVB_ERR_BUSY if 2^20 tickets are unreleased or the server is being
+ * destroyed; SSVB_ERR_DEVICE after a device error stopped the server.  A frame with no
+ * pixels finishes at once. */
+ssvb_status ssvb_server_submit(ssvb_server* server, const ssvb_frame* frame, uint64_t* ticket);
+
+/* *done = 1 once the request's outputs are in the caller's buffers; *latency_ms (may be
+ * NULL) is then the time from submission to completion.  SSVB_ERR_NOT_FOUND for an
+ * unknown or released ticket; SSVB_ERR_DEVICE (with *done = 1) if it failed. */
+ssvb_status ssvb_server_poll(ssvb_server* server, uint64_t ticket, int32_t* done, double* latency_ms);
+
+/* Block until the request finishes or timeout_ms passes (negative: no limit); returns
+ * SSVB_ERR_TIMEOUT if it has not finished by then. */
+ssvb_status ssvb_server_wait(ssvb_server* server, uint64_t ticket, double timeout_ms, double* latency_ms);
+
+/* Forget a finished request (SSVB_ERR_BUSY if it has not finished). */
+ssvb_status ssvb_server_release(ssvb_server* server, uint64_t ticket);
+
+/* Copy the server's counters. */
+ssvb_status ssvb_server_stats(ssvb_server* server, ssvb_server_counters* out);
+
+/* Stop the server: requests not yet started are dropped, rounds on the device are waited
+ * for, then the arena, streams and thread are freed.  NULL is ignored. */
+ssvb_status ssvb_server_destroy(ssvb_server* server);
+
 /* Test hook: the integer step lattice of ssvb_compute.  xy_out (device, int32) receives,
  * for every pixel, slice, side (+ then -) and step, the sampled texel (X, Y), laid out
  * [H][W][N_d][2][N_s][2] densely.  Same validation of depth/camera/params. */

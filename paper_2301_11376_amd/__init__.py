@@ -9,6 +9,7 @@ from .binding import (  # noqa: F401
     Context,
     Params,
     SSVBError,
+    Server,
     HIT_ROUND,
     HIT_PSEUDOCODE,
     NOISE_HASH,

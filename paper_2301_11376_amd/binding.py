@@ -28,7 +28,8 @@ EXPORTED = [
     "ssvb_status_string", "ssvb_last_error", "ssvb_default_params", "ssvb_create", "ssvb_destroy",
     "ssvb_validate", "ssvb_compute", "ssvb_compute_batch", "ssvb_set_launch", "ssvb_get_launch",
     "ssvb_autotune", "ssvb_debug_lattice", "ssvb_debug_endpoints", "ssvb_debug_direction_table",
-    "ssvb_debug_noise_constants",
+    "ssvb_debug_noise_constants", "ssvb_server_create", "ssvb_server_submit", "ssvb_server_poll",
+    "ssvb_server_wait", "ssvb_server_release", "ssvb_server_stats", "ssvb_server_destroy",
 ]
 
 
@@ -68,6 +69,19 @@ class ssvb_launch(ctypes.Structure):
 
     def as_tuple(self):
         return (self.tile_w, self.tile_h, self.strip, self.lanes_per_pixel)
+
+
+class ssvb_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("rounds", ctypes.c_uint64), ("frames_in_rounds", ctypes.c_uint64),
+                ("admitted_while_running", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_in_use", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64), ("queued", ctypes.c_int32),
+                ("resident", ctypes.c_int32), ("running_rounds", ctypes.c_int32),
+                ("max_running_rounds", ctypes.c_int32), ("max_round_frames", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _LIB = None
@@ -115,6 +129,21 @@ def lib() -> ctypes.CDLL:
     L.ssvb_debug_direction_table.argtypes = [V, P(ctypes.c_int32)]
     L.ssvb_debug_noise_constants.restype = None
     L.ssvb_debug_noise_constants.argtypes = [P(ctypes.c_uint32)]
+    U64, D = ctypes.c_uint64, ctypes.c_double
+    L.ssvb_server_create.restype = I
+    L.ssvb_server_create.argtypes = [V, U64, I, P(V)]
+    L.ssvb_server_submit.restype = I
+    L.ssvb_server_submit.argtypes = [V, P(ssvb_frame), P(U64)]
+    L.ssvb_server_poll.restype = I
+    L.ssvb_server_poll.argtypes = [V, U64, P(I), P(D)]
+    L.ssvb_server_wait.restype = I
+    L.ssvb_server_wait.argtypes = [V, U64, D, P(D)]
+    L.ssvb_server_release.restype = I
+    L.ssvb_server_release.argtypes = [V, U64]
+    L.ssvb_server_stats.restype = I
+    L.ssvb_server_stats.argtypes = [V, P(ssvb_server_counters)]
+    L.ssvb_server_destroy.restype = I
+    L.ssvb_server_destroy.argtypes = [V]
     _LIB = L
     return L
 
@@ -326,6 +355,61 @@ class Context:
         buf = (ctypes.c_int32 * 8192)()
         check(lib().ssvb_debug_direction_table(self.handle, buf), "ssvb_debug_direction_table")
         return [(buf[2 * k], buf[2 * k + 1]) for k in range(4096)]
+
+
+class Server:
+    """An ssvb_server: admission by HBM footprint and continuous batching on `streams`
+    compute streams.  Tensors handed to submit (device, or pinned host) must stay alive
+    until the request has finished; this wrapper keeps a reference to them meanwhile."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, streams: int = 2):
+        h = ctypes.c_void_p()
+        check(lib().ssvb_server_create(ctx.handle, int(hbm_budget_bytes), int(streams), ctypes.byref(h)),
+              "ssvb_server_create")
+        self.handle = h
+        self.ctx = ctx
+        self._held = {}
+
+    def submit(self, depth, normal, radiance, camera: Camera, params: Params, out) -> int:
+        F = self.ctx.frame(depth, normal, radiance, camera, params, out)
+        t = ctypes.c_uint64()
+        check(lib().ssvb_server_submit(self.handle, ctypes.byref(F), ctypes.byref(t)), "ssvb_server_submit")
+        self._held[t.value] = (depth, normal, radiance, out)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, latency_ms or None)."""
+        done, lat = ctypes.c_int32(), ctypes.c_double()
+        check(lib().ssvb_server_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(lat)), "ssvb_server_poll")
+        return bool(done.value), (lat.value if done.value else None)
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> float:
+        """Block until the request finishes; returns its latency in ms."""
+        lat = ctypes.c_double()
+        check(lib().ssvb_server_wait(self.handle, ticket, float(timeout_ms), ctypes.byref(lat)), "ssvb_server_wait")
+        return lat.value
+
+    def release(self, ticket: int) -> None:
+        check(lib().ssvb_server_release(self.handle, ticket), "ssvb_server_release")
+        self._held.pop(ticket, None)
+
+    def stats(self) -> dict:
+        c = ssvb_server_counters()
+        check(lib().ssvb_server_stats(self.handle, ctypes.byref(c)), "ssvb_server_stats")
+        return c.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            st = lib().ssvb_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+            check(st, "ssvb_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def default_params() -> ssvb_params:

@@ -8,12 +8,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libssvb.so")
 
-SOURCES = ["ssvb_kernels.hip", "ssvb_api.cpp"]
+SOURCES = ["ssvb_kernels.hip", "ssvb_api.cpp", "ssvb_server.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions (v_pk_*_f32) anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", "-Wno-bitwise-instead-of-logical",
 ]
 
 

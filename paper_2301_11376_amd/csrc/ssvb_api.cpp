@@ -13,51 +13,30 @@
 #include <tuple>
 #include <vector>
 
-#include "ssvb_internal.h"
-
-namespace ssvb {
-hipError_t launch_plain(const FrameArgs& A, hipStream_t stream);
-hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream);
-hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t stream);
-hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, int grid,
-                         hipStream_t s);
-int batch_blocks_per_cu();
-}  // namespace ssvb
+#include "ssvb_host.h"
 
 using namespace ssvb;
-
-// frame class for tuned launch shapes: width, height, slices, steps, FP16 mask
-using ShapeKey = std::tuple<int, int, int, int, int>;
 
 constexpr int kBatchSlots = 2;  // descriptor slots of the batched path (double buffering)
 
 struct ssvb_ctx {
     int device = 0;
-    int2* d_lut = nullptr;      // slice directions
-    double2* d_half = nullptr;  // cos, sin of h pi / 64, h = -64..64
     int2 h_lut[kLutSize];
-    // launch shapes
-    bool forced = false;
-    LaunchShape force{32, 8, 4, 1};
-    std::map<ShapeKey, LaunchShape> tuned;
+    FrameTables tab;  // device tables and launch shapes
     std::string tune_cache;
-    // batched path: pinned + device descriptor tables, queue counters, captured graphs
+    // batched path
     bool batch_ready = false;
     int batch_grid = 0;
     hipStream_t cap_stream = nullptr;
-    BatchDesc* h_desc[kBatchSlots] = {};
-    BatchDesc* d_desc[kBatchSlots] = {};
-    uint32_t* d_queues[kBatchSlots] = {};
-    hipGraph_t graph[kBatchSlots] = {};
-    hipGraphExec_t exec[kBatchSlots] = {};
-    hipEvent_t done[kBatchSlots] = {};
-    bool pending[kBatchSlots] = {};
+    BatchSlot slot[kBatchSlots];
     uint64_t next_slot = 0;
 };
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace ssvb {
 
 ssvb_status fail(ssvb_status s, const char* fmt, ...) {
     char buf[512];
@@ -73,9 +52,16 @@ ssvb_status hip_fail(hipError_t e, const char* what) {
     return fail(SSVB_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-bool finite(float v) { return isfinite(v) != 0; }
+const std::string& last_error() { return g_last_error; }
 
-int64_t elem_size(int32_t dtype) { return dtype == SSVB_F16 ? 2 : 4; }
+int ctx_device(const ssvb_ctx* ctx) { return ctx->device; }
+const FrameTables* ctx_tables(const ssvb_ctx* ctx) { return &ctx->tab; }
+
+}  // namespace ssvb
+
+namespace {
+
+bool finite(float v) { return isfinite(v) != 0; }
 
 ssvb_status check_image(const ssvb_image* im, const char* name, int32_t W, int32_t H, bool is_depth) {
     if (!im) return fail(SSVB_ERR_INVALID_ARG, "%s: NULL image descriptor", name);
@@ -177,10 +163,10 @@ void set_launch(FrameArgs& A, LaunchShape L) {
 }
 }  // namespace ssvb
 
-namespace {
+namespace ssvb {
 
 // Fill the frame constants: FP64 derivation, one rounding to FP32.
-void fill_frame(FrameArgs& A, const ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
+void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, const ssvb_image* normal,
                 const ssvb_image* radiance, const ssvb_camera* cam, const ssvb_params* p, const ssvb_outputs* out) {
     memset(&A, 0, sizeof A);
     const int W = cam->width, H = cam->height;
@@ -245,93 +231,29 @@ void fill_frame(FrameArgs& A, const ssvb_ctx* ctx, const ssvb_image* depth, cons
         A.amb_cb[k] = (float)cos(beta);
         A.amb_sb[k] = (float)sin(beta);
     }
-    A.lut = ctx ? ctx->d_lut : nullptr;
-    A.half_sector = ctx ? ctx->d_half : nullptr;
+    A.lut = tab ? tab->d_lut : nullptr;
+    A.half_sector = tab ? tab->d_half : nullptr;
     LaunchShape shape{32, 8, 4, 1};
-    if (ctx) {
-        if (ctx->forced) {
-            shape = ctx->force;
+    if (tab) {
+        if (tab->forced) {
+            shape = tab->force;
         } else {
             const int fmt = (normal && normal->dtype == SSVB_F16 ? 1 : 0) | (radiance && radiance->dtype == SSVB_F16 ? 2 : 0);
-            auto it = ctx->tuned.find(ShapeKey{W, H, p->slices, p->steps, fmt});
-            if (it != ctx->tuned.end()) shape = it->second;
+            auto it = tab->tuned.find(ShapeKey{W, H, p->slices, p->steps, fmt});
+            if (it != tab->tuned.end()) shape = it->second;
         }
     }
     set_launch(A, shape);
 }
 
-bool valid_shape(const ssvb_launch* L) {
-    if (!L) return false;
-    const int lp = L->lanes_per_pixel;
-    return (lp == 1 || lp == 2 || lp == 4 || lp == 8) && L->tile_w > 0 && L->tile_h > 0 &&
-           L->tile_w * L->tile_h * lp == 256 && L->strip > 0;
-}
-
-void load_tune_cache(ssvb_ctx* ctx) {
-    const char* path = getenv("SSVB_TUNE_CACHE");
-    if (!path || !*path) return;
-    ctx->tune_cache = path;
-    FILE* f = fopen(path, "r");
-    if (!f) return;
-    int W, H, nd, ns, fmt, tw, th, st, lp;
-    float ms;
-    while (fscanf(f, "%d %d %d %d %d %d %d %d %d %f", &W, &H, &nd, &ns, &fmt, &tw, &th, &st, &lp, &ms) == 10) {
-        ssvb_launch L{tw, th, st, lp};
-        if (valid_shape(&L)) ctx->tuned[ShapeKey{W, H, nd, ns, fmt}] = LaunchShape{tw, th, st, lp};
-    }
-    fclose(f);
-}
-
-ssvb_status init_batch(ssvb_ctx* ctx) {
-    if (ctx->batch_ready) return SSVB_OK;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-    const int per_cu = batch_blocks_per_cu();
-    ctx->batch_grid = ((prop.multiProcessorCount * per_cu + kXcds - 1) / kXcds) * kXcds;
-    e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
-    for (int k = 0; k < kBatchSlots && e == hipSuccess; ++k) {
-        e = hipHostMalloc((void**)&ctx->h_desc[k], sizeof(BatchDesc), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_desc[k], sizeof(BatchDesc));
-        if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_queues[k], 64 * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->done[k], hipEventDisableTiming);
-        if (e != hipSuccess) break;
-        memset(ctx->h_desc[k], 0, sizeof(BatchDesc));
-        // one graph per slot: descriptor upload, queue reset, persistent kernel
-        e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) break;
-        hipError_t ce = capture_batch(ctx->d_desc[k], ctx->h_desc[k], ctx->d_queues[k], ctx->batch_grid,
-                                      ctx->cap_stream);
-        e = hipStreamEndCapture(ctx->cap_stream, &ctx->graph[k]);
-        if (ce != hipSuccess) e = ce;
-        if (e == hipSuccess) e = hipGraphInstantiate(&ctx->exec[k], ctx->graph[k], nullptr, nullptr, 0);
-    }
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(SSVB_ERR_OUT_OF_MEMORY, "batch buffers")
-                                                          : hip_fail(e, "batch set-up");
-    ctx->batch_ready = true;
-    return SSVB_OK;
-}
-
-void free_batch(ssvb_ctx* ctx) {
-    for (int k = 0; k < kBatchSlots; ++k) {
-        if (ctx->exec[k]) hipGraphExecDestroy(ctx->exec[k]);
-        if (ctx->graph[k]) hipGraphDestroy(ctx->graph[k]);
-        if (ctx->done[k]) hipEventDestroy(ctx->done[k]);
-        if (ctx->d_queues[k]) hipFree(ctx->d_queues[k]);
-        if (ctx->d_desc[k]) hipFree(ctx->d_desc[k]);
-        if (ctx->h_desc[k]) hipHostFree(ctx->h_desc[k]);
-    }
-    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-}
-
 // Build one descriptor table: frame constants and, per XCD, the cost-ordered segments.
-void build_batch(ssvb_ctx* ctx, BatchDesc* D, const ssvb_frame* frames, int n) {
+void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames, int n) {
     D->n_frames = n;
     std::vector<int> order(n);
     std::vector<double> cost(n);
     for (int f = 0; f < n; ++f) {
         const ssvb_frame& F = frames[f];
-        fill_frame(D->frames[f], ctx, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
+        fill_frame(D->frames[f], tab, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
         order[f] = f;
         // work of one tile: its pixels times the samples of a pixel
         const FrameArgs& A = D->frames[f];
@@ -354,6 +276,85 @@ void build_batch(ssvb_ctx* ctx, BatchDesc* D, const ssvb_frame* frames, int n) {
         D->n_seg[k] = ns;
         D->total[k] = start;
     }
+}
+
+hipError_t batch_grid_size(int device, int* grid) {
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return e;
+    const int per_cu = batch_blocks_per_cu();
+    *grid = ((prop.multiProcessorCount * per_cu + kXcds - 1) / kXcds) * kXcds;
+    return hipSuccess;
+}
+
+hipError_t init_slot(BatchSlot& s, int grid, hipStream_t cap_stream) {
+    hipError_t e = hipHostMalloc((void**)&s.h_desc, sizeof(BatchDesc), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&s.d_desc, sizeof(BatchDesc));
+    if (e == hipSuccess) e = hipMalloc((void**)&s.d_queues, 64 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    memset(s.h_desc, 0, sizeof(BatchDesc));
+    e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t ce = capture_batch(s.d_desc, s.h_desc, s.d_queues, grid, cap_stream);
+    e = hipStreamEndCapture(cap_stream, &s.graph);
+    if (ce != hipSuccess) e = ce;
+    if (e == hipSuccess) e = hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0);
+    return e;
+}
+
+void free_slot(BatchSlot& s) {
+    if (s.exec) hipGraphExecDestroy(s.exec);
+    if (s.graph) hipGraphDestroy(s.graph);
+    if (s.done) hipEventDestroy(s.done);
+    if (s.d_queues) hipFree(s.d_queues);
+    if (s.d_desc) hipFree(s.d_desc);
+    if (s.h_desc) hipHostFree(s.h_desc);
+    s = BatchSlot{};
+}
+
+}  // namespace ssvb
+
+namespace {
+
+bool valid_shape(const ssvb_launch* L) {
+    if (!L) return false;
+    const int lp = L->lanes_per_pixel;
+    return (lp == 1 || lp == 2 || lp == 4 || lp == 8) && L->tile_w > 0 && L->tile_h > 0 &&
+           L->tile_w * L->tile_h * lp == 256 && L->strip > 0;
+}
+
+void load_tune_cache(ssvb_ctx* ctx) {
+    const char* path = getenv("SSVB_TUNE_CACHE");
+    if (!path || !*path) return;
+    ctx->tune_cache = path;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    int W, H, nd, ns, fmt, tw, th, st, lp;
+    float ms;
+    while (fscanf(f, "%d %d %d %d %d %d %d %d %d %f", &W, &H, &nd, &ns, &fmt, &tw, &th, &st, &lp, &ms) == 10) {
+        ssvb_launch L{tw, th, st, lp};
+        if (valid_shape(&L)) ctx->tab.tuned[ShapeKey{W, H, nd, ns, fmt}] = LaunchShape{tw, th, st, lp};
+    }
+    fclose(f);
+}
+
+ssvb_status init_batch(ssvb_ctx* ctx) {
+    if (ctx->batch_ready) return SSVB_OK;
+    hipError_t e = batch_grid_size(ctx->device, &ctx->batch_grid);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    for (int k = 0; k < kBatchSlots && e == hipSuccess; ++k) e = init_slot(ctx->slot[k], ctx->batch_grid, ctx->cap_stream);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(SSVB_ERR_OUT_OF_MEMORY, "batch buffers")
+                                                          : hip_fail(e, "batch set-up");
+    ctx->batch_ready = true;
+    return SSVB_OK;
+}
+
+void free_batch(ssvb_ctx* ctx) {
+    for (int k = 0; k < kBatchSlots; ++k) free_slot(ctx->slot[k]);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    ctx->cap_stream = nullptr;
+    ctx->batch_ready = false;
 }
 
 }  // namespace
@@ -416,14 +417,14 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
     load_tune_cache(ctx);
     double2 half[129];
     for (int h = -64; h <= 64; ++h) half[h + 64] = make_double2(cos(M_PI * h / 64.0), sin(M_PI * h / 64.0));
-    e = hipMalloc((void**)&ctx->d_lut, sizeof ctx->h_lut);
-    if (e == hipSuccess) e = hipMemcpy(ctx->d_lut, ctx->h_lut, sizeof ctx->h_lut, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_half, sizeof half);
-    if (e == hipSuccess) e = hipMemcpy(ctx->d_half, half, sizeof half, hipMemcpyHostToDevice);
+    e = hipMalloc((void**)&ctx->tab.d_lut, sizeof ctx->h_lut);
+    if (e == hipSuccess) e = hipMemcpy(ctx->tab.d_lut, ctx->h_lut, sizeof ctx->h_lut, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->tab.d_half, sizeof half);
+    if (e == hipSuccess) e = hipMemcpy(ctx->tab.d_half, half, sizeof half, hipMemcpyHostToDevice);
     hipSetDevice(prev);
     if (e != hipSuccess) {
-        if (ctx->d_lut) hipFree(ctx->d_lut);
-        if (ctx->d_half) hipFree(ctx->d_half);
+        if (ctx->tab.d_lut) hipFree(ctx->tab.d_lut);
+        if (ctx->tab.d_half) hipFree(ctx->tab.d_half);
         delete ctx;
         return e == hipErrorOutOfMemory ? fail(SSVB_ERR_OUT_OF_MEMORY, "direction table") : hip_fail(e, "direction table");
     }
@@ -437,8 +438,8 @@ ssvb_status ssvb_destroy(ssvb_ctx* ctx) {
     hipGetDevice(&prev);
     hipSetDevice(ctx->device);
     free_batch(ctx);
-    if (ctx->d_lut) hipFree(ctx->d_lut);
-    if (ctx->d_half) hipFree(ctx->d_half);
+    if (ctx->tab.d_lut) hipFree(ctx->tab.d_lut);
+    if (ctx->tab.d_half) hipFree(ctx->tab.d_half);
     hipSetDevice(prev);
     delete ctx;
     return SSVB_OK;
@@ -473,7 +474,7 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     if (s) return s;
     if ((int64_t)camera->width * camera->height == 0) return SSVB_OK;
     FrameArgs A;
-    fill_frame(A, ctx, depth, normal, radiance, camera, params, out);
+    fill_frame(A, &ctx->tab, depth, normal, radiance, camera, params, out);
     int prev = 0;
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
@@ -489,7 +490,7 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
     for (int f = 0; f < n; ++f) {
         const ssvb_frame& F = frames[f];
         ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
-        if (s) return fail(s, "frame %d: %s", f, g_last_error.c_str());
+        if (s) return fail(s, "frame %d: %s", f, last_error().c_str());
     }
     int prev = 0;
     hipGetDevice(&prev);
@@ -502,16 +503,16 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
         for (int f = f0; f < std::min(n, f0 + kMaxBatch); ++f)
             if ((int64_t)frames[f].camera.width * frames[f].camera.height > 0) chunk.push_back(frames[f]);
         if (chunk.empty()) continue;
-        const int slot = (int)(ctx->next_slot++ % kBatchSlots);
+        BatchSlot& S = ctx->slot[ctx->next_slot++ % kBatchSlots];
         hipError_t e = hipSuccess;
-        if (ctx->pending[slot]) e = hipEventSynchronize(ctx->done[slot]);  // the slot's last upload is done
+        if (S.pending) e = hipEventSynchronize(S.done);  // the slot's last upload is done
         if (e == hipSuccess) {
-            build_batch(ctx, ctx->h_desc[slot], chunk.data(), (int)chunk.size());
-            e = hipGraphLaunch(ctx->exec[slot], stream);
+            build_batch(&ctx->tab, S.h_desc, chunk.data(), (int)chunk.size());
+            e = hipGraphLaunch(S.exec, stream);
         }
-        if (e == hipSuccess) e = hipEventRecord(ctx->done[slot], stream);
+        if (e == hipSuccess) e = hipEventRecord(S.done, stream);
         if (e != hipSuccess) st = hip_fail(e, "batch launch");
-        else ctx->pending[slot] = true;
+        else S.pending = true;
     }
     if (prev != ctx->device) hipSetDevice(prev);
     return st;
@@ -520,12 +521,12 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
 ssvb_status ssvb_set_launch(ssvb_ctx* ctx, const ssvb_launch* shape) {
     if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
     if (!shape) {
-        ctx->forced = false;
+        ctx->tab.forced = false;
         return SSVB_OK;
     }
     if (!valid_shape(shape)) return fail(SSVB_ERR_INVALID_ARG, "launch shape needs tile_w*tile_h*lanes = 256, lanes 1/2/4/8, strip > 0");
-    ctx->forced = true;
-    ctx->force = LaunchShape{shape->tile_w, shape->tile_h, shape->strip, shape->lanes_per_pixel};
+    ctx->tab.forced = true;
+    ctx->tab.force = LaunchShape{shape->tile_w, shape->tile_h, shape->strip, shape->lanes_per_pixel};
     return SSVB_OK;
 }
 
@@ -536,7 +537,7 @@ ssvb_status ssvb_get_launch(ssvb_ctx* ctx, const ssvb_camera* camera, const ssvb
     ssvb_image r{nullptr, 0, (fp16_mask & 2) ? SSVB_F16 : SSVB_F32, 3};
     ssvb_image d{nullptr, 0, SSVB_F32, 1};
     FrameArgs A;
-    fill_frame(A, ctx, &d, &n, &r, camera, params, nullptr);
+    fill_frame(A, &ctx->tab, &d, &n, &r, camera, params, nullptr);
     *out = ssvb_launch{A.tile_w, A.tile_h, A.strip, A.lp};
     return SSVB_OK;
 }
@@ -554,8 +555,8 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
     int prev = 0;
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
-    const bool was_forced = ctx->forced;
-    const LaunchShape was = ctx->force;
+    const bool was_forced = ctx->tab.forced;
+    const LaunchShape was = ctx->tab.force;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -564,8 +565,8 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
     for (const auto& tl : kTiles) {
         for (int st : kStrips) {
             if (e != hipSuccess) break;
-            ctx->forced = true;
-            ctx->force = LaunchShape{tl[0], tl[1], st, tl[2]};
+            ctx->tab.forced = true;
+            ctx->tab.force = LaunchShape{tl[0], tl[1], st, tl[2]};
             float times[3];
             for (int rep = -1; rep < 3 && e == hipSuccess; ++rep) {
                 e = hipEventRecord(e0, stream);
@@ -580,18 +581,18 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
             std::sort(times, times + 3);
             if (times[1] < best_t) {
                 best_t = times[1];
-                best_s = ctx->force;
+                best_s = ctx->tab.force;
             }
         }
     }
-    ctx->forced = was_forced;
-    ctx->force = was;
+    ctx->tab.forced = was_forced;
+    ctx->tab.force = was;
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) return s != SSVB_OK ? s : hip_fail(e, "autotune");
     const int fmt = (F.normal.dtype == SSVB_F16 ? 1 : 0) | (F.radiance.dtype == SSVB_F16 ? 2 : 0);
-    ctx->tuned[ShapeKey{F.camera.width, F.camera.height, F.params.slices, F.params.steps, fmt}] = best_s;
+    ctx->tab.tuned[ShapeKey{F.camera.width, F.camera.height, F.params.slices, F.params.steps, fmt}] = best_s;
     if (!ctx->tune_cache.empty()) {
         if (FILE* f = fopen(ctx->tune_cache.c_str(), "a")) {
             fprintf(f, "%d %d %d %d %d %d %d %d %d %.4f\n", F.camera.width, F.camera.height, F.params.slices,
@@ -613,7 +614,7 @@ ssvb_status ssvb_debug_lattice(ssvb_ctx* ctx, const ssvb_image* depth, const ssv
     if ((int64_t)camera->width * camera->height == 0) return SSVB_OK;
     if (!xy_out) return fail(SSVB_ERR_INVALID_ARG, "NULL lattice output");
     FrameArgs A;
-    fill_frame(A, ctx, depth, nullptr, nullptr, camera, params, nullptr);
+    fill_frame(A, &ctx->tab, depth, nullptr, nullptr, camera, params, nullptr);
     hipError_t e = launch_debug_lattice(A, xy_out, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "lattice launch");
     return SSVB_OK;
@@ -631,7 +632,7 @@ ssvb_status ssvb_debug_endpoints(ssvb_ctx* ctx, const ssvb_image* depth, const s
     if ((int64_t)W * H == 0) return SSVB_OK;
     if (!ep_out) return fail(SSVB_ERR_INVALID_ARG, "NULL endpoint output");
     FrameArgs A;
-    fill_frame(A, ctx, depth, normal, nullptr, camera, params, nullptr);
+    fill_frame(A, &ctx->tab, depth, normal, nullptr, camera, params, nullptr);
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t bytes = (size_t)W * H * params->slices * 2 * params->steps * 2 * sizeof(float);
     hipError_t e = hipMemsetAsync(ep_out, 0xFF, bytes, st);  // all-ones = NaN for skipped samples
@@ -643,7 +644,7 @@ ssvb_status ssvb_debug_endpoints(ssvb_ctx* ctx, const ssvb_image* depth, const s
 ssvb_status ssvb_debug_direction_table(ssvb_ctx* ctx, int32_t* host_out) {
     if (!ctx || !host_out) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
     int2 tmp[kLutSize];
-    hipError_t e = hipMemcpy(tmp, ctx->d_lut, sizeof tmp, hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(tmp, ctx->tab.d_lut, sizeof tmp, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "direction table copy");
     for (int k = 0; k < kLutSize; ++k) {
         host_out[2 * k] = tmp[k].x;

@@ -1,0 +1,76 @@
+// Host-side pieces shared by the C ABI (ssvb_api.cpp) and the request loop
+// (ssvb_server.cpp): frame constants, launch-shape tables, batch descriptor slots,
+// launchers and error reporting.
+#ifndef SSVB_HOST_H
+#define SSVB_HOST_H
+
+#include <map>
+#include <string>
+#include <tuple>
+
+#include "ssvb_internal.h"
+
+namespace ssvb {
+
+// frame class for tuned launch shapes: width, height, slices, steps, FP16 mask
+using ShapeKey = std::tuple<int, int, int, int, int>;
+
+// What the frame constants need from a context: device tables and launch shapes.
+struct FrameTables {
+    int2* d_lut = nullptr;      // slice directions
+    double2* d_half = nullptr;  // cos, sin of h pi / 64, h = -64..64
+    bool forced = false;
+    LaunchShape force{32, 8, 4, 1};
+    std::map<ShapeKey, LaunchShape> tuned;
+};
+
+// One descriptor slot of the batched path: pinned + device descriptor table, per-XCD
+// queue counters and the captured graph (descriptor upload, queue reset, persistent
+// kernel) that replays it.
+struct BatchSlot {
+    BatchDesc* h_desc = nullptr;
+    BatchDesc* d_desc = nullptr;
+    uint32_t* d_queues = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+// Workgroups of the persistent batch kernel on `device`: resident blocks per CU times
+// CUs, rounded up to a multiple of the XCD count.
+hipError_t batch_grid_size(int device, int* grid);
+// Allocate a slot and capture its graph on `cap_stream`.
+hipError_t init_slot(BatchSlot& s, int grid, hipStream_t cap_stream);
+void free_slot(BatchSlot& s);
+
+// Frame constants (FP64 derivation, one rounding to FP32) and the launch shape from
+// `tab` (forced, tuned for the frame's class, else the default).
+void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, const ssvb_image* normal,
+                const ssvb_image* radiance, const ssvb_camera* cam, const ssvb_params* p, const ssvb_outputs* out);
+// Descriptor table of up to kMaxBatch non-empty frames: constants and, per XCD, the
+// frames' tiles in order of decreasing tile cost.
+void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames, int n);
+
+hipError_t launch_plain(const FrameArgs& A, hipStream_t stream);
+hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream);
+hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t stream);
+hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, int grid,
+                         hipStream_t s);
+int batch_blocks_per_cu();
+
+// The device and the frame tables of a context.
+int ctx_device(const ssvb_ctx* ctx);
+const FrameTables* ctx_tables(const ssvb_ctx* ctx);
+
+// Error reporting: the detail goes to the calling thread's last-error string.
+ssvb_status fail(ssvb_status s, const char* fmt, ...);
+ssvb_status hip_fail(hipError_t e, const char* what);
+const std::string& last_error();
+
+// Bytes per element of an ssvb_dtype.
+inline int64_t elem_size(int32_t dtype) { return dtype == SSVB_F16 ? 2 : 4; }
+
+}  // namespace ssvb
+
+#endif

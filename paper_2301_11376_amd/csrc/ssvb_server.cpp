@@ -1,0 +1,479 @@
+// Request loop of the visibility-bitmask gather: frames are admitted by their HBM
+// footprint into a device arena owned by the server (FIFO), their G-buffers are staged
+// into it on a copy stream, and admitted frames are run in rounds of up to 64 through
+// the persistent batch kernel on two or more compute streams, so that a round can start
+// while another is still on the device.  Results are copied back to the caller's
+// buffers and each request is stamped with its completion time.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ssvb_host.h"
+#include "ssvb_sched.h"
+
+using namespace ssvb;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr int kMaxStreams = 8;
+constexpr size_t kMaxLive = (size_t)1 << 20;  // tickets not yet released
+constexpr uint64_t kAlign = 256;
+
+enum State { QUEUED, RESIDENT, RUNNING, DONE, FAILED };
+
+// Arena layout of one request: the G-buffer as the caller gave it (dense rows) and the
+// three FP32 outputs; every part starts on a 256-byte boundary.
+struct Layout {
+    uint64_t depth, normal, radiance, ao, gi, amb, total;
+};
+
+uint64_t up(uint64_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+Layout layout_of(const ssvb_frame& F) {
+    const uint64_t px = (uint64_t)F.camera.width * (uint64_t)F.camera.height;
+    Layout L;
+    uint64_t o = 0;
+    L.depth = o;
+    o += up(px * 4);
+    L.normal = o;
+    o += up(px * F.normal.channels * elem_size(F.normal.dtype));
+    L.radiance = o;
+    o += up(px * F.radiance.channels * elem_size(F.radiance.dtype));
+    L.ao = o;
+    o += up(px * 4);
+    L.gi = o;
+    o += up(px * 12);
+    L.amb = o;
+    o += up(px * 12);
+    L.total = o;
+    return L;
+}
+
+struct Request {
+    ssvb_frame caller;  // the caller's buffers
+    ssvb_frame staged;  // the same frame in the arena
+    Layout lay;
+    int state = QUEUED;
+    ssvb_status err = SSVB_OK;
+    Clock::time_point t_submit, t_done;
+};
+
+struct Round {
+    bool busy = false;
+    std::vector<uint64_t> tickets;
+};
+
+bool terminal(int state) { return state == DONE || state == FAILED; }
+
+int64_t pitch_of(const ssvb_image& im, int W) {
+    return im.pitch_bytes ? im.pitch_bytes : (int64_t)W * im.channels * elem_size(im.dtype);
+}
+
+}  // namespace
+
+struct ssvb_server {
+    int device = 0;
+    FrameTables tab;  // the context's device tables and launch shapes, as at creation
+    char* arena = nullptr;
+    Admission adm;
+    int nstreams = 0;
+    int grid = 0;
+    hipStream_t copy_stream = nullptr, cap_stream = nullptr;
+    hipStream_t streams[kMaxStreams] = {};
+    BatchSlot slots[kMaxStreams];
+    Round rounds[kMaxStreams];
+    hipEvent_t staged = nullptr;  // recorded on copy_stream after each admission pass
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    hipError_t fatal = hipSuccess;  // first device error; every later request fails with it
+    std::string fatal_what;
+    std::unordered_map<uint64_t, Request> reqs;
+    uint64_t next_ticket = 1;
+    ssvb_server_counters st{};
+};
+
+namespace {
+
+hipError_t stage(ssvb_server* S, Request& r, uint64_t off) {
+    const ssvb_frame& F = r.caller;
+    const int W = F.camera.width, H = F.camera.height;
+    char* base = S->arena + off;
+    r.staged = F;
+    r.staged.depth.ptr = base + r.lay.depth;
+    r.staged.depth.pitch_bytes = 0;
+    r.staged.normal.ptr = base + r.lay.normal;
+    r.staged.normal.pitch_bytes = 0;
+    r.staged.radiance.ptr = base + r.lay.radiance;
+    r.staged.radiance.pitch_bytes = 0;
+    r.staged.out = ssvb_outputs{(float*)(base + r.lay.ao), (float*)(base + r.lay.gi), (float*)(base + r.lay.amb),
+                                nullptr, 0, 0, 0, 0};
+    const ssvb_image* src[3] = {&F.depth, &F.normal, &F.radiance};
+    const ssvb_image* dst[3] = {&r.staged.depth, &r.staged.normal, &r.staged.radiance};
+    for (int i = 0; i < 3; ++i) {
+        const size_t row = (size_t)W * src[i]->channels * elem_size(src[i]->dtype);
+        hipError_t e = hipMemcpy2DAsync((void*)dst[i]->ptr, row, src[i]->ptr, (size_t)pitch_of(*src[i], W), row,
+                                        (size_t)H, hipMemcpyDefault, S->copy_stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs) {
+    hipStream_t s = S->streams[k];
+    BatchSlot& B = S->slots[k];
+    std::vector<ssvb_frame> frames;
+    frames.reserve(rs.size());
+    for (const Request* r : rs) frames.push_back(r->staged);
+    // the slot's previous replay has completed (its round was retired), so its pinned
+    // descriptor table may be rewritten
+    build_batch(&S->tab, B.h_desc, frames.data(), (int)frames.size());
+    hipError_t e = hipStreamWaitEvent(s, S->staged, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(B.exec, s);
+    for (const Request* r : rs) {
+        if (e != hipSuccess) break;
+        const ssvb_frame& F = r->caller;
+        const int W = F.camera.width, H = F.camera.height;
+        struct {
+            void* dst;
+            int64_t pitch;
+            const void* src;
+            size_t row;
+        } c[3] = {{F.out.ao, F.out.ao_pitch_bytes, r->staged.out.ao, (size_t)W * 4},
+                  {F.out.gi, F.out.gi_pitch_bytes, r->staged.out.gi, (size_t)W * 12},
+                  {F.out.ambient, F.out.ambient_pitch_bytes, r->staged.out.ambient, (size_t)W * 12}};
+        for (int i = 0; i < 3 && e == hipSuccess; ++i)
+            e = hipMemcpy2DAsync(c[i].dst, c[i].pitch ? (size_t)c[i].pitch : c[i].row, c[i].src, c[i].row, c[i].row,
+                                 (size_t)H, hipMemcpyDefault, s);
+    }
+    if (e == hipSuccess) e = hipEventRecord(B.done, s);
+    return e;
+}
+
+void fail_request(ssvb_server* S, uint64_t t, Request& r, Clock::time_point now) {
+    r.state = FAILED;
+    r.err = SSVB_ERR_DEVICE;
+    r.t_done = now;
+    S->adm.finish(t);
+    S->st.failed++;
+}
+
+// The scheduler: retire finished rounds, admit from the queue while memory allows,
+// start a round on every idle stream.  HIP calls are made with the lock released; the
+// requests they touch are not erased meanwhile (release refuses unfinished tickets).
+void run(ssvb_server* S) {
+    hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        bool progress = false;
+        // 1. retire rounds whose completion event has fired
+        int busy[kMaxStreams], nbusy = 0;
+        for (int k = 0; k < S->nstreams; ++k)
+            if (S->rounds[k].busy) busy[nbusy++] = k;
+        hipError_t q[kMaxStreams];
+        if (nbusy) {
+            lk.unlock();
+            for (int i = 0; i < nbusy; ++i) q[i] = hipEventQuery(S->slots[busy[i]].done);
+            lk.lock();
+        }
+        const Clock::time_point now = Clock::now();
+        int running = 0;
+        for (int i = 0; i < nbusy; ++i) {
+            Round& R = S->rounds[busy[i]];
+            if (q[i] == hipErrorNotReady) {
+                ++running;
+                continue;
+            }
+            for (uint64_t t : R.tickets) {
+                Request& r = S->reqs[t];
+                if (q[i] != hipSuccess) {
+                    fail_request(S, t, r, now);
+                    continue;
+                }
+                r.state = DONE;
+                r.t_done = now;
+                S->adm.finish(t);
+                S->st.completed++;
+            }
+            if (q[i] != hipSuccess && S->fatal == hipSuccess) {
+                S->fatal = q[i];
+                S->fatal_what = "round";
+            }
+            R.tickets.clear();
+            R.busy = false;
+            progress = true;
+        }
+        if (progress) S->cv_done.notify_all();
+        if (S->stop) {
+            if (running == 0) break;
+            S->cv_work.wait_for(lk, std::chrono::microseconds(50));
+            continue;
+        }
+        // 2. admit in arrival order while the head fits; 3. one round per idle stream
+        std::vector<std::pair<uint64_t, uint64_t>> admitted;
+        std::vector<std::pair<int, std::vector<uint64_t>>> starts;
+        if (S->fatal == hipSuccess) {
+            S->adm.admit(admitted);
+            for (auto& a : admitted) {
+                S->reqs[a.first].state = RESIDENT;
+                if (running > 0) S->st.admitted_while_running++;
+            }
+            for (int k = 0; k < S->nstreams && S->adm.ready() > 0; ++k) {
+                if (S->rounds[k].busy) continue;
+                std::vector<uint64_t> tk;
+                S->adm.take_round(tk);
+                for (uint64_t t : tk) S->reqs[t].state = RUNNING;
+                S->rounds[k].busy = true;
+                S->rounds[k].tickets = tk;
+                S->st.rounds++;
+                S->st.frames_in_rounds += tk.size();
+                if ((int32_t)tk.size() > S->st.max_round_frames) S->st.max_round_frames = (int32_t)tk.size();
+                starts.push_back({k, std::move(tk)});
+                ++running;
+            }
+            if (running > S->st.max_running_rounds) S->st.max_running_rounds = running;
+        }
+        if (admitted.empty() && starts.empty()) {
+            if (running > 0) S->cv_work.wait_for(lk, std::chrono::microseconds(50));
+            else if (!progress) S->cv_work.wait(lk);
+            continue;
+        }
+        std::vector<Request*> adm_req;
+        for (auto& a : admitted) adm_req.push_back(&S->reqs[a.first]);
+        std::vector<std::vector<Request*>> round_req;
+        for (auto& s : starts) {
+            round_req.emplace_back();
+            for (uint64_t t : s.second) round_req.back().push_back(&S->reqs[t]);
+        }
+        lk.unlock();
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < admitted.size() && e == hipSuccess; ++i) e = stage(S, *adm_req[i], admitted[i].second);
+        if (!admitted.empty() && e == hipSuccess) e = hipEventRecord(S->staged, S->copy_stream);
+        const char* what = "staging";
+        for (size_t i = 0; i < starts.size() && e == hipSuccess; ++i) {
+            e = launch_round(S, starts[i].first, round_req[i]);
+            what = "round launch";
+        }
+        lk.lock();
+        if (e != hipSuccess) {
+            // a device error leaves the server unusable: fail everything not yet retired
+            if (S->fatal == hipSuccess) {
+                S->fatal = e;
+                S->fatal_what = what;
+            }
+            const Clock::time_point t_fail = Clock::now();
+            for (auto& s : starts) {
+                for (uint64_t t : s.second) fail_request(S, t, S->reqs[t], t_fail);
+                S->rounds[s.first].busy = false;
+                S->rounds[s.first].tickets.clear();
+            }
+            for (uint64_t t : S->adm.cancel_ready()) fail_request(S, t, S->reqs[t], t_fail);
+            for (uint64_t t : S->adm.cancel_queued()) {
+                Request& r = S->reqs[t];
+                r.state = FAILED;
+                r.err = SSVB_ERR_DEVICE;
+                r.t_done = t_fail;
+                S->st.failed++;
+            }
+            S->cv_done.notify_all();
+        }
+    }
+}
+
+ssvb_status fatal_status(const ssvb_server* S) {
+    return fail(SSVB_ERR_DEVICE, "server stopped after a device error (%s): %s", S->fatal_what.c_str(),
+                hipGetErrorString(S->fatal));
+}
+
+void destroy_resources(ssvb_server* S) {
+    for (int k = 0; k < kMaxStreams; ++k) {
+        free_slot(S->slots[k]);
+        if (S->streams[k]) hipStreamDestroy(S->streams[k]);
+    }
+    if (S->staged) hipEventDestroy(S->staged);
+    if (S->copy_stream) hipStreamDestroy(S->copy_stream);
+    if (S->cap_stream) hipStreamDestroy(S->cap_stream);
+    if (S->arena) hipFree(S->arena);
+}
+
+}  // namespace
+
+extern "C" {
+
+ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t streams, ssvb_server** out) {
+    if (!out) return fail(SSVB_ERR_INVALID_ARG, "NULL output handle");
+    *out = nullptr;
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    if (streams == 0) streams = 2;
+    if (streams < 1 || streams > kMaxStreams)
+        return fail(SSVB_ERR_INVALID_ARG, "streams %d outside [1, %d]", streams, kMaxStreams);
+    if (hbm_budget_bytes < kAlign) return fail(SSVB_ERR_INVALID_ARG, "HBM budget of %llu bytes is too small",
+                                               (unsigned long long)hbm_budget_bytes);
+    ssvb_server* S = new (std::nothrow) ssvb_server();
+    if (!S) return fail(SSVB_ERR_OUT_OF_MEMORY, "host allocation");
+    S->device = ctx_device(ctx);
+    S->tab = *ctx_tables(ctx);
+    S->nstreams = streams;
+    S->adm = Admission(hbm_budget_bytes, kMaxBatch, kAlign);
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(S->device);
+    hipError_t e = hipMalloc((void**)&S->arena, S->adm.arena().size());
+    const bool oom = e == hipErrorOutOfMemory;
+    if (e == hipSuccess) e = batch_grid_size(S->device, &S->grid);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->staged, hipEventDisableTiming);
+    for (int k = 0; k < streams && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&S->streams[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = init_slot(S->slots[k], S->grid, S->cap_stream);
+    }
+    // a round waits on `staged` even before anything was staged: record it once
+    if (e == hipSuccess) e = hipEventRecord(S->staged, S->copy_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->copy_stream);
+    if (e != hipSuccess) {
+        destroy_resources(S);
+        hipSetDevice(prev);
+        delete S;
+        return oom ? fail(SSVB_ERR_OUT_OF_MEMORY, "arena of %llu bytes", (unsigned long long)hbm_budget_bytes)
+                   : hip_fail(e, "server set-up");
+    }
+    hipSetDevice(prev);
+    S->st.arena_bytes = S->adm.arena().size();
+    try {
+        S->worker = std::thread(run, S);
+    } catch (...) {
+        destroy_resources(S);
+        delete S;
+        return fail(SSVB_ERR_OUT_OF_MEMORY, "scheduler thread");
+    }
+    *out = S;
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_server_submit(ssvb_server* S, const ssvb_frame* frame, uint64_t* ticket) {
+    if (!S || !frame || !ticket) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
+    const ssvb_frame& F = *frame;
+    ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
+    if (s) return s;
+    if (F.out.masks) return fail(SSVB_ERR_INVALID_ARG, "served requests do not return slice masks");
+    Request r;
+    r.caller = F;
+    r.lay = layout_of(F);
+    if (!S->adm.fits_at_all(r.lay.total))
+        return fail(SSVB_ERR_OUT_OF_MEMORY, "request footprint %llu bytes exceeds the %llu-byte arena",
+                    (unsigned long long)r.lay.total, (unsigned long long)S->adm.arena().size());
+    const bool empty = (int64_t)F.camera.width * F.camera.height == 0;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        if (S->fatal != hipSuccess) return fatal_status(S);
+        if (S->stop) return fail(SSVB_ERR_BUSY, "server is shutting down");
+        if (S->reqs.size() >= kMaxLive) return fail(SSVB_ERR_BUSY, "%zu requests not yet released", S->reqs.size());
+        const uint64_t t = S->next_ticket++;
+        r.t_submit = Clock::now();
+        if (empty) {
+            r.state = DONE;
+            r.t_done = r.t_submit;
+            S->st.completed++;
+        } else {
+            S->adm.submit(t, r.lay.total);
+        }
+        S->reqs.emplace(t, r);
+        S->st.submitted++;
+        *ticket = t;
+    }
+    S->cv_work.notify_one();
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_server_poll(ssvb_server* S, uint64_t ticket, int32_t* done, double* latency_ms) {
+    if (!S || !done) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(SSVB_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    const Request& r = it->second;
+    *done = terminal(r.state) ? 1 : 0;
+    if (latency_ms) *latency_ms = *done ? std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count() : 0.0;
+    if (r.state == FAILED) return fail(r.err, "request %llu failed on the device", (unsigned long long)ticket);
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_server_wait(ssvb_server* S, uint64_t ticket, double timeout_ms, double* latency_ms) {
+    if (!S) return fail(SSVB_ERR_INVALID_ARG, "NULL server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(SSVB_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = &it->second;
+    auto finished = [&] { return terminal(r->state); };
+    if (timeout_ms < 0) {
+        S->cv_done.wait(lk, finished);
+    } else if (!S->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), finished)) {
+        return fail(SSVB_ERR_TIMEOUT, "request %llu not finished after %.3f ms", (unsigned long long)ticket, timeout_ms);
+    }
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    if (r->state == FAILED) return fail(r->err, "request %llu failed on the device", (unsigned long long)ticket);
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_server_release(ssvb_server* S, uint64_t ticket) {
+    if (!S) return fail(SSVB_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(SSVB_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!terminal(it->second.state)) return fail(SSVB_ERR_BUSY, "request %llu has not finished", (unsigned long long)ticket);
+    S->reqs.erase(it);
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_server_stats(ssvb_server* S, ssvb_server_counters* out) {
+    if (!S || !out) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(S->mu);
+    *out = S->st;
+    out->arena_in_use = S->adm.arena().in_use();
+    out->arena_peak = S->adm.arena().peak();
+    out->queued = (int32_t)S->adm.queued();
+    out->resident = (int32_t)S->adm.resident();
+    int running = 0;
+    for (int k = 0; k < S->nstreams; ++k) running += S->rounds[k].busy;
+    out->running_rounds = running;
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_server_destroy(ssvb_server* S) {
+    if (!S) return SSVB_OK;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+        // requests not yet in a round are dropped; rounds on the device are waited for
+        for (uint64_t t : S->adm.cancel_ready()) S->reqs[t].state = FAILED;
+        for (uint64_t t : S->adm.cancel_queued()) S->reqs[t].state = FAILED;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(S->device);
+    hipError_t e = hipStreamSynchronize(S->copy_stream);  // staging of dropped requests
+    for (int k = 0; k < S->nstreams; ++k) {
+        const hipError_t e2 = hipStreamSynchronize(S->streams[k]);
+        if (e == hipSuccess) e = e2;
+    }
+    destroy_resources(S);
+    hipSetDevice(prev);
+    delete S;
+    if (e != hipSuccess) return hip_fail(e, "server shutdown");
+    return SSVB_OK;
+}
+
+}  // extern "C"
