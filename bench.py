@@ -1,12 +1,20 @@
 """Benchmark of the visibility-bitmask gather on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2_1080p]
+                [--no-batch] [--no-serve] [--no-autotune] [--serve-requests N]
+                [--serve-sweep] [--no-cpu-baseline]
 
 One step = one pass of the whole hot path (ssvb_compute: AO, GI and ambient of one
 frame) over a seeded synthetic 1920x1080 G-buffer already resident in HBM.  Prints one
 JSON line with Gsamples/s (a sample is one depth fetch of one pixel, slice, side and
-step: px * N_d * 2 * N_s per frame), ms per frame, the roofline of the gather kernel
-and the FP64 oracle timed on a bounded sample on the host cores.
+step: px * N_d * 2 * N_s per frame), ms per frame, the roofline of the gather kernel and
+the FP64 oracle timed on a bounded sample on the host cores.  Two more legs run the
+mixed-frame workloads: a batch of 64 frames of mixed resolution and sample counts (one
+graph launch against 64 plain launches) and a Poisson request stream through the
+request loop (p50 / p99 latency, frames/s).
+
+Everything the host renders or computes on the CPU (scene pools, the oracle) runs in
+forked worker processes before this process touches the GPU.
 """
 from __future__ import annotations
 
@@ -22,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+SERVE_BUDGET = 64 << 30  # HBM budget of the request loop
+HOST_WORKERS = 16  # CPU share of one GPU on the benchmark hosts
 
 
 def algorithmic_bytes(W, H, nd, ns, fp16):
@@ -33,6 +43,10 @@ def algorithmic_bytes(W, H, nd, ns, fp16):
     per_sample = 16 if fp16 else 28
     per_px = 38 if fp16 else 44
     return samples, samples * per_sample + px * per_px
+
+
+def samples_of(f):
+    return f["width"] * f["height"] * f["slices"] * 2 * f["steps"]
 
 
 def device_source_sha256():
@@ -47,7 +61,7 @@ def device_source_sha256():
 def measured_traffic(workload_name):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes
     (scaled by the copy calibration), or None when the device code has changed since."""
-    path = os.path.join(ROOT, "profiles", f"gather_plain_{workload_name}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"gather_frame_{workload_name}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -57,22 +71,268 @@ def measured_traffic(workload_name):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(gb, cam, kw):
-    """The FP64 oracle, as it stands, on a 128-row band of the frame (single process)."""
+# ---------------------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on row bands, one process per band
+# ---------------------------------------------------------------------------------------
+
+_CPU_JOB = None
+
+
+def _oracle_band(rows):
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    gb, oc, kw = _CPU_JOB
+    W = gb["depth"].shape[1]
+    ys = np.repeat(np.arange(rows[0], rows[1]), W)
+    xs = np.tile(np.arange(W), rows[1] - rows[0])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, O.Params(**kw), pixels=(ys, xs))
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(gb, cam, kw, rows_per_worker=48):
+    """The FP64 oracle on `workers` disjoint row bands of the frame, one forked process
+    (one thread) per band, timed end to end."""
+    global _CPU_JOB
+    import multiprocessing as mp
     import oracle as O
     H, W = gb["depth"].shape
-    rows = min(128, H)
-    y0 = (H - rows) // 2
-    ys = np.repeat(np.arange(y0, y0 + rows), W)
-    xs = np.tile(np.arange(W), rows)
+    workers = max(1, min(HOST_WORKERS, os.cpu_count() or 1, H // rows_per_worker))
+    y0 = (H - workers * rows_per_worker) // 2
+    bands = [(y0 + i * rows_per_worker, y0 + (i + 1) * rows_per_worker) for i in range(workers)]
     oc = O.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(cam.view_to_world))
+    _CPU_JOB = (gb, oc, kw)
     t0 = time.perf_counter()
-    O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, O.Params(**kw), pixels=(ys, xs))
-    dt = time.perf_counter() - t0
-    samples = len(ys) * kw["slices"] * 2 * kw["steps"]
-    return {"value": samples / dt / 1e9, "unit": "Gsamples/s", "cores": 1, "kind": "oracle",
-            "sample": f"rows {y0}..{y0 + rows - 1} of the same frame ({len(ys)} px, {samples} samples), "
-                      f"{dt:.1f} s single-threaded NumPy FP64"}
+    with mp.get_context("fork").Pool(workers) as p:
+        per = p.map(_oracle_band, bands)
+    wall = time.perf_counter() - t0
+    px = workers * rows_per_worker * W
+    samples = px * kw["slices"] * 2 * kw["steps"]
+    return {"value": samples / wall / 1e9, "unit": "Gsamples/s", "cores": workers, "kind": "oracle",
+            "sample": f"rows {bands[0][0]}..{bands[-1][1] - 1} of the same frame ({px} px, {samples} samples) "
+                      f"in {workers} bands of {rows_per_worker} rows, one single-threaded NumPy FP64 process "
+                      f"per band; {wall:.1f} s wall, {sum(per):.1f} s CPU",
+            "single_process_value": samples / sum(per) / 1e9}
+
+
+# ---------------------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------------------
+
+def to_params(Params, NOISE_NAMES, f, scene):
+    return Params(slices=f["slices"], steps=f["steps"], radius=f["radius"], thickness=f["thickness"],
+                  noise=NOISE_NAMES[f["noise"]], seed=f["noise_seed"],
+                  ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
+
+
+def camera_of(Camera, W, H):
+    from gbuffer_scene import make_camera
+    c = make_camera(W, H)
+    return Camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, tuple(c.view_to_world))
+
+
+def timed(fn, stream, reps):
+    """Median, min and all of `reps` HIP-event timings (ms) of fn() on `stream`."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts)), float(np.min(ts)), ts
+
+
+def batch_leg(ctx, pool, autotune):
+    """64 mixed frames: 64 plain launches on one stream against one graph launch of the
+    persistent batch kernel, both with the autotuned shape of each frame's class."""
+    import torch
+    from gbuffer_scene import mixed_batch
+    from paper_2301_11376_amd import Camera, Context, Params, NOISE_NAMES
+    frames = mixed_batch()
+    dev = torch.device("cuda:0")
+    base = {}
+    for f in frames:
+        k = (f["scene_seed"], f["width"], f["height"])
+        if k not in base:
+            gb, _ = pool[k]
+            base[k] = {n: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for n, v in gb.items()}
+    items_plain, items_batch = [], []
+    for f in frames:
+        k = (f["scene_seed"], f["width"], f["height"])
+        t = {n: v.clone() for n, v in base[k].items()}  # every frame its own G-buffer in HBM
+        cam = camera_of(Camera, f["width"], f["height"])
+        p = to_params(Params, NOISE_NAMES, f, pool[k][1])
+        oa = Context.alloc_outputs(f["height"], f["width"], f["slices"], dev)
+        ob = Context.alloc_outputs(f["height"], f["width"], f["slices"], dev)
+        items_plain.append((t["depth"], t["normal"], t["radiance"], cam, p, oa))
+        items_batch.append((t["depth"], t["normal"], t["radiance"], cam, p, ob))
+    del base
+    tuned = 0
+    if autotune:
+        seen = set()
+        for it in items_plain:
+            cls = (it[3].width, it[3].height, it[4].slices, it[4].steps)
+            if cls in seen:
+                continue
+            seen.add(cls)
+            ctx.autotune(*it)
+            tuned += 1
+        torch.cuda.synchronize()
+        print(f"autotuned {tuned} frame classes", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        for it in items_plain:
+            ctx.compute(*it[:5], out=it[5])
+
+    def batched():
+        ctx.compute_batch(items_batch)
+
+    plain(), batched()
+    torch.cuda.synchronize()
+    identical = all(torch.equal(a[5][n], b[5][n]) for a, b in zip(items_plain, items_batch)
+                    for n in ("ao", "gi", "ambient"))
+    p_med, p_min, _ = timed(plain, stream, 5)
+    b_med, b_min, _ = timed(batched, stream, 5)
+    samples = sum(samples_of(f) for f in frames)
+    res = {"workload": "64 frames, resolution uniform over 1280x720 / 1920x1080 / 2560x1440 / 3840x2160, "
+                       "slices {2,4,8}, steps {8,16,32}, FP32 G-buffers, radius 3, t 0.5, R2 noise, scenes from "
+                       "4 procedural seeds per resolution (64 boxes, 32 thin planes), draw seed 4",
+           "frames": len(frames), "samples": samples, "autotuned_classes": tuned,
+           "plain_ms": p_med, "plain_min_ms": p_min, "batched_ms": b_med, "batched_min_ms": b_min,
+           "speedup": p_med / b_med, "plain_gsamples_s": samples / p_med / 1e6,
+           "batched_gsamples_s": samples / b_med / 1e6, "bit_identical_to_plain": bool(identical)}
+    print(f"batch: plain {p_med:.2f} ms, batched {b_med:.2f} ms, x{p_med / b_med:.3f}, identical {identical}",
+          file=sys.stderr, flush=True)
+    del items_plain, items_batch
+    torch.cuda.empty_cache()
+    return res
+
+
+def serve_leg(ctx, pool, n_requests, rates):
+    """Poisson stream through the request loop; G-buffers device-resident in a pool, the
+    loop stages each request into its 64 GB arena and copies results to the request's
+    output buffers."""
+    import torch
+    from gbuffer_scene import request_stream, as_format
+    from paper_2301_11376_amd import Camera, Context, Params, Server, NOISE_NAMES
+    reqs = request_stream(n_requests=n_requests)
+    dev = torch.device("cuda:0")
+    gbs = {}
+    for r in reqs:
+        k = (r["scene_seed"], r["width"], r["height"], r["fp16"])
+        if k not in gbs:
+            gb = as_format(pool[k[:3]][0], r["fp16"])
+            gbs[k] = {n: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for n, v in gb.items()}
+    cams = {}
+    prm = []
+    for r in reqs:
+        if (r["width"], r["height"]) not in cams:
+            cams[(r["width"], r["height"])] = camera_of(Camera, r["width"], r["height"])
+        prm.append(to_params(Params, NOISE_NAMES, r, pool[(r["scene_seed"], r["width"], r["height"])][1]))
+    free_out = {}
+
+    def get_out(W, H):
+        lst = free_out.setdefault((W, H), [])
+        return lst.pop() if lst else Context.alloc_outputs(H, W, 1, dev)
+
+    def args(i):
+        r = reqs[i]
+        g = gbs[(r["scene_seed"], r["width"], r["height"], r["fp16"])]
+        return g, cams[(r["width"], r["height"])], prm[i]
+
+    # plain launches of the same mix, back to back on one stream (no staging)
+    stream = torch.cuda.current_stream()
+    n_sat = min(300, len(reqs))
+    plain_out = {}  # one output set per resolution: the launches are ordered on one stream
+    outs = [plain_out.setdefault((reqs[i]["width"], reqs[i]["height"]),
+                                 get_out(reqs[i]["width"], reqs[i]["height"])) for i in range(n_sat)]
+
+    def plain():
+        for i in range(n_sat):
+            g, c, p = args(i)
+            ctx.compute(g["depth"], g["normal"], g["radiance"], c, p, out=outs[i])
+    plain()
+    torch.cuda.synchronize()
+    t_plain, _, _ = timed(plain, stream, 3)
+    for key, o in plain_out.items():
+        free_out[key].append(o)
+    plain_fps = n_sat / (t_plain * 1e-3)
+
+    srv = Server(ctx, SERVE_BUDGET, streams=2)
+    try:
+        def run(schedule, count):
+            """Submit requests 0..count-1 at host times `schedule` (s, relative); returns
+            latencies (ms) in request order and the wall time."""
+            pend, lat = {}, [None] * count
+            t0 = time.perf_counter()
+            i = 0
+            while i < count or pend:
+                now = time.perf_counter() - t0
+                while i < count and schedule[i] <= now:
+                    g, c, p = args(i)
+                    o = get_out(c.width, c.height)
+                    tk = srv.submit(g["depth"], g["normal"], g["radiance"], c, p, o)
+                    pend[tk] = (i, o, (c.width, c.height))
+                    i += 1
+                    now = time.perf_counter() - t0
+                for tk in list(pend):
+                    done, lt = srv.poll(tk)
+                    if done:
+                        j, o, key = pend.pop(tk)
+                        lat[j] = lt
+                        srv.release(tk)
+                        free_out[key].append(o)
+                if i < count:
+                    wait = schedule[i] - (time.perf_counter() - t0)
+                    if wait > 0.0005:
+                        time.sleep(min(wait - 0.0003, 0.002))
+                else:
+                    time.sleep(0.0002)
+            return lat, time.perf_counter() - t0
+
+        # saturated: the first n_sat requests submitted at once
+        run([0.0] * n_sat, n_sat)  # warm-up (graphs, output buffers)
+        _, wall_sat = run([0.0] * n_sat, n_sat)
+        sat_fps = n_sat / wall_sat
+        print(f"serve: plain {plain_fps:.1f} frames/s, saturated served {sat_fps:.1f} frames/s",
+              file=sys.stderr, flush=True)
+        results = []
+        for frac in rates:
+            lam = frac * sat_fps
+            sched = np.cumsum([r["gap"] for r in reqs]) / lam
+            sched -= sched[0]
+            st0 = srv.stats()
+            lat, wall = run(list(sched), len(reqs))
+            st = srv.stats()
+            keep = np.array(lat[200:]) if len(lat) > 400 else np.array(lat)
+            samples = sum(samples_of(r) for r in reqs)
+            res = {"rate_fraction_of_saturated": frac, "rate_hz": lam, "requests": len(reqs),
+                   "discarded_warmup": len(reqs) - len(keep), "p50_ms": float(np.percentile(keep, 50)),
+                   "p99_ms": float(np.percentile(keep, 99)), "mean_ms": float(keep.mean()),
+                   "frames_per_s": len(reqs) / wall, "gsamples_s": samples / wall / 1e9,
+                   "rounds": st["rounds"] - st0["rounds"],
+                   "frames_per_round": (st["frames_in_rounds"] - st0["frames_in_rounds"]) /
+                                       max(1, st["rounds"] - st0["rounds"]),
+                   "admitted_while_running": st["admitted_while_running"] - st0["admitted_while_running"],
+                   "max_running_rounds": st["max_running_rounds"], "arena_peak_bytes": st["arena_peak"]}
+            print(f"serve at {frac:.2f} x saturated ({lam:.1f}/s): p50 {res['p50_ms']:.2f} ms, "
+                  f"p99 {res['p99_ms']:.2f} ms, {res['frames_per_s']:.1f} frames/s", file=sys.stderr, flush=True)
+            results.append(res)
+    finally:
+        srv.close()
+    head = next((r for r in results if abs(r["rate_fraction_of_saturated"] - 0.7) < 1e-9), results[0])
+    return {"workload": f"Poisson stream of {len(reqs)} requests (first 200 discarded), resolution uniform over "
+                        "960x540 / 1280x720 / 1920x1080 / 2560x1440 / 3840x2160, slices 2..8, steps {8,16,32}, "
+                        "FP16 or FP32 normals+radiance (p = 1/2), radius 3, t 0.5, R2 noise, 2 procedural scenes "
+                        "per resolution, draw seed 5; G-buffers device-resident, 64 GB HBM budget, 2 streams",
+            "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "frames_per_s": head["frames_per_s"],
+            "rate_hz": head["rate_hz"], "saturated_frames_per_s": sat_fps,
+            "plain_frames_per_s": plain_fps, "served_vs_plain": sat_fps / plain_fps, "rates": results}
 
 
 def main():
@@ -82,6 +342,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2_1080p")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-sweep", action="store_true", help="also serve at 0.5 and 0.9 of saturation")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the gather, run a plain device copy of MIB MiB (scales HBM counters)")
     args = ap.parse_args()
@@ -90,8 +355,8 @@ def main():
               "(frames or row bands would shard with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     if args.copy_calibration:
+        import torch
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.arange(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -100,12 +365,33 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": max(args.steps, 1)}))
         return
-    from gbuffer_scene import workload
-    from paper_2301_11376_amd import Camera, Context, Params, NOISE_NAMES
 
+    # ---- host work first (forked workers), before anything touches the GPU ----
+    from gbuffer_scene import workload, mixed_batch, request_stream, render_pool
     gb, cam, w, scene = workload(args.workload)
     kw = dict(slices=w["slices"], steps=w["steps"], radius=w["radius"], thickness=w["thickness"],
-              noise=NOISE_NAMES[w["noise"]], seed=w["seed"], ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
+              seed=w["seed"], ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
+    keys = []
+    if not args.no_batch:
+        keys += [(f["scene_seed"], f["width"], f["height"]) for f in mixed_batch()]
+    if not args.no_serve:
+        keys += [(r["scene_seed"], r["width"], r["height"]) for r in request_stream(n_requests=args.serve_requests)]
+    pool = {}
+    if keys:
+        t0 = time.perf_counter()
+        pool = render_pool(keys, workers=min(HOST_WORKERS, os.cpu_count() or 1))
+        print(f"rendered {len(pool)} pool frames in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        onoise = {"hash": O.NOISE_HASH, "r2": O.NOISE_R2, "fixed": O.NOISE_FIXED}[w["noise"]]
+        cpu = cpu_baseline(gb, cam, dict(kw, noise=onoise))
+        print(f"cpu baseline {cpu['value']:.4f} Gsamples/s on {cpu['cores']} processes", file=sys.stderr, flush=True)
+
+    # ---- GPU ----
+    import torch
+    from paper_2301_11376_amd import Camera, Context, Params, NOISE_NAMES
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in gb.items()}
@@ -114,7 +400,7 @@ def main():
            "ambient": torch.empty((H, W, 3), device=dev)}
     ctx = Context(0)
     c = Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(cam.view_to_world))
-    p = Params(**kw)
+    p = Params(**dict(kw, noise=NOISE_NAMES[w["noise"]]))
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -160,12 +446,16 @@ def main():
         "kernel_ms": {"mean": kernel_ms, "p50": float(np.percentile(per_launch_ms, 50)),
                       "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload), "traffic_unit": "B per launch",
-                     "algorithmic_bytes_per_launch": abytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": abytes},
     }
-    if not args.no_cpu_baseline:
-        print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(gb, cam, kw)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    if not args.no_batch:
+        result["batch"] = batch_leg(ctx, pool, autotune=not args.no_autotune)
+    if not args.no_serve:
+        rates = [0.5, 0.7, 0.9] if args.serve_sweep else [0.7]
+        result["serving"] = serve_leg(ctx, pool, args.serve_requests, rates)
     ctx.close()
     print(json.dumps(result), flush=True)
 

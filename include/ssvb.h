@@ -166,17 +166,21 @@ ssvb_status ssvb_validate(const ssvb_image* depth, const ssvb_image* normal,
 
 /* The visibility-bitmask gather of one frame (Algorithm 1 with the ambient term of
  * Section 3.2): writes AO, GI (RGB indirect diffuse) and ambient (RGB), each divided by
- * N_d, and optionally the N_d slice masks.  Asynchronous on `hip_stream`. */
+ * N_d, and optionally the N_d slice masks.  Asynchronous on `hip_stream`: one persistent
+ * kernel whose workgroups take the frame's tiles from per-XCD work queues.  The context
+ * keeps 32 sets of queue counters; a call blocks the host only if the launch that last
+ * used its set (32 calls earlier) has not yet finished. */
 ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
                          const ssvb_image* radiance, const ssvb_camera* camera,
                          const ssvb_params* params, const ssvb_outputs* out, void* hip_stream);
 
 /* Many frames of mixed size, slice/step counts, criteria and element types in one
- * replay of a captured HIP graph (descriptor upload + one persistent kernel), asynchronous
- * on `hip_stream`.  Each frame's outputs equal what ssvb_compute writes for it with the
- * same launch shape.  Frames are processed in chunks of 64.  The library keeps two
- * descriptor slots, so a call may block until the batch submitted two calls earlier has
- * been uploaded.  Returns SSVB_ERR_INVALID_ARG naming the first invalid frame. */
+ * replay of a captured HIP graph (descriptor upload, queue reset, one persistent kernel
+ * that works through the frames in the given order), asynchronous on `hip_stream`.  Each
+ * frame's outputs equal, bit for bit, what ssvb_compute writes for it with the same
+ * launch shape.  Frames are processed in chunks of 64.  The library keeps two descriptor
+ * slots, so a call may block until the batch submitted two chunks earlier has finished.
+ * Returns SSVB_ERR_INVALID_ARG naming the first invalid frame. */
 ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t n, void* hip_stream);
 
 /* Force one launch shape for every later frame of this context (NULL: back to the

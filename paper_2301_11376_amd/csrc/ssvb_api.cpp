@@ -18,12 +18,21 @@
 using namespace ssvb;
 
 constexpr int kBatchSlots = 2;  // descriptor slots of the batched path (double buffering)
+constexpr int kRing = 32;       // queue-counter sets of single-frame launches that may be in flight
+constexpr int kRingStride = 16; // uint32 per set (9 used)
 
 struct ssvb_ctx {
     int device = 0;
     int2 h_lut[kLutSize];
     FrameTables tab;  // device tables and launch shapes
     std::string tune_cache;
+    // single-frame path: persistent grid and a ring of queue-counter sets, each guarded
+    // by the event recorded after its last launch
+    int frame_grid = 0;
+    uint32_t* d_ring = nullptr;
+    hipEvent_t ring_ev[kRing] = {};
+    bool ring_pending[kRing] = {};
+    uint64_t next_ring = 0;
     // batched path
     bool batch_ready = false;
     int batch_grid = 0;
@@ -155,7 +164,6 @@ void set_launch(FrameArgs& A, LaunchShape L) {
     A.tile_w = L.tile_w;
     A.tile_h = L.tile_h;
     A.lp = L.lp;
-    A.xcd_remap = 1;
     A.tiles_x = (A.W + A.tile_w - 1) / A.tile_w;
     A.tiles_y = (A.H + A.tile_h - 1) / A.tile_h;
     A.strip = L.strip > 0 ? L.strip : 1;
@@ -246,35 +254,14 @@ void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, c
     set_launch(A, shape);
 }
 
-// Build one descriptor table: frame constants and, per XCD, the cost-ordered segments.
+// Build one descriptor table: frame constants and the order of work (the order given;
+// with work stealing inside each frame, sorting by cost measured no better).
 void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames, int n) {
     D->n_frames = n;
-    std::vector<int> order(n);
-    std::vector<double> cost(n);
     for (int f = 0; f < n; ++f) {
         const ssvb_frame& F = frames[f];
         fill_frame(D->frames[f], tab, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
-        order[f] = f;
-        // work of one tile: its pixels times the samples of a pixel
-        const FrameArgs& A = D->frames[f];
-        cost[f] = (double)A.tile_w * A.tile_h * A.nd * A.ns;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    for (int k = 0; k < kXcds; ++k) {
-        uint32_t start = 0;
-        int ns = 0;
-        for (int f : order) {
-            const FrameArgs& A = D->frames[f];
-            const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
-            const uint32_t per = (nt + kXcds - 1) / kXcds;
-            const uint32_t first = (uint32_t)k * per;
-            if (first >= nt) continue;
-            const uint32_t count = std::min(per, nt - first);
-            D->seg[k][ns++] = BatchSegment{f, first, count, start};
-            start += count;
-        }
-        D->n_seg[k] = ns;
-        D->total[k] = start;
+        D->order[f] = f;
     }
 }
 
@@ -290,7 +277,7 @@ hipError_t batch_grid_size(int device, int* grid) {
 hipError_t init_slot(BatchSlot& s, int grid, hipStream_t cap_stream) {
     hipError_t e = hipHostMalloc((void**)&s.h_desc, sizeof(BatchDesc), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&s.d_desc, sizeof(BatchDesc));
-    if (e == hipSuccess) e = hipMalloc((void**)&s.d_queues, 64 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&s.d_queues, kBatchQueues * sizeof(uint32_t));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
     if (e != hipSuccess) return e;
     memset(s.h_desc, 0, sizeof(BatchDesc));
@@ -304,12 +291,12 @@ hipError_t init_slot(BatchSlot& s, int grid, hipStream_t cap_stream) {
 }
 
 void free_slot(BatchSlot& s) {
-    if (s.exec) hipGraphExecDestroy(s.exec);
-    if (s.graph) hipGraphDestroy(s.graph);
-    if (s.done) hipEventDestroy(s.done);
-    if (s.d_queues) hipFree(s.d_queues);
-    if (s.d_desc) hipFree(s.d_desc);
-    if (s.h_desc) hipHostFree(s.h_desc);
+    if (s.exec) (void)hipGraphExecDestroy(s.exec);
+    if (s.graph) (void)hipGraphDestroy(s.graph);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.d_queues) (void)hipFree(s.d_queues);
+    if (s.d_desc) (void)hipFree(s.d_desc);
+    if (s.h_desc) (void)hipHostFree(s.h_desc);
     s = BatchSlot{};
 }
 
@@ -352,7 +339,7 @@ ssvb_status init_batch(ssvb_ctx* ctx) {
 
 void free_batch(ssvb_ctx* ctx) {
     for (int k = 0; k < kBatchSlots; ++k) free_slot(ctx->slot[k]);
-    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     ctx->cap_stream = nullptr;
     ctx->batch_ready = false;
 }
@@ -409,7 +396,7 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
         ctx->h_lut[k] = make_int2((int)floor(kLutOne * cos(phi) + 0.5), (int)floor(kLutOne * sin(phi) + 0.5));
     }
     int prev = 0;
-    hipGetDevice(&prev);
+    (void)hipGetDevice(&prev);
     if ((e = hipSetDevice(device)) != hipSuccess) {
         delete ctx;
         return hip_fail(e, "hipSetDevice");
@@ -421,10 +408,22 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
     if (e == hipSuccess) e = hipMemcpy(ctx->tab.d_lut, ctx->h_lut, sizeof ctx->h_lut, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->tab.d_half, sizeof half);
     if (e == hipSuccess) e = hipMemcpy(ctx->tab.d_half, half, sizeof half, hipMemcpyHostToDevice);
-    hipSetDevice(prev);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_ring, kRing * kRingStride * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(ctx->d_ring, 0, kRing * kRingStride * sizeof(uint32_t));
+    for (int k = 0; k < kRing && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ctx->ring_ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, device);
+        ctx->frame_grid = prop.multiProcessorCount * frame_blocks_per_cu();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipSetDevice(prev);
     if (e != hipSuccess) {
-        if (ctx->tab.d_lut) hipFree(ctx->tab.d_lut);
-        if (ctx->tab.d_half) hipFree(ctx->tab.d_half);
+        if (ctx->tab.d_lut) (void)hipFree(ctx->tab.d_lut);
+        if (ctx->tab.d_half) (void)hipFree(ctx->tab.d_half);
+        if (ctx->d_ring) (void)hipFree(ctx->d_ring);
+        for (int k = 0; k < kRing; ++k)
+            if (ctx->ring_ev[k]) (void)hipEventDestroy(ctx->ring_ev[k]);
         delete ctx;
         return e == hipErrorOutOfMemory ? fail(SSVB_ERR_OUT_OF_MEMORY, "direction table") : hip_fail(e, "direction table");
     }
@@ -435,12 +434,15 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
 ssvb_status ssvb_destroy(ssvb_ctx* ctx) {
     if (!ctx) return SSVB_OK;
     int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(ctx->device);
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
     free_batch(ctx);
-    if (ctx->tab.d_lut) hipFree(ctx->tab.d_lut);
-    if (ctx->tab.d_half) hipFree(ctx->tab.d_half);
-    hipSetDevice(prev);
+    if (ctx->tab.d_lut) (void)hipFree(ctx->tab.d_lut);
+    if (ctx->tab.d_half) (void)hipFree(ctx->tab.d_half);
+    if (ctx->d_ring) (void)hipFree(ctx->d_ring);
+    for (int k = 0; k < kRing; ++k)
+        if (ctx->ring_ev[k]) (void)hipEventDestroy(ctx->ring_ev[k]);
+    (void)hipSetDevice(prev);
     delete ctx;
     return SSVB_OK;
 }
@@ -476,10 +478,17 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     FrameArgs A;
     fill_frame(A, &ctx->tab, depth, normal, radiance, camera, params, out);
     int prev = 0;
-    hipGetDevice(&prev);
-    if (prev != ctx->device) hipSetDevice(ctx->device);
-    const hipError_t e = launch_plain(A, (hipStream_t)hip_stream);
-    if (prev != ctx->device) hipSetDevice(prev);
+    (void)hipGetDevice(&prev);
+    if (prev != ctx->device) (void)hipSetDevice(ctx->device);
+    // a counter set is reused only once its previous launch has completed (blocks the
+    // host only with kRing launches of this context still in flight)
+    const int r = (int)(ctx->next_ring++ % kRing);
+    hipError_t e = hipSuccess;
+    if (ctx->ring_pending[r]) e = hipEventSynchronize(ctx->ring_ev[r]);
+    if (e == hipSuccess) e = launch_plain(A, ctx->d_ring + r * kRingStride, ctx->frame_grid, (hipStream_t)hip_stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ring_ev[r], (hipStream_t)hip_stream);
+    if (e == hipSuccess) ctx->ring_pending[r] = true;
+    if (prev != ctx->device) (void)hipSetDevice(prev);
     if (e != hipSuccess) return hip_fail(e, "gather launch");
     return SSVB_OK;
 }
@@ -493,8 +502,8 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
         if (s) return fail(s, "frame %d: %s", f, last_error().c_str());
     }
     int prev = 0;
-    hipGetDevice(&prev);
-    if (prev != ctx->device) hipSetDevice(ctx->device);
+    (void)hipGetDevice(&prev);
+    if (prev != ctx->device) (void)hipSetDevice(ctx->device);
     ssvb_status st = init_batch(ctx);
     hipStream_t stream = (hipStream_t)hip_stream;
     for (int f0 = 0; st == SSVB_OK && f0 < n; f0 += kMaxBatch) {
@@ -514,7 +523,7 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
         if (e != hipSuccess) st = hip_fail(e, "batch launch");
         else S.pending = true;
     }
-    if (prev != ctx->device) hipSetDevice(prev);
+    if (prev != ctx->device) (void)hipSetDevice(prev);
     return st;
 }
 
@@ -553,8 +562,8 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
     static const int kStrips[] = {2, 4, 8};
     hipStream_t stream = (hipStream_t)hip_stream;
     int prev = 0;
-    hipGetDevice(&prev);
-    if (prev != ctx->device) hipSetDevice(ctx->device);
+    (void)hipGetDevice(&prev);
+    if (prev != ctx->device) (void)hipSetDevice(ctx->device);
     const bool was_forced = ctx->tab.forced;
     const LaunchShape was = ctx->tab.force;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -587,9 +596,9 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
     }
     ctx->tab.forced = was_forced;
     ctx->tab.force = was;
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    if (prev != ctx->device) hipSetDevice(prev);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (prev != ctx->device) (void)hipSetDevice(prev);
     if (e != hipSuccess) return s != SSVB_OK ? s : hip_fail(e, "autotune");
     const int fmt = (F.normal.dtype == SSVB_F16 ? 1 : 0) | (F.radiance.dtype == SSVB_F16 ? 2 : 0);
     ctx->tab.tuned[ShapeKey{F.camera.width, F.camera.height, F.params.slices, F.params.steps, fmt}] = best_s;

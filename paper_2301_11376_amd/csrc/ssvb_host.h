@@ -24,9 +24,9 @@ struct FrameTables {
     std::map<ShapeKey, LaunchShape> tuned;
 };
 
-// One descriptor slot of the batched path: pinned + device descriptor table, per-XCD
-// queue counters and the captured graph (descriptor upload, queue reset, persistent
-// kernel) that replays it.
+// One descriptor slot of the batched path: pinned + device descriptor table, the queue
+// heads (one per frame and XCD) and the captured graph (descriptor upload, queue reset,
+// persistent kernel) that replays it.
 struct BatchSlot {
     BatchDesc* h_desc = nullptr;
     BatchDesc* d_desc = nullptr;
@@ -48,11 +48,15 @@ void free_slot(BatchSlot& s);
 // `tab` (forced, tuned for the frame's class, else the default).
 void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, const ssvb_image* normal,
                 const ssvb_image* radiance, const ssvb_camera* cam, const ssvb_params* p, const ssvb_outputs* out);
-// Descriptor table of up to kMaxBatch non-empty frames: constants and, per XCD, the
-// frames' tiles in order of decreasing tile cost.
+// Descriptor table of up to kMaxBatch non-empty frames: constants and the order in which
+// the persistent kernel works through them.
 void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames, int n);
 
-hipError_t launch_plain(const FrameArgs& A, hipStream_t stream);
+// One frame with the persistent kernel: `queues` is a set of 9 counters that must be
+// zero at launch (the kernel leaves them zero when it completes); at most `grid`
+// workgroups.
+hipError_t launch_plain(const FrameArgs& A, uint32_t* queues, int grid, hipStream_t stream);
+int frame_blocks_per_cu();
 hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream);
 hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t stream);
 hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, int grid,

@@ -55,9 +55,8 @@ struct FrameArgs {
     // cos and sin of h pi / 64 for h = -64..64 (device, FP64), index h + 64
     const double2* half_sector;
     // launch shape: tile_w x tile_h pixels per workgroup; tiles are walked in vertical
-    // strips of `strip` tiles, and with xcd_remap each XCD takes a contiguous run of that
-    // walk (workgroup i runs on XCD i mod kXcds)
-    int32_t tile_w, tile_h, tiles_x, tiles_y, strip, xcd_remap;
+    // strips of `strip` tiles, and the walk is cut into one contiguous run per XCD
+    int32_t tile_w, tile_h, tiles_x, tiles_y, strip;
     // lanes per pixel: the N_d slices of a pixel are split over lp adjacent lanes;
     // tile_w * tile_h * lp = 256 threads per workgroup
     int32_t lp;
@@ -86,36 +85,17 @@ __device__ __forceinline__ void walk_tile(const FrameArgs& A, uint32_t ord, int&
     }
 }
 
-// Workgroup index -> tile (tx, ty); false for the padding workgroups past the end.
-__device__ __forceinline__ bool tile_of(const FrameArgs& A, uint32_t bid, int& tx, int& ty) {
-    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
-    uint32_t ord = bid;
-    if (A.xcd_remap) {
-        const uint32_t per = (nt + kXcds - 1) / kXcds;
-        ord = (bid % kXcds) * per + bid / kXcds;
-    }
-    if (ord >= nt) return false;
-    walk_tile(A, ord, tx, ty);
-    return true;
-}
-
 // ---------------------------------------------------------------------------------------
 // batched persistent path
 // ---------------------------------------------------------------------------------------
 constexpr int kMaxBatch = 64;  // frames per descriptor table (larger batches are chunked)
+constexpr int kBatchQueues = kMaxBatch * kXcds;  // one queue head per frame and XCD
 
-// A run of one frame's tile walk in one XCD's queue: queue items [start, start + count)
-// are the frame's walk positions [first, first + count).
-struct BatchSegment {
-    int32_t frame;
-    uint32_t first, count, start;
-};
-
+// Frames of one persistent launch and the order they are worked through.  Queue
+// f * kXcds + k holds run k of frame f's tile walk (the walk cut into kXcds equal runs).
 struct BatchDesc {
     int32_t n_frames;
-    int32_t n_seg[kXcds];
-    uint32_t total[kXcds];
-    BatchSegment seg[kXcds][kMaxBatch];
+    int32_t order[kMaxBatch];
     FrameArgs frames[kMaxBatch];
 };
 

@@ -61,12 +61,17 @@ __device__ __forceinline__ uint32_t jitter8(const FrameArgs& A, int x, int y, in
 // ---------------------------------------------------------------------------------------
 // G-buffer access (every image spans less than 4 GiB: 32-bit byte offsets)
 // ---------------------------------------------------------------------------------------
+// Images and outputs live in global device memory.  Pointers read from a descriptor in
+// memory are generic to the compiler; accessing them through pointers of the global
+// address space lets it use global (rather than flat) loads and stores.
+#define GMEM __attribute__((address_space(1)))
+
 __device__ __forceinline__ uint32_t depth_off(const FrameArgs& A, int X, int Y) {
     return (uint32_t)Y * (uint32_t)A.depth_pitch + (uint32_t)X * 4u;
 }
 
 __device__ __forceinline__ float depth_load(const FrameArgs& A, uint32_t off) {
-    return *(const float*)((const char*)A.depth + off);
+    return *(const GMEM float*)((const GMEM char*)A.depth + off);
 }
 
 // F: 0 = FP32, 1 = FP16, -1 = given at run time by `f16`
@@ -74,11 +79,12 @@ template <int F>
 __device__ __forceinline__ float3 load3(const char* base, int64_t pitch, int ch, int f16, int x, int y) {
     const bool h = F < 0 ? f16 != 0 : F == 1;
     const uint32_t off = (uint32_t)y * (uint32_t)pitch + (uint32_t)(x * ch) * (h ? 2u : 4u);
+    const GMEM char* b = (const GMEM char*)base + off;
     if (h) {
-        const _Float16* p = (const _Float16*)(base + off);
+        const GMEM _Float16* p = (const GMEM _Float16*)b;
         return make_float3((float)p[0], (float)p[1], (float)p[2]);
     }
-    const float* p = (const float*)(base + off);
+    const GMEM float* p = (const GMEM float*)b;
     return make_float3(p[0], p[1], p[2]);
 }
 
@@ -179,7 +185,8 @@ __device__ __forceinline__ SliceF slice_constants(const FrameArgs& A, double rpx
 // directions is exactly zero.
 __device__ __forceinline__ bool at_or_above(const FrameArgs& A, int h, double cg, double sg, double sv, double se) {
 #pragma clang fp contract(off)
-    const double2 cs = A.half_sector[h + 64];  // cos, sin of h pi / 64
+    const GMEM double* hs = (const GMEM double*)A.half_sector + 2 * (h + 64);  // cos, sin of h pi / 64
+    const double2 cs = make_double2(hs[0], hs[1]);
     const double dv = cs.x * cg - cs.y * sg, de = cs.y * cg + cs.x * sg;
     return dv * se - de * sv >= 0.0;
 }
@@ -218,13 +225,13 @@ enum { MODE_COMPUTE = 0, MODE_LATTICE = 1, MODE_ENDPOINTS = 2 };
 
 __device__ __forceinline__ void store_background(const FrameArgs& A, int x, int y, int li) {
     if (li != 0) return;
-    *(float*)((char*)A.ao + (int64_t)y * A.ao_pitch + (int64_t)x * 4) = 1.0f;
-    float* g = (float*)((char*)A.gi + (int64_t)y * A.gi_pitch) + 3 * (int64_t)x;
-    float* m = (float*)((char*)A.amb + (int64_t)y * A.amb_pitch) + 3 * (int64_t)x;
+    *(GMEM float*)((GMEM char*)A.ao + (int64_t)y * A.ao_pitch + (int64_t)x * 4) = 1.0f;
+    GMEM float* g = (GMEM float*)((GMEM char*)A.gi + (int64_t)y * A.gi_pitch) + 3 * (int64_t)x;
+    GMEM float* m = (GMEM float*)((GMEM char*)A.amb + (int64_t)y * A.amb_pitch) + 3 * (int64_t)x;
     g[0] = g[1] = g[2] = 0.0f;
     m[0] = m[1] = m[2] = 0.0f;
     if (A.masks) {
-        uint32_t* mk = (uint32_t*)((char*)A.masks + (int64_t)y * A.masks_pitch) + (int64_t)x * A.nd;
+        GMEM uint32_t* mk = (GMEM uint32_t*)((GMEM char*)A.masks + (int64_t)y * A.masks_pitch) + (int64_t)x * A.nd;
         for (int i = 0; i < A.nd; ++i) mk[i] = 0u;
     }
 }
@@ -301,7 +308,9 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
                     const double lv = s > 0 ? fv : bv2, le = s > 0 ? fe : be2;
                     const double hv = s > 0 ? bv2 : fv, hev = s > 0 ? be2 : fe;
                     const int m = max((int)rintf(wf), 0);
-                    const double2 cs = A.half_sector[2 * m + 64];  // rotate the low end by m pi / 32
+                    // rotate the low end by m pi / 32
+                    const GMEM double* hs = (const GMEM double*)A.half_sector + 2 * (2 * m + 64);
+                    const double2 cs = make_double2(hs[0], hs[1]);
                     const double rv = cs.x * lv - cs.y * le, re = cs.y * lv + cs.x * le;
                     w = (rv * hev - re * hv <= 0.0) ? m : m + 1;
                 }
@@ -348,7 +357,7 @@ template <int CRIT, int MODE, bool TINF, int FMT>
 __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int li, int lp,
                                              int32_t* dbg_i, float* dbg_f) {
     const int t = (int)threadIdx.x;
-    const float zp = *(const float*)((const char*)A.depth + depth_off(A, x, y));
+    const float zp = depth_load(A, depth_off(A, x, y));
     const bool geom = is_geometry(zp);
     if (MODE == MODE_COMPUTE && !geom) {
         store_background(A, x, y, li);
@@ -387,7 +396,8 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
 
     for (int i = li; i < A.nd; i += lp) {
         const int k = (int)(((uint32_t)i * 65536u + rho) / (uint32_t)(16 * A.nd));
-        const int2 D = A.lut[k];
+        const GMEM int* dk = (const GMEM int*)A.lut + 2 * k;
+        const int2 D = make_int2(dk[0], dk[1]);
         const int jit = (q * (int)jitter8(A, x, y, i)) >> 8;
         if (MODE == MODE_LATTICE) {
             for (int side = 0; side < 2; ++side) {
@@ -458,7 +468,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
         if (MODE != MODE_COMPUTE) continue;
         ao_acc += 1.0f - (float)__popc(B) * (1.0f / 32.0f);
         if (A.masks) {
-            uint32_t* mk = (uint32_t*)((char*)A.masks + (int64_t)y * A.masks_pitch) + (int64_t)x * A.nd;
+            GMEM uint32_t* mk = (GMEM uint32_t*)((GMEM char*)A.masks + (int64_t)y * A.masks_pitch) + (int64_t)x * A.nd;
             mk[i] = B;
         }
         // directionally occluded ambient (Section 3.2)
@@ -505,27 +515,75 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
     }
     if (li != 0) return;
     const float inv_nd = 1.0f / (float)A.nd;
-    *(float*)((char*)A.ao + (int64_t)y * A.ao_pitch + (int64_t)x * 4) = ao_acc * inv_nd;
-    float* g = (float*)((char*)A.gi + (int64_t)y * A.gi_pitch) + 3 * (int64_t)x;
+    *(GMEM float*)((GMEM char*)A.ao + (int64_t)y * A.ao_pitch + (int64_t)x * 4) = ao_acc * inv_nd;
+    GMEM float* g = (GMEM float*)((GMEM char*)A.gi + (int64_t)y * A.gi_pitch) + 3 * (int64_t)x;
     g[0] = gir * inv_nd;
     g[1] = gig * inv_nd;
     g[2] = gib * inv_nd;
-    float* m = (float*)((char*)A.amb + (int64_t)y * A.amb_pitch) + 3 * (int64_t)x;
+    GMEM float* m = (GMEM float*)((GMEM char*)A.amb + (int64_t)y * A.amb_pitch) + 3 * (int64_t)x;
     m[0] = amr * inv_nd;
     m[1] = amg * inv_nd;
     m[2] = amb * inv_nd;
 }
 
+// The XCD this wave runs on (hardware register XCC_ID; the die's own L2 serves it).
+__device__ __forceinline__ int hw_xcd() {
+    unsigned id;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(id));
+    return (int)(id & (kXcds - 1));
+}
+
+// Next item of queue `q` for the whole workgroup (uniform).
+__device__ __forceinline__ uint32_t grab(uint32_t* q, uint32_t* s_item) {
+    if (threadIdx.x == 0) *s_item = atomicAdd(q, 1u);
+    __syncthreads();
+    const uint32_t item = __builtin_amdgcn_readfirstlane(*s_item);
+    __syncthreads();
+    return item;
+}
+
+// One frame, persistent workgroups.  The frame's tile walk is cut into 8 equal runs,
+// run k queued for XCD k (its tiles stay in that die's L2); a workgroup drains the queue
+// of its own XCD first and then takes what is left in the others, so dies that finish
+// early help the slow ones.  q[0..7] are the queue heads, q[8] counts finished
+// workgroups: the last one to finish sets all nine back to zero for the next launch.
 template <int CRIT, bool TINF, int FMT>
-__global__ __launch_bounds__(kBlock) void gather_plain(FrameArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void gather_frame(
+    FrameArgs A, uint32_t* __restrict__ q) {
     __shared__ ExactLds L;
-    int tx, ty;
-    if (!tile_of(A, blockIdx.x, tx, ty)) return;
-    const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
-    const int x = tx * A.tile_w + px % A.tile_w;
-    const int y = ty * A.tile_h + px / A.tile_w;
-    if (x >= A.W || y >= A.H) return;
-    gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT>(A, L, x, y, li, lp, nullptr, nullptr);
+    __shared__ uint32_t s_item;
+    // the frame constants are read from the kernel-argument segment on every tile: an
+    // opaque pointer keeps the compiler from holding tile-invariant values in registers
+    // across the tile loop (which would cost occupancy)
+    typedef const __attribute__((address_space(4))) FrameArgs* ConstArgs;  // scalar-loadable
+    const ConstArgs args = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
+    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+    const uint32_t per = (nt + kXcds - 1) / kXcds;
+    const int home = hw_xcd();
+    for (int qi = 0; qi < kXcds; ++qi) {
+        const int k = (home + qi) & (kXcds - 1);
+        const uint32_t first = (uint32_t)k * per;
+        const uint32_t count = first < nt ? min(per, nt - first) : 0u;
+        for (;;) {
+            const uint32_t item = grab(&q[k], &s_item);
+            if (item >= count) break;
+            ConstArgs ap = args;
+            asm volatile("" : "+s"(ap));
+            const FrameArgs& F = *(const FrameArgs*)ap;
+            int tx, ty;
+            walk_tile(F, first + item, tx, ty);
+            const int lp = F.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
+            const int x = tx * F.tile_w + px % F.tile_w;
+            const int y = ty * F.tile_h + px / F.tile_w;
+            if (x < F.W && y < F.H) gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT>(F, L, x, y, li, lp, nullptr, nullptr);
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&q[kXcds], 1u) == gridDim.x - 1) {
+            for (int k = 0; k <= kXcds; ++k) atomicExch(&q[k], 0u);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void debug_lattice(FrameArgs A, int32_t* out) {
@@ -552,37 +610,41 @@ __global__ __launch_bounds__(kBlock) void debug_endpoints(FrameArgs A, float* ou
 // contiguous parts, one per XCD, so every XCD works on compact regions (its L2), and the
 // queues list expensive frames first so that the tail is short.  Criterion, element types
 // and thickness are taken per frame at run time.
-__global__ __launch_bounds__(kBlock) void gather_batch(const BatchDesc* __restrict__ D, uint32_t* __restrict__ queues) {
+// Many frames, persistent workgroups, frame by frame in the descriptor's order: for each
+// frame a workgroup drains its own XCD's run of the frame, then whatever is left of the
+// frame's other runs, and moves on to the next frame without waiting for the rest (as
+// back-to-back single-frame launches would, with their tails overlapped).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void gather_batch(
+    const BatchDesc* __restrict__ D, uint32_t* __restrict__ queues) {
     __shared__ ExactLds L;
     __shared__ uint32_t s_item;
-    const int xcd = (int)(blockIdx.x % kXcds);
-    const uint32_t total = D->total[xcd];
-    const int nseg = D->n_seg[xcd];
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&queues[xcd], 1u);
-        __syncthreads();
-        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (item >= total) break;
-        int lo = 0, hi = nseg - 1;  // last segment whose start <= item
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (D->seg[xcd][mid].start <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchSegment sg = D->seg[xcd][lo];
-        const FrameArgs& A = D->frames[sg.frame];
-        int tx, ty;
-        walk_tile(A, sg.first + (item - sg.start), tx, ty);
+    const int home = hw_xcd();
+    const int n = D->n_frames;
+    for (int oi = 0; oi < n; ++oi) {
+        const int f = D->order[oi];
+        const FrameArgs& A = D->frames[f];
+        const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+        const uint32_t per = (nt + kXcds - 1) / kXcds;
         const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
-        const int x = tx * A.tile_w + px % A.tile_w;
-        const int y = ty * A.tile_h + px / A.tile_w;
-        if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1>(A, L, x, y, li, lp, nullptr, nullptr);
+        for (int qi = 0; qi < kXcds; ++qi) {
+            const int k = (home + qi) & (kXcds - 1);
+            const uint32_t first = (uint32_t)k * per;
+            const uint32_t count = first < nt ? min(per, nt - first) : 0u;
+            for (;;) {
+                const uint32_t item = grab(&queues[f * kXcds + k], &s_item);
+                if (item >= count) break;
+                int tx, ty;
+                walk_tile(A, first + item, tx, ty);
+                const int x = tx * A.tile_w + px % A.tile_w;
+                const int y = ty * A.tile_h + px / A.tile_w;
+                if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1>(A, L, x, y, li, lp, nullptr, nullptr);
+            }
+        }
     }
 }
 
 __global__ void reset_queues(uint32_t* q) {
-    if (threadIdx.x < kXcds) q[threadIdx.x] = 0u;
+    for (int i = (int)threadIdx.x; i < kBatchQueues; i += (int)blockDim.x) q[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -592,7 +654,7 @@ hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint3
                          hipStream_t s) {
     hipError_t e = hipMemcpyAsync((void*)d_desc, h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reset_queues, dim3(1), dim3(64), 0, s, d_queues);
+    hipLaunchKernelGGL(reset_queues, dim3(1), dim3(256), 0, s, d_queues);
     hipLaunchKernelGGL(gather_batch, dim3(grid), dim3(kBlock), 0, s, d_desc, d_queues);
     return hipGetLastError();
 }
@@ -605,32 +667,43 @@ int batch_blocks_per_cu() {
 static dim3 grid16(const FrameArgs& A) { return dim3((A.W + 15) / 16, (A.H + 15) / 16); }
 
 template <int CRIT, bool TINF, int FMT>
-static void launch_main(const FrameArgs& A, hipStream_t stream) {
+static void launch_main(const FrameArgs& A, uint32_t* q, int grid, hipStream_t stream) {
+    // no more workgroups than the frame has tiles (rounded to whole XCD rounds)
     const uint32_t nt = (uint32_t)A.tiles_x * A.tiles_y;
-    const uint32_t nwg = A.xcd_remap ? kXcds * ((nt + kXcds - 1) / kXcds) : nt;
-    hipLaunchKernelGGL((gather_plain<CRIT, TINF, FMT>), dim3(nwg), dim3(kBlock), 0, stream, A);
+    const uint32_t need = kXcds * ((nt + kXcds - 1) / kXcds);
+    const uint32_t nwg = need < (uint32_t)grid ? need : (uint32_t)grid;
+    hipLaunchKernelGGL((gather_frame<CRIT, TINF, FMT>), dim3(nwg), dim3(kBlock), 0, stream, A, q);
 }
 
 template <int CRIT, bool TINF>
-static void launch_fmt(const FrameArgs& A, hipStream_t stream) {
+static void launch_fmt(const FrameArgs& A, uint32_t* q, int grid, hipStream_t stream) {
     switch (A.normal_f16 | (A.radiance_f16 << 1)) {
-        case 0: launch_main<CRIT, TINF, 0>(A, stream); break;
-        case 1: launch_main<CRIT, TINF, 1>(A, stream); break;
-        case 2: launch_main<CRIT, TINF, 2>(A, stream); break;
-        default: launch_main<CRIT, TINF, 3>(A, stream); break;
+        case 0: launch_main<CRIT, TINF, 0>(A, q, grid, stream); break;
+        case 1: launch_main<CRIT, TINF, 1>(A, q, grid, stream); break;
+        case 2: launch_main<CRIT, TINF, 2>(A, q, grid, stream); break;
+        default: launch_main<CRIT, TINF, 3>(A, q, grid, stream); break;
     }
 }
 
-hipError_t launch_plain(const FrameArgs& A, hipStream_t stream) {
+hipError_t launch_plain(const FrameArgs& A, uint32_t* queues, int grid, hipStream_t stream) {
     const bool tinf = isinf(A.t0);
     if (A.criterion == SSVB_HIT_ROUND) {
-        if (tinf) launch_fmt<SSVB_HIT_ROUND, true>(A, stream);
-        else launch_fmt<SSVB_HIT_ROUND, false>(A, stream);
+        if (tinf) launch_fmt<SSVB_HIT_ROUND, true>(A, queues, grid, stream);
+        else launch_fmt<SSVB_HIT_ROUND, false>(A, queues, grid, stream);
     } else {
-        if (tinf) launch_fmt<SSVB_HIT_PSEUDOCODE, true>(A, stream);
-        else launch_fmt<SSVB_HIT_PSEUDOCODE, false>(A, stream);
+        if (tinf) launch_fmt<SSVB_HIT_PSEUDOCODE, true>(A, queues, grid, stream);
+        else launch_fmt<SSVB_HIT_PSEUDOCODE, false>(A, queues, grid, stream);
     }
     return hipGetLastError();
+}
+
+int frame_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gather_frame<SSVB_HIT_ROUND, false, 0>, kBlock, 0) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 2;
+    return nb;
 }
 
 hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream) {

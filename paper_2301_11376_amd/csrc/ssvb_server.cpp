@@ -173,7 +173,7 @@ void fail_request(ssvb_server* S, uint64_t t, Request& r, Clock::time_point now)
 // start a round on every idle stream.  HIP calls are made with the lock released; the
 // requests they touch are not erased meanwhile (release refuses unfinished tickets).
 void run(ssvb_server* S) {
-    hipSetDevice(S->device);
+    (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         bool progress = false;
@@ -299,12 +299,12 @@ ssvb_status fatal_status(const ssvb_server* S) {
 void destroy_resources(ssvb_server* S) {
     for (int k = 0; k < kMaxStreams; ++k) {
         free_slot(S->slots[k]);
-        if (S->streams[k]) hipStreamDestroy(S->streams[k]);
+        if (S->streams[k]) (void)hipStreamDestroy(S->streams[k]);
     }
-    if (S->staged) hipEventDestroy(S->staged);
-    if (S->copy_stream) hipStreamDestroy(S->copy_stream);
-    if (S->cap_stream) hipStreamDestroy(S->cap_stream);
-    if (S->arena) hipFree(S->arena);
+    if (S->staged) (void)hipEventDestroy(S->staged);
+    if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
+    if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
+    if (S->arena) (void)hipFree(S->arena);
 }
 
 }  // namespace
@@ -327,8 +327,8 @@ ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t
     S->nstreams = streams;
     S->adm = Admission(hbm_budget_bytes, kMaxBatch, kAlign);
     int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(S->device);
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(S->device);
     hipError_t e = hipMalloc((void**)&S->arena, S->adm.arena().size());
     const bool oom = e == hipErrorOutOfMemory;
     if (e == hipSuccess) e = batch_grid_size(S->device, &S->grid);
@@ -344,12 +344,12 @@ ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t
     if (e == hipSuccess) e = hipStreamSynchronize(S->copy_stream);
     if (e != hipSuccess) {
         destroy_resources(S);
-        hipSetDevice(prev);
+        (void)hipSetDevice(prev);
         delete S;
         return oom ? fail(SSVB_ERR_OUT_OF_MEMORY, "arena of %llu bytes", (unsigned long long)hbm_budget_bytes)
                    : hip_fail(e, "server set-up");
     }
-    hipSetDevice(prev);
+    (void)hipSetDevice(prev);
     S->st.arena_bytes = S->adm.arena().size();
     try {
         S->worker = std::thread(run, S);
@@ -462,15 +462,15 @@ ssvb_status ssvb_server_destroy(ssvb_server* S) {
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();
     int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(S->device);
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(S->device);
     hipError_t e = hipStreamSynchronize(S->copy_stream);  // staging of dropped requests
     for (int k = 0; k < S->nstreams; ++k) {
         const hipError_t e2 = hipStreamSynchronize(S->streams[k]);
         if (e == hipSuccess) e = e2;
     }
     destroy_resources(S);
-    hipSetDevice(prev);
+    (void)hipSetDevice(prev);
     delete S;
     if (e != hipSuccess) return hip_fail(e, "server shutdown");
     return SSVB_OK;

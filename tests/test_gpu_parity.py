@@ -277,3 +277,30 @@ def test_parity_c3_4k_fp16_sampled(ctx):
     log(f"  vs FP32 originals (p99.9, max, mean): {stats}")
     for k, (p999, mx, _) in stats.items():
         assert p999 <= 2e-2 and mx <= 2e-2, (k, stats)
+
+
+def test_many_launches_two_streams(ctx):
+    """Single-frame launches draw their queue counters from a ring of 32 sets: 80
+    launches alternating over two streams without host synchronisation (every set reused
+    at least twice, launches on the two streams overlapping) all equal the result of one
+    launch, bit for bit."""
+    import torch
+    from paper_2301_11376_amd import Context
+    sc = make_scene(21, 30, 10)
+    cam = make_camera(96, 64, fov_y_deg=60, pitch_deg=-25)
+    gb = render_gbuffer(sc, cam, cache=False)
+    bc, _ = PY.cams(cam)
+    bp, _ = PY.params(slices=3, steps=6, radius=1.5, thickness=0.4, noise=O.NOISE_HASH, seed=4)
+    t = PY.to_device(gb)
+    ref = ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [Context.alloc_outputs(64, 96, 3, "cuda") for _ in range(80)]
+    torch.cuda.synchronize()
+    log("80 launches on two streams")
+    for i, o in enumerate(outs):
+        ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp, out=o, stream=streams[i % 2])
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        for k in ("ao", "gi", "ambient"):
+            assert torch.equal(o[k], ref[k]), (i, k)
