@@ -206,8 +206,9 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
  * in the arena:
  *     W * H * (4 + normal bytes/px + radiance bytes/px + 28), each part 256-aligned
  * (depth FP32, the normal and radiance buffers as given, AO + GI + ambient FP32).
- * Admitted frames are copied into the arena on a copy stream and stay resident there
- * until their result has been copied out.  As soon as one of the server's compute
+ * An admitted frame holds that much of the arena until it has finished: its buffers that
+ * are in host memory are copied into it on a copy stream (results copied back), buffers
+ * already in this device's memory are read and written in place.  As soon as one of the server's compute
  * streams is idle, every admitted frame not yet started (at most 64) runs as one round
  * of the persistent batch kernel, so frames that arrive while a round is on the device
  * join the next one and rounds on different streams overlap.  Each frame's results are

@@ -1,9 +1,10 @@
 // Request loop of the visibility-bitmask gather: frames are admitted by their HBM
-// footprint into a device arena owned by the server (FIFO), their G-buffers are staged
-// into it on a copy stream, and admitted frames are run in rounds of up to 64 through
-// the persistent batch kernel on two or more compute streams, so that a round can start
-// while another is still on the device.  Results are copied back to the caller's
-// buffers and each request is stamped with its completion time.
+// footprint into a device arena owned by the server (FIFO); buffers in host memory are
+// staged through the arena on a copy stream, buffers already in device memory are used
+// in place; admitted frames are run in rounds of up to 64 through the persistent batch
+// kernel on two or more compute streams, so that a round can start while another is
+// still on the device.  Each request is stamped with its completion time once its
+// results are in the caller's buffers.
 #include <string.h>
 
 #include <algorithm>
@@ -60,8 +61,10 @@ Layout layout_of(const ssvb_frame& F) {
 
 struct Request {
     ssvb_frame caller;  // the caller's buffers
-    ssvb_frame staged;  // the same frame in the arena
+    ssvb_frame staged;  // the frame as the kernel reads it: arena copies or the caller's buffers
     Layout lay;
+    bool in_place[3] = {};  // depth, normal, radiance already in this device's memory
+    bool out_in_place = false;  // all three outputs in this device's memory
     int state = QUEUED;
     ssvb_status err = SSVB_OK;
     Clock::time_point t_submit, t_done;
@@ -106,22 +109,36 @@ struct ssvb_server {
 
 namespace {
 
+// True if `p` is memory of HIP device `device` (not host memory, pinned or not).
+bool on_device(const void* p, int device) {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();  // pageable host memory: not an error for the caller
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice && at.device == device && !at.isManaged;
+}
+
+// Point the kernel's view of the request at its arena block, copying in the inputs that
+// are not already in device memory (those are read in place).
 hipError_t stage(ssvb_server* S, Request& r, uint64_t off) {
     const ssvb_frame& F = r.caller;
     const int W = F.camera.width, H = F.camera.height;
     char* base = S->arena + off;
     r.staged = F;
-    r.staged.depth.ptr = base + r.lay.depth;
-    r.staged.depth.pitch_bytes = 0;
-    r.staged.normal.ptr = base + r.lay.normal;
-    r.staged.normal.pitch_bytes = 0;
-    r.staged.radiance.ptr = base + r.lay.radiance;
-    r.staged.radiance.pitch_bytes = 0;
-    r.staged.out = ssvb_outputs{(float*)(base + r.lay.ao), (float*)(base + r.lay.gi), (float*)(base + r.lay.amb),
-                                nullptr, 0, 0, 0, 0};
-    const ssvb_image* src[3] = {&F.depth, &F.normal, &F.radiance};
-    const ssvb_image* dst[3] = {&r.staged.depth, &r.staged.normal, &r.staged.radiance};
+    const uint64_t at[3] = {r.lay.depth, r.lay.normal, r.lay.radiance};
+    ssvb_image* dst[3] = {&r.staged.depth, &r.staged.normal, &r.staged.radiance};
     for (int i = 0; i < 3; ++i) {
+        if (r.in_place[i]) continue;
+        dst[i]->ptr = base + at[i];
+        dst[i]->pitch_bytes = 0;
+    }
+    if (!r.out_in_place)
+        r.staged.out = ssvb_outputs{(float*)(base + r.lay.ao), (float*)(base + r.lay.gi), (float*)(base + r.lay.amb),
+                                    nullptr, 0, 0, 0, 0};
+    const ssvb_image* src[3] = {&F.depth, &F.normal, &F.radiance};
+    for (int i = 0; i < 3; ++i) {
+        if (r.in_place[i]) continue;
         const size_t row = (size_t)W * src[i]->channels * elem_size(src[i]->dtype);
         hipError_t e = hipMemcpy2DAsync((void*)dst[i]->ptr, row, src[i]->ptr, (size_t)pitch_of(*src[i], W), row,
                                         (size_t)H, hipMemcpyDefault, S->copy_stream);
@@ -143,6 +160,7 @@ hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs) 
     if (e == hipSuccess) e = hipGraphLaunch(B.exec, s);
     for (const Request* r : rs) {
         if (e != hipSuccess) break;
+        if (r->out_in_place) continue;  // the kernel wrote the caller's buffers
         const ssvb_frame& F = r->caller;
         const int W = F.camera.width, H = F.camera.height;
         struct {
@@ -371,6 +389,13 @@ ssvb_status ssvb_server_submit(ssvb_server* S, const ssvb_frame* frame, uint64_t
     Request r;
     r.caller = F;
     r.lay = layout_of(F);
+    if ((int64_t)F.camera.width * F.camera.height > 0) {
+        r.in_place[0] = on_device(F.depth.ptr, S->device);
+        r.in_place[1] = on_device(F.normal.ptr, S->device);
+        r.in_place[2] = on_device(F.radiance.ptr, S->device);
+        r.out_in_place = on_device(F.out.ao, S->device) && on_device(F.out.gi, S->device) &&
+                         on_device(F.out.ambient, S->device);
+    }
     if (!S->adm.fits_at_all(r.lay.total))
         return fail(SSVB_ERR_OUT_OF_MEMORY, "request footprint %llu bytes exceeds the %llu-byte arena",
                     (unsigned long long)r.lay.total, (unsigned long long)S->adm.arena().size());

@@ -304,3 +304,36 @@ def test_wait_timeout(ctx):
         srv.release(tk)
     finally:
         srv.close()
+
+
+def test_mixed_residency(ctx):
+    """Buffers in device memory are used in place, those in host memory staged through the
+    arena: every mix gives the per-frame launch's result."""
+    import torch
+    from paper_2301_11376_amd import Server
+    gb, cam, kw = make_items(SPECS[3:4])[0]
+    H, W = gb["depth"].shape
+    ref = plain(ctx, gb, cam, kw)
+    bc, _ = PY.cams(cam)
+    bp, _ = PY.params(**kw)
+    dev = PY.to_device(gb)
+    pin = {k: torch.from_numpy(np.ascontiguousarray(v)).pin_memory() for k, v in gb.items()}
+    srv = Server(ctx, 256 << 20)
+    try:
+        for mix in [("cuda", "pin", "cuda", "pin"), ("pin", "cuda", "pin", "cuda"), ("cuda", "cuda", "cuda", "pin")]:
+            src = [dev if m == "cuda" else pin for m in mix[:3]]
+            if mix[3] == "cuda":
+                out = {"ao": torch.empty((H, W), device="cuda"), "gi": torch.empty((H, W, 3), device="cuda"),
+                       "ambient": torch.empty((H, W, 3), device="cuda")}
+            else:
+                out = {"ao": torch.empty((H, W), pin_memory=True), "gi": torch.empty((H, W, 3), pin_memory=True),
+                       "ambient": torch.empty((H, W, 3), pin_memory=True)}
+            for v in out.values():
+                v.fill_(float("nan"))
+            torch.cuda.synchronize()
+            tk = srv.submit(src[0]["depth"], src[1]["normal"], src[2]["radiance"], bc, bp, out)
+            srv.wait(tk, 60000)
+            srv.release(tk)
+            same(host(out), ref, mix)
+    finally:
+        srv.close()
