@@ -14,12 +14,15 @@ from .ssvb_oracle import (  # noqa: F401
     NOISE_R2,
     NOISE_FIXED,
     NOISE_NAMES,
+    STEPS_UNIFORM,
+    STEPS_QUADRATIC,
     pcg_hash,
     pixel_hash,
     r2_constants,
     direction_lut,
     slice_noise,
     step_q4,
+    step_offset_q4,
     compute,
     sh_eval,
 )

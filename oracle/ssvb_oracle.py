@@ -50,6 +50,10 @@ listed again in the design notes):
   R19 "view-space position at step j" is the depth read from the texel containing the
       step's exact screen position, placed on that exact position's view ray (the depth
       buffer is point sampled; the sample stays in the slice plane).
+  R21 the optional "exponential" step distribution (Section 4.3: samples denser near the
+      pixel; the curve is not given) is quadratic: step j sits at ((j + 1 + xi) /
+      (N_s + 1))^2 of the reach q (N_s + 1), with the same jitter xi; in integers,
+      o_j = (((q a_j^2) >> 16) * floor(2^32 / (N_s + 1))) >> 32, a_j = 256 (j + 1) + xi8.
 """
 from __future__ import annotations
 
@@ -62,6 +66,7 @@ import numpy as np
 ROUND, PSEUDOCODE = 0, 1
 NOISE_HASH, NOISE_R2, NOISE_FIXED = 0, 1, 2
 NOISE_NAMES = {"hash": NOISE_HASH, "r2": NOISE_R2, "fixed": NOISE_FIXED}
+STEPS_UNIFORM, STEPS_QUADRATIC = 0, 1
 
 LUT_SIZE = 4096           # slice directions quantised to pi / 4096
 LUT_ONE = 4096            # fixed-point 1.0 of the direction table
@@ -99,6 +104,7 @@ class Params:
     thickness_slope: float = 0.0  # k in t_p = t0 + k z_p
     max_radius_px: float = 0.0    # 0: lattice cap only
     min_step_q4: int = 16         # shortest step, 1/16 px
+    step_distribution: int = 0    # STEPS_UNIFORM or STEPS_QUADRATIC (R21)
     hit_criterion: int = ROUND
     noise: int = NOISE_HASH
     seed: int = 0
@@ -193,6 +199,18 @@ def step_q4(z_p, cam: Camera, prm: Params):
     quot = np.minimum(quot, np.float32(q_max))
     q = np.floor(quot).astype(np.int64)
     return np.clip(q, q_min, q_max)
+
+
+def step_offset_q4(q, xi8, j, ns, dist):
+    """Offset of step j (0-based) from the pixel centre along the slice, 1/16 px.
+
+    UNIFORM (Algorithm 1): (j + 1 + xi) steps of q.  QUADRATIC (Section 4.3, reading
+    R21): the reach q (N_s + 1) times ((j + 1 + xi) / (N_s + 1))^2, in exact integers."""
+    if dist == STEPS_UNIFORM:
+        return q * (j + 1) + ((q * xi8) >> 8)
+    a = (j + 1) * 256 + xi8
+    t = (q * a * a) >> 16
+    return (t * ((1 << 32) // (ns + 1))) >> 32
 
 
 def sh_eval(coeffs, dirs):
@@ -303,7 +321,7 @@ def compute(depth, normal, radiance, cam: Camera, prm: Params, pixels=None,
         b_i = np.zeros((n, nb), dtype=bool)                    # bitmask b_i <- 0
         for side_idx, s in enumerate((1, -1)):
             for j in range(ns):
-                o = q * (j + 1) + ((q * xi8[:, i]) >> 8)       # offset, 1/16 px
+                o = step_offset_q4(q, xi8[:, i], j, ns, prm.step_distribution)  # 1/16 px
                 X = ((xs << 16) + 32768 + s * o * dx_i) >> 16
                 Y = ((ys << 16) + 32768 + s * o * dy_i) >> 16
                 if return_lattice:

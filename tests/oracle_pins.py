@@ -610,6 +610,79 @@ def pin_lattice_geometry(O):
             assert np.all(cross[fg] <= 1.5)
 
 
+def pin_quadratic_steps(O):
+    """Quadratic step distribution (Section 4.3; reading R21): the sampled texels lie at
+    ((j + 1 + xi) / (N_s + 1))^2 of the reach from the pixel (closed form of the law
+    against the lattice; xi from the pinned noise), the steps inside half the reach are
+    the first floor((N_s + 1) / sqrt 2) - 1, a plane facing the camera still sets no
+    sector, and every sector occluded in the box scene lies in the model's occluded set."""
+    gb, cam, _ = tiny_scene()
+    H, W = gb["depth"].shape
+    z = gb["depth"].astype(np.float64)
+    fg = z > 0
+    ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    for noise in (O.NOISE_FIXED, O.NOISE_HASH):
+        steps, nd = 9, 3
+        prm = O.Params(slices=nd, steps=steps, radius=1.5, thickness=0.5, noise=noise, seed=2,
+                       step_distribution=O.STEPS_QUADRATIC, min_step_q4=1)
+        r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, return_lattice=True)
+        L = r["lattice"].astype(np.float64)                      # [H, W, nd, 2, ns, 2]
+        off = L - np.stack([xs, ys], -1)[:, :, None, None, None, :]
+        dist = np.linalg.norm(off, axis=-1)                      # [H, W, nd, 2, ns]
+        q = O.step_q4(np.where(fg, z, 1.0), ocam(O, cam), prm).astype(np.float64)
+        reach = q * (steps + 1) / 16.0                            # px
+        _, xi8 = O.slice_noise(xs.reshape(-1), ys.reshape(-1), nd, noise, 2)
+        xi = xi8.reshape(H, W, nd).astype(np.float64) / 256.0
+        j = np.arange(steps)[None, None, None, None, :]
+        u = (j + 1 + xi[:, :, :, None, None]) / (steps + 1)
+        expect = reach[:, :, None, None, None] * u * u
+        # texel snapping moves a sample by at most half a pixel diagonal (0.707), the
+        # integer evaluation of the law by less than 1/16 px, the direction table's
+        # rounding (|D| = 4096 within 0.71) by 1.7e-4 of the distance
+        assert np.all(np.abs(dist - expect)[fg] <= 0.8)
+    # the steps inside half the reach
+    ns, q = 64, 1000
+    o = np.array([O.step_offset_q4(q, 0, jj, ns, O.STEPS_QUADRATIC) for jj in range(ns)])
+    assert np.all(np.diff(o) > 0)
+    assert int(np.sum(o <= q * (ns + 1) / 2)) == int(math.floor((ns + 1) / math.sqrt(2.0)))
+    # a plane facing the camera sets nothing
+    camp = make_camera(41, 31, fov_y_deg=90, pitch_deg=0)
+    gbp = plane_gbuffer(camp, (0, 0, 1), (0, 0, -4.0))
+    for t in (0.1, INF):
+        prm = O.Params(slices=3, steps=8, radius=1.5, thickness=t, noise=O.NOISE_HASH, seed=5,
+                       step_distribution=O.STEPS_QUADRATIC)
+        rp = O.compute(gbp["depth"], gbp["normal"], gbp["radiance"], ocam(O, camp), prm, return_masks=True)
+        assert np.all(rp["masks"] == 0) and np.all(rp["ao"] == 1.0) and np.all(rp["gi"] == 0.0)
+    # brute force: the samples lie between the first and the last step, so the model's
+    # occluded set over that range contains every sector the oracle sets
+    cam4 = (cam.fx, cam.fy, cam.cx, cam.cy)
+    lut_dx = [math.floor(4096 * math.cos(math.pi * k / 4096) + 0.5) for k in range(4096)]
+    lut_dy = [math.floor(4096 * math.sin(math.pi * k / 4096) + 0.5) for k in range(4096)]
+    qq, steps, nd = 40, 6, 8
+    offs = [O.step_offset_q4(qq, 0, jj, steps, O.STEPS_QUADRATIC) for jj in range(steps)]
+    lam = (min(offs) / 16.0, max(offs) / 16.0)
+    sel = _bf_pixels(gb, 40, 3)
+    nset = 0
+    for t in (0.3, INF):
+        prm = O.Params(slices=nd, steps=steps, radius=1e6, max_radius_px=qq * (steps + 1) / 16.0,
+                       thickness=t, noise=O.NOISE_FIXED, step_distribution=O.STEPS_QUADRATIC)
+        rb = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                       pixels=(sel[:, 0], sel[:, 1]), return_masks=True)
+        for idx, (y, x) in enumerate(sel):
+            for i in range(nd):
+                kk = (i * 65536) // (16 * nd)
+                ivals, _ = BF.occluded_intervals(gb["depth"].astype(np.float64), cam4, x, y,
+                                                 gb["normal"][y, x, :3].astype(np.float64),
+                                                 lut_dx[kk], lut_dy[kk], t, lam, lam)
+                m = int(rb["masks"][idx, i])
+                for bit in range(32):
+                    if (m >> bit) & 1:
+                        nset += 1
+                        centre = -math.pi / 2 + (bit + 0.5) * math.pi / 32
+                        assert BF.is_occluded(ivals, centre, 1e-7), (t, y, x, i, bit)
+    assert nset > 50
+
+
 def pin_noise_statistics(O):
     """Rotations and jitters are uniform (chi-square) and the slices of one pixel are
     spread evenly over pi; the R2 rotation is a low-discrepancy dither."""
@@ -668,4 +741,5 @@ ALL_PINS = [
     pin_side_symmetry,
     pin_lattice_geometry,
     pin_noise_statistics,
+    pin_quadratic_steps,
 ]

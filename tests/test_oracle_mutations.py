@@ -24,7 +24,7 @@ MUTATIONS = {
     "sample normal factor sign": ("np.maximum(0.0, -_dot(n_j, l_j))", "np.maximum(0.0, _dot(n_j, l_j))"),
     "GI counts all covered sectors": ("new = b_j & ~b_i", "new = b_j"),
     "ambient weight over the subregion": ("free / nb", "free / per"),
-    "first step at zero offset": ("o = q * (j + 1) +", "o = q * j +"),
+    "first step at zero offset": ("return q * (j + 1) +", "return q * j +"),
     "exact position ignores the side": ("X_e = xs + 0.5 + s * o * dx_i / 65536.0",
                                         "X_e = xs + 0.5 + o * dx_i / 65536.0"),
     "slice tangent sign": ("e = d3 - _dot(d3, v)[:, None] * v", "e = d3 + _dot(d3, v)[:, None] * v"),
@@ -50,7 +50,10 @@ MUTATIONS = {
     "GI light direction reversed": ("l_j = delta / np.linalg.norm", "l_j = -delta / np.linalg.norm"),
     "front/back not ordered": ("t_min, t_max = np.minimum(theta_f, theta_b), np.maximum(theta_f, theta_b)",
                                "t_min, t_max = theta_f, theta_b"),
-    "jitter too large": ("((q * xi8[:, i]) >> 8)", "((q * xi8[:, i]) >> 5)"),
+    "jitter too large": ("((q * xi8) >> 8)", "((q * xi8) >> 5)"),
+    "quadratic steps linear in j": ("t = (q * a * a) >> 16", "t = (q * a * 256) >> 16"),
+    "quadratic reach over N_s": ("((1 << 32) // (ns + 1))", "((1 << 32) // ns)"),
+    "quadratic steps ignore the jitter": ("a = (j + 1) * 256 + xi8", "a = (j + 1) * 256"),
     "background samples kept": ("ok &= np.isfinite(z_s) & (z_s > 0)", "ok &= np.isfinite(z_s)"),
     "step floor not clamped": ("return np.clip(q, q_min, q_max)", "return np.clip(q, 1, q_max)"),
 }
