@@ -63,6 +63,13 @@ typedef enum { SSVB_HIT_ROUND = 0, SSVB_HIT_PSEUDOCODE = 1 } ssvb_hit_criterion;
  * In HASH and R2 the jitter of slice i is pcg(x + pcg(y + pcg(seed + 1 + i))) >> 24. */
 typedef enum { SSVB_NOISE_HASH = 0, SSVB_NOISE_R2 = 1, SSVB_NOISE_FIXED = 2 } ssvb_noise;
 
+/* Placement of the N_s steps along each side of a slice.  UNIFORM (Algorithm 1): step j
+ * (0-based) at (j + 1 + xi) / (N_s + 1) of the reach.  QUADRATIC (Section 4.3 distributes
+ * samples more densely near the pixel; the curve is this library's choice): at
+ * ((j + 1 + xi) / (N_s + 1))^2 of the reach.  xi is the slice's jitter; the reach is
+ * q (N_s + 1) sixteenths of a pixel in both, q the pixel's step length. */
+typedef enum { SSVB_STEPS_UNIFORM = 0, SSVB_STEPS_QUADRATIC = 1 } ssvb_step_distribution;
+
 /* One image.  ptr: device pointer aligned to its element size.  pitch_bytes: bytes
  * between rows, 0 = dense (width * channels * element size).  dtype: ssvb_dtype.
  * channels: 1 for depth (F32 only), 3 or 4 for normals and radiance (the fourth
@@ -95,6 +102,7 @@ typedef struct {
  *  max_radius_px    0, or a cap in pixels on the projected radius (hard cap 16383)
  *  min_step_q4      shortest step in 1/16 pixel, 1..16 (16 keeps samples off the
  *                   centre pixel)
+ *  step_distribution  ssvb_step_distribution
  *  hit_criterion    ssvb_hit_criterion
  *  noise, seed      ssvb_noise and its 32-bit seed
  *  ambient_sh       L2 real spherical-harmonic probe, world space, [9][3]
@@ -103,6 +111,7 @@ typedef struct {
     int32_t slices, steps, sectors, ambient_samples;
     float radius, thickness, thickness_slope, max_radius_px;
     int32_t min_step_q4;
+    int32_t step_distribution;
     int32_t hit_criterion;
     int32_t noise;
     uint32_t seed;
@@ -146,8 +155,8 @@ const char* ssvb_status_string(ssvb_status s);
 const char* ssvb_last_error(void);
 
 /* Fill *p with the defaults: 4 slices, 16 steps, 32 sectors, 4 ambient samples,
- * radius 1, thickness 0.5, slope 0, no pixel cap, min step 16, ROUND, HASH, seed 0,
- * zero ambient probe. */
+ * radius 1, thickness 0.5, slope 0, no pixel cap, min step 16, uniform steps, ROUND,
+ * HASH, seed 0, zero ambient probe. */
 void ssvb_default_params(ssvb_params* p);
 
 /* Create a context on HIP device `device`: uploads the slice-direction table.  The

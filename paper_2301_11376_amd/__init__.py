@@ -16,5 +16,7 @@ from .binding import (  # noqa: F401
     NOISE_R2,
     NOISE_FIXED,
     NOISE_NAMES,
+    STEPS_UNIFORM,
+    STEPS_QUADRATIC,
     lib,
 )

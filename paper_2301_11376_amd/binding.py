@@ -22,6 +22,7 @@ F32, F16 = 0, 1
 HIT_ROUND, HIT_PSEUDOCODE = 0, 1
 NOISE_HASH, NOISE_R2, NOISE_FIXED = 0, 1, 2
 NOISE_NAMES = {"hash": NOISE_HASH, "r2": NOISE_R2, "fixed": NOISE_FIXED}
+STEPS_UNIFORM, STEPS_QUADRATIC = 0, 1
 
 # every symbol include/ssvb.h declares
 EXPORTED = [
@@ -48,7 +49,8 @@ class ssvb_params(ctypes.Structure):
     _fields_ = [("slices", ctypes.c_int32), ("steps", ctypes.c_int32), ("sectors", ctypes.c_int32),
                 ("ambient_samples", ctypes.c_int32), ("radius", ctypes.c_float), ("thickness", ctypes.c_float),
                 ("thickness_slope", ctypes.c_float), ("max_radius_px", ctypes.c_float),
-                ("min_step_q4", ctypes.c_int32), ("hit_criterion", ctypes.c_int32), ("noise", ctypes.c_int32),
+                ("min_step_q4", ctypes.c_int32), ("step_distribution", ctypes.c_int32),
+                ("hit_criterion", ctypes.c_int32), ("noise", ctypes.c_int32),
                 ("seed", ctypes.c_uint32), ("ambient_sh", ctypes.c_float * 27)]
 
 
@@ -192,6 +194,7 @@ class Params:
     thickness_slope: float = 0.0
     max_radius_px: float = 0.0
     min_step_q4: int = 16
+    step_distribution: int = STEPS_UNIFORM
     hit_criterion: int = HIT_ROUND
     noise: int = NOISE_HASH
     seed: int = 0
@@ -199,8 +202,8 @@ class Params:
 
     def to_c(self) -> ssvb_params:
         p = ssvb_params(self.slices, self.steps, self.sectors, self.ambient_samples, self.radius, self.thickness,
-                        self.thickness_slope, self.max_radius_px, self.min_step_q4, self.hit_criterion,
-                        self.noise, self.seed & 0xFFFFFFFF)
+                        self.thickness_slope, self.max_radius_px, self.min_step_q4, self.step_distribution,
+                        self.hit_criterion, self.noise, self.seed & 0xFFFFFFFF)
         for i, v in enumerate(self.ambient_sh):
             p.ambient_sh[i] = v
         return p

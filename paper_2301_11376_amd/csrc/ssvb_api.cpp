@@ -131,6 +131,8 @@ ssvb_status check_camera_params(const ssvb_camera* cam, const ssvb_params* p) {
         return fail(SSVB_ERR_INVALID_ARG, "max_radius_px must be finite and >= 0");
     if (p->min_step_q4 < 1 || p->min_step_q4 > 16)
         return fail(SSVB_ERR_INVALID_ARG, "min_step_q4 %d outside [1, 16]", p->min_step_q4);
+    if (p->step_distribution != SSVB_STEPS_UNIFORM && p->step_distribution != SSVB_STEPS_QUADRATIC)
+        return fail(SSVB_ERR_INVALID_ARG, "unknown step distribution %d", p->step_distribution);
     if (p->hit_criterion != SSVB_HIT_ROUND && p->hit_criterion != SSVB_HIT_PSEUDOCODE)
         return fail(SSVB_ERR_INVALID_ARG, "unknown hit criterion %d", p->hit_criterion);
     if (p->noise != SSVB_NOISE_HASH && p->noise != SSVB_NOISE_R2 && p->noise != SSVB_NOISE_FIXED)
@@ -218,6 +220,8 @@ void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, c
     A.ns = p->steps;
     A.na = p->ambient_samples;
     A.criterion = p->hit_criterion;
+    A.step_dist = p->step_distribution;
+    A.ns_recip = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)(p->steps + 1));  // steps >= 1
     A.noise = p->noise;
     A.seed = p->seed;
     uint32_t r2[3];
@@ -376,6 +380,7 @@ void ssvb_default_params(ssvb_params* p) {
     p->thickness_slope = 0.0f;
     p->max_radius_px = 0.0f;
     p->min_step_q4 = 16;
+    p->step_distribution = SSVB_STEPS_UNIFORM;
     p->hit_criterion = SSVB_HIT_ROUND;
     p->noise = SSVB_NOISE_HASH;
     p->seed = 0;

@@ -41,6 +41,8 @@ struct FrameArgs {
     // sampling
     int32_t nd, ns, na;
     int32_t criterion, noise;
+    int32_t step_dist;      // ssvb_step_distribution
+    uint32_t ns_recip;      // floor(2^32 / (N_s + 1)), for quadratic steps
     uint32_t seed;
     uint32_t r2a1, r2a2, r2a3;
     float c_step;           // 16 radius fy / (N_s + 1), FP32

@@ -66,6 +66,18 @@ __device__ __forceinline__ uint32_t jitter8(const FrameArgs& A, int x, int y, in
 // address space lets it use global (rather than flat) loads and stores.
 #define GMEM __attribute__((address_space(1)))
 
+// Offset of step j (0-based) from the pixel centre along the slice, in 1/16 pixel.
+// Uniform steps (Algorithm 1): (j + 1 + xi) steps of q, jit = (q xi8) >> 8.  Quadratic
+// steps (Section 4.3: denser near the pixel): the reach q (N_s + 1) times
+// ((j + 1 + xi) / (N_s + 1))^2, in integers: ((q a^2) >> 16) * floor(2^32 / (N_s + 1))
+// >> 32 with a = 256 (j + 1) + xi8 (q a^2 < 2^44, the second product < 2^50).
+__device__ __forceinline__ int step_offset(const FrameArgs& A, int q, int jit, int xi8, int j) {
+    if (A.step_dist == SSVB_STEPS_UNIFORM) return q * (j + 1) + jit;
+    const uint64_t a = (uint64_t)(uint32_t)((j + 1) * 256 + xi8);
+    const uint64_t t = ((uint64_t)(uint32_t)q * (a * a)) >> 16;
+    return (int)((t * (uint64_t)A.ns_recip) >> 32);
+}
+
 __device__ __forceinline__ uint32_t depth_off(const FrameArgs& A, int X, int Y) {
     return (uint32_t)Y * (uint32_t)A.depth_pitch + (uint32_t)X * 4u;
 }
@@ -398,12 +410,13 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
         const int k = (int)(((uint32_t)i * 65536u + rho) / (uint32_t)(16 * A.nd));
         const GMEM int* dk = (const GMEM int*)A.lut + 2 * k;
         const int2 D = make_int2(dk[0], dk[1]);
-        const int jit = (q * (int)jitter8(A, x, y, i)) >> 8;
+        const int xi8 = (int)jitter8(A, x, y, i);
+        const int jit = (q * xi8) >> 8;
         if (MODE == MODE_LATTICE) {
             for (int side = 0; side < 2; ++side) {
                 const int s = side ? -1 : 1;
                 for (int j = 0; j < A.ns; ++j) {
-                    const int o = q * (j + 1) + jit;
+                    const int o = step_offset(A, q, jit, xi8, j);
                     int32_t* d = dbg_i + ((((int64_t)i * 2 + side) * A.ns + j) * 2);
                     d[0] = (x16 + s * o * D.x) >> 16;
                     d[1] = (y16 + s * o * D.y) >> 16;
@@ -420,7 +433,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
             float zs[kBatch][2];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
-                const int o = q * (j0 + u + 1) + jit;
+                const int o = step_offset(A, q, jit, xi8, j0 + u);
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
                     const int so = side ? -o : o;
@@ -434,7 +447,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
             for (int u = 0; u < kBatch; ++u) {
                 const int j = j0 + u;
                 if (j >= A.ns) break;
-                const int o = q * (j + 1) + jit;
+                const int o = step_offset(A, q, jit, xi8, j);
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
                     const int s = side ? -1 : 1;

@@ -55,7 +55,7 @@ MIXED = [
                                 noise=O.NOISE_R2, seed=4)),
     (1, 1, 5, False, 3, dict(slices=1, steps=1, radius=1.0, noise=O.NOISE_FIXED)),
     (96, 64, 6, False, 3, dict(slices=5, steps=7, radius=1.5, thickness=0.3, noise=O.NOISE_HASH, seed=6,
-                               ambient_samples=8)),
+                               ambient_samples=8, step_distribution=1)),
 ]
 
 

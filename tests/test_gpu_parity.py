@@ -69,6 +69,9 @@ LATTICE_CASES = [
     dict(slices=3, steps=5, radius=0.3, noise=O.NOISE_FIXED),
     dict(slices=8, steps=3, radius=5.0, noise=O.NOISE_HASH, seed=0xFFFFFFFF, max_radius_px=20.0),
     dict(slices=1, steps=40, radius=1.0, noise=O.NOISE_R2, seed=9, min_step_q4=1),
+    dict(slices=3, steps=12, radius=2.5, noise=O.NOISE_HASH, seed=3, step_distribution=1),
+    dict(slices=2, steps=1024, radius=4.0, noise=O.NOISE_R2, seed=5, step_distribution=1, min_step_q4=1),
+    dict(slices=4, steps=7, radius=1.5, noise=O.NOISE_FIXED, step_distribution=1),
 ]
 
 
@@ -150,6 +153,10 @@ VARIANTS = {
     "capped_subpixel": dict(slices=2, steps=20, radius=4.0, noise=O.NOISE_HASH, seed=18, max_radius_px=6.0,
                             min_step_q4=2),
     "zero_thickness": dict(slices=2, steps=6, radius=1.5, thickness=0.0, noise=O.NOISE_HASH, seed=19),
+    "quadratic_steps": dict(slices=3, steps=12, radius=2.0, thickness=0.3, noise=O.NOISE_R2, seed=20,
+                            step_distribution=1),
+    "quadratic_pseudocode_tinf": dict(slices=2, steps=8, radius=1.5, thickness=INF, noise=O.NOISE_HASH, seed=21,
+                                      step_distribution=1, hit_criterion=1),
 }
 
 
