@@ -24,5 +24,8 @@ from .ssvb_oracle import (  # noqa: F401
     step_q4,
     step_offset_q4,
     compute,
+    bilateral_upsample,
+    UPSAMPLE_SIGMA,
+    UPSAMPLE_FLOOR,
     sh_eval,
 )

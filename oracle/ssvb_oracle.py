@@ -54,6 +54,13 @@ listed again in the design notes):
       pixel; the curve is not given) is quadratic: step j sits at ((j + 1 + xi) /
       (N_s + 1))^2 of the reach q (N_s + 1), with the same jitter xi; in integers,
       o_j = (((q a_j^2) >> 16) * floor(2^32 / (N_s + 1))) >> 32, a_j = 256 (j + 1) + xi8.
+  R22 half resolution (Section 4.3: the gather runs on a quarter of the pixels, then a
+      "classic bilateral upsampler" fills the image; neither is specified further): the
+      gather runs on the pixels whose x and y are both even, reading the full-resolution
+      G-buffer; every other pixel takes the average of its 1, 2 or 4 nearest computed
+      pixels with weights bilinear x (1e-3 + exp(-((z - z_n) / (0.05 z))^2)), background
+      neighbours excluded; a background pixel, or one with no computed foreground
+      neighbour, outputs AO = 1, GI = 0, ambient = 0.
 """
 from __future__ import annotations
 
@@ -105,6 +112,7 @@ class Params:
     max_radius_px: float = 0.0    # 0: lattice cap only
     min_step_q4: int = 16         # shortest step, 1/16 px
     step_distribution: int = 0    # STEPS_UNIFORM or STEPS_QUADRATIC (R21)
+    resolution: int = 1           # 1: every pixel; 2: half resolution + upsampling (R22)
     hit_criterion: int = ROUND
     noise: int = NOISE_HASH
     seed: int = 0
@@ -250,6 +258,43 @@ def _bits(lo, hi, nb):
 # the method
 # ----------------------------------------------------------------------------------------
 
+UPSAMPLE_SIGMA = 0.05    # relative depth scale of the upsampling weights (R22)
+UPSAMPLE_FLOOR = 1e-3    # weight floor: depth-incompatible neighbours still blend
+
+
+def bilateral_upsample(depth, ao, gi, amb):
+    """Fill the pixels with an odd coordinate from the computed (even, even) pixels
+    (reading R22).  ``ao`` [H, W], ``gi`` / ``amb`` [H, W, 3] hold the gather's results at
+    the even pixels; returns full images (the even pixels unchanged)."""
+    H, W = depth.shape
+    z = np.asarray(depth, dtype=np.float32).astype(np.float64)
+    fg = np.isfinite(z) & (z > 0)
+    ao_o, gi_o, amb_o = ao.copy(), gi.copy(), amb.copy()
+    for y in range(H):
+        ny = [(y, 1.0)] if y % 2 == 0 else ([(y - 1, 0.5), (y + 1, 0.5)] if y + 1 < H else [(y - 1, 1.0)])
+        for x in range(W):
+            if x % 2 == 0 and y % 2 == 0:
+                continue
+            nx = [(x, 1.0)] if x % 2 == 0 else ([(x - 1, 0.5), (x + 1, 0.5)] if x + 1 < W else [(x - 1, 1.0)])
+            sw, sao, sgi, samb = 0.0, 0.0, np.zeros(3), np.zeros(3)
+            if fg[y, x]:
+                for yy, by in ny:
+                    for xx, bx in nx:
+                        if not fg[yy, xx]:
+                            continue
+                        d = (z[y, x] - z[yy, xx]) / (UPSAMPLE_SIGMA * z[y, x])
+                        w = by * bx * (UPSAMPLE_FLOOR + math.exp(-d * d))
+                        sw += w
+                        sao += w * ao[yy, xx]
+                        sgi += w * gi[yy, xx]
+                        samb += w * amb[yy, xx]
+            if sw > 0.0:
+                ao_o[y, x], gi_o[y, x], amb_o[y, x] = sao / sw, sgi / sw, samb / sw
+            else:
+                ao_o[y, x], gi_o[y, x], amb_o[y, x] = 1.0, 0.0, 0.0
+    return ao_o, gi_o, amb_o
+
+
 def compute(depth, normal, radiance, cam: Camera, prm: Params, pixels=None,
             return_masks=False, return_lattice=False, return_endpoints=False,
             index_bias=None):
@@ -266,6 +311,23 @@ def compute(depth, normal, radiance, cam: Camera, prm: Params, pixels=None,
     those integers; the mismatch tracer uses it to flip a near-tie rounding.
     """
     H, W = depth.shape
+    if getattr(prm, "resolution", 1) == 2:
+        # half resolution (R22): the gather on the even pixels, then the upsampler
+        if pixels is not None or return_masks or return_lattice or return_endpoints:
+            raise ValueError("half resolution computes whole images of AO, GI and ambient only")
+        from dataclasses import replace
+        ye, xe = np.meshgrid(np.arange(0, H, 2), np.arange(0, W, 2), indexing="ij")
+        part = compute(depth, normal, radiance, cam, replace(prm, resolution=1),
+                       pixels=(ye.reshape(-1), xe.reshape(-1)))
+        ao = np.ones((H, W))
+        gi = np.zeros((H, W, 3))
+        amb = np.zeros((H, W, 3))
+        ao[ye, xe] = part["ao"].reshape(ye.shape)
+        gi[ye, xe] = part["gi"].reshape(ye.shape + (3,))
+        amb[ye, xe] = part["ambient"].reshape(ye.shape + (3,))
+        ao, gi, amb = bilateral_upsample(depth, ao, gi, amb)
+        z = np.asarray(depth, dtype=np.float32)
+        return {"ao": ao, "gi": gi, "ambient": amb, "valid": np.isfinite(z) & (z > 0)}
     depth64 = np.asarray(depth, dtype=np.float32).astype(np.float64)
     nrm64 = np.asarray(normal)[..., :3].astype(np.float64)
     rad64 = np.asarray(radiance)[..., :3].astype(np.float64)

@@ -683,6 +683,62 @@ def pin_quadratic_steps(O):
     assert nset > 50
 
 
+def pin_half_resolution(O):
+    """Half resolution (Section 4.3; reading R22): the computed pixels equal the full
+    resolution gather there; on equal depths the upsampler reproduces a linear field
+    exactly (bilinear interpolation); across a depth edge a pixel takes at most the weight
+    floor from the far layer; background pixels and foreground pixels with no computed
+    foreground neighbour take AO = 1, GI = 0, ambient = 0; a constant probe on a plane
+    gives a constant ambient."""
+    gb, cam, sc = tiny_scene()
+    H, W = gb["depth"].shape
+    kw = dict(slices=3, steps=6, radius=1.2, thickness=0.4, noise=O.NOISE_HASH, seed=3,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    full = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), O.Params(**kw))
+    half = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), O.Params(resolution=2, **kw))
+    for k in ("ao", "gi", "ambient"):
+        assert np.array_equal(half[k][0::2, 0::2], full[k][0::2, 0::2])
+        assert np.all(np.isfinite(half[k]))
+    # linear field on equal depths (9 x 7: odd sizes exercise the last row and column)
+    Hh, Wh = 7, 9
+    depth = np.full((Hh, Wh), 4.0, dtype=np.float32)
+    yy, xx = np.meshgrid(np.arange(Hh, dtype=np.float64), np.arange(Wh, dtype=np.float64), indexing="ij")
+    lin = 0.2 + 0.03 * xx - 0.05 * yy
+    vec = np.stack([lin, 2 * lin, 0.5 - lin], -1)
+    ev = np.zeros((Hh, Wh), bool)
+    ev[0::2, 0::2] = True
+    ao0 = np.where(ev, lin, -9.0)
+    gi0 = np.where(ev[..., None], vec, -9.0)
+    a, g, m = O.bilateral_upsample(depth, ao0, gi0, gi0.copy())
+    inner = (xx <= 2 * ((Wh - 1) // 2)) & (yy <= 2 * ((Hh - 1) // 2))   # inside the computed hull
+    assert np.allclose(a[inner], lin[inner], atol=1e-12, rtol=0)
+    assert np.allclose(g[inner], vec[inner], atol=1e-12, rtol=0) and np.allclose(m[inner], vec[inner], atol=1e-12)
+    # depth edge: near layer (z = 2) left of column 5, far layer (z = 10) from it on
+    He, We = 5, 11
+    depth = np.where(np.arange(We)[None, :] < 5, 2.0, 10.0).astype(np.float32) * np.ones((He, 1), np.float32)
+    val = np.where(np.arange(We)[None, :] < 5, 0.0, 1.0) * np.ones((He, 1))
+    a, g, _ = O.bilateral_upsample(depth, val.copy(), np.repeat(val[..., None], 3, -1),
+                                   np.repeat(val[..., None], 3, -1))
+    floor = O.UPSAMPLE_FLOOR
+    assert np.all(np.abs(a - val) <= floor / (1 + floor) + 1e-15)
+    # background and isolated foreground pixels
+    depth = np.zeros((5, 5), np.float32)
+    depth[1, 1] = 3.0                     # foreground with only background computed neighbours
+    depth[4, 4] = 3.0                     # computed foreground pixel, not a neighbour of (1, 1)
+    a, g, m = O.bilateral_upsample(depth, np.full((5, 5), 0.25), np.full((5, 5, 3), 0.5), np.full((5, 5, 3), 0.5))
+    assert a[1, 1] == 1.0 and np.all(g[1, 1] == 0.0) and np.all(m[1, 1] == 0.0)
+    assert a[0, 1] == 1.0 and np.all(g[0, 1] == 0.0)          # background
+    assert a[4, 4] == 0.25                                     # computed pixel unchanged
+    # a camera-facing plane under a constant probe: ambient = C at every pixel
+    camp = make_camera(21, 15, fov_y_deg=90, pitch_deg=0)
+    gbp = plane_gbuffer(camp, (0, 0, 1), (0, 0, -4.0))
+    C = (0.3, 0.5, 0.7)
+    rp = O.compute(gbp["depth"], gbp["normal"], gbp["radiance"], ocam(O, camp),
+                   O.Params(slices=2, steps=5, radius=1.0, noise=O.NOISE_HASH, resolution=2, ambient_sh=const_sh(C)))
+    assert np.all(rp["ao"] == 1.0) and np.all(rp["gi"] == 0.0)
+    assert np.allclose(rp["ambient"], np.asarray(C), rtol=1e-7, atol=0)
+
+
 def pin_noise_statistics(O):
     """Rotations and jitters are uniform (chi-square) and the slices of one pixel are
     spread evenly over pi; the R2 rotation is a low-discrepancy dither."""
@@ -742,4 +798,5 @@ ALL_PINS = [
     pin_lattice_geometry,
     pin_noise_statistics,
     pin_quadratic_steps,
+    pin_half_resolution,
 ]

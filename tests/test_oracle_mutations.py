@@ -54,6 +54,10 @@ MUTATIONS = {
     "quadratic steps linear in j": ("t = (q * a * a) >> 16", "t = (q * a * 256) >> 16"),
     "quadratic reach over N_s": ("((1 << 32) // (ns + 1))", "((1 << 32) // ns)"),
     "quadratic steps ignore the jitter": ("a = (j + 1) * 256 + xi8", "a = (j + 1) * 256"),
+    "upsampling ignores depth": ("(UPSAMPLE_FLOOR + math.exp(-d * d))", "(UPSAMPLE_FLOOR + 1.0)"),
+    "upsampling not normalised": ("sao / sw, sgi / sw, samb / sw", "sao, sgi, samb"),
+    "upsampling takes the far neighbour twice": ("[(y - 1, 0.5), (y + 1, 0.5)]", "[(y + 1, 0.5), (y + 1, 0.5)]"),
+    "half resolution samples odd pixels": ("np.arange(0, H, 2), np.arange(0, W, 2)", "np.arange(1, H, 2), np.arange(1, W, 2)"),
     "background samples kept": ("ok &= np.isfinite(z_s) & (z_s > 0)", "ok &= np.isfinite(z_s)"),
     "step floor not clamped": ("return np.clip(q, q_min, q_max)", "return np.clip(q, 1, q_max)"),
 }
