@@ -103,6 +103,13 @@ typedef struct {
  *  min_step_q4      shortest step in 1/16 pixel, 1..16 (16 keeps samples off the
  *                   centre pixel)
  *  step_distribution  ssvb_step_distribution
+ *  resolution       1: every pixel is gathered; 2: half resolution (Section 4.3): only
+ *                   pixels with both coordinates even are gathered (reading the full
+ *                   G-buffer), every other pixel averages its 1, 2 or 4 nearest gathered
+ *                   pixels with weights bilinear x (1e-3 + exp(-((z - z_n)/(0.05 z))^2))
+ *                   (background neighbours excluded; none left: AO 1, GI 0, ambient 0).
+ *                   ssvb_compute only (batches and servers: SSVB_ERR_UNSUPPORTED); no
+ *                   slice masks.
  *  hit_criterion    ssvb_hit_criterion
  *  noise, seed      ssvb_noise and its 32-bit seed
  *  ambient_sh       L2 real spherical-harmonic probe, world space, [9][3]
@@ -112,6 +119,7 @@ typedef struct {
     float radius, thickness, thickness_slope, max_radius_px;
     int32_t min_step_q4;
     int32_t step_distribution;
+    int32_t resolution;
     int32_t hit_criterion;
     int32_t noise;
     uint32_t seed;
@@ -155,8 +163,8 @@ const char* ssvb_status_string(ssvb_status s);
 const char* ssvb_last_error(void);
 
 /* Fill *p with the defaults: 4 slices, 16 steps, 32 sectors, 4 ambient samples,
- * radius 1, thickness 0.5, slope 0, no pixel cap, min step 16, uniform steps, ROUND,
- * HASH, seed 0, zero ambient probe. */
+ * radius 1, thickness 0.5, slope 0, no pixel cap, min step 16, uniform steps, full
+ * resolution, ROUND, HASH, seed 0, zero ambient probe. */
 void ssvb_default_params(ssvb_params* p);
 
 /* Create a context on HIP device `device`: uploads the slice-direction table.  The

@@ -50,7 +50,7 @@ class ssvb_params(ctypes.Structure):
                 ("ambient_samples", ctypes.c_int32), ("radius", ctypes.c_float), ("thickness", ctypes.c_float),
                 ("thickness_slope", ctypes.c_float), ("max_radius_px", ctypes.c_float),
                 ("min_step_q4", ctypes.c_int32), ("step_distribution", ctypes.c_int32),
-                ("hit_criterion", ctypes.c_int32), ("noise", ctypes.c_int32),
+                ("resolution", ctypes.c_int32), ("hit_criterion", ctypes.c_int32), ("noise", ctypes.c_int32),
                 ("seed", ctypes.c_uint32), ("ambient_sh", ctypes.c_float * 27)]
 
 
@@ -195,6 +195,7 @@ class Params:
     max_radius_px: float = 0.0
     min_step_q4: int = 16
     step_distribution: int = STEPS_UNIFORM
+    resolution: int = 1
     hit_criterion: int = HIT_ROUND
     noise: int = NOISE_HASH
     seed: int = 0
@@ -203,7 +204,7 @@ class Params:
     def to_c(self) -> ssvb_params:
         p = ssvb_params(self.slices, self.steps, self.sectors, self.ambient_samples, self.radius, self.thickness,
                         self.thickness_slope, self.max_radius_px, self.min_step_q4, self.step_distribution,
-                        self.hit_criterion, self.noise, self.seed & 0xFFFFFFFF)
+                        self.resolution, self.hit_criterion, self.noise, self.seed & 0xFFFFFFFF)
         for i, v in enumerate(self.ambient_sh):
             p.ambient_sh[i] = v
         return p

@@ -133,6 +133,8 @@ ssvb_status check_camera_params(const ssvb_camera* cam, const ssvb_params* p) {
         return fail(SSVB_ERR_INVALID_ARG, "min_step_q4 %d outside [1, 16]", p->min_step_q4);
     if (p->step_distribution != SSVB_STEPS_UNIFORM && p->step_distribution != SSVB_STEPS_QUADRATIC)
         return fail(SSVB_ERR_INVALID_ARG, "unknown step distribution %d", p->step_distribution);
+    if (p->resolution != 1 && p->resolution != 2)
+        return fail(SSVB_ERR_INVALID_ARG, "resolution divisor %d (need 1 or 2)", p->resolution);
     if (p->hit_criterion != SSVB_HIT_ROUND && p->hit_criterion != SSVB_HIT_PSEUDOCODE)
         return fail(SSVB_ERR_INVALID_ARG, "unknown hit criterion %d", p->hit_criterion);
     if (p->noise != SSVB_NOISE_HASH && p->noise != SSVB_NOISE_R2 && p->noise != SSVB_NOISE_FIXED)
@@ -166,8 +168,9 @@ void set_launch(FrameArgs& A, LaunchShape L) {
     A.tile_w = L.tile_w;
     A.tile_h = L.tile_h;
     A.lp = L.lp;
-    A.tiles_x = (A.W + A.tile_w - 1) / A.tile_w;
-    A.tiles_y = (A.H + A.tile_h - 1) / A.tile_h;
+    const int gw = (A.W + A.sub - 1) / A.sub, gh = (A.H + A.sub - 1) / A.sub;  // computed pixel grid
+    A.tiles_x = (gw + A.tile_w - 1) / A.tile_w;
+    A.tiles_y = (gh + A.tile_h - 1) / A.tile_h;
     A.strip = L.strip > 0 ? L.strip : 1;
     if (A.strip > A.tiles_x) A.strip = A.tiles_x > 0 ? A.tiles_x : 1;
 }
@@ -221,6 +224,7 @@ void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, c
     A.na = p->ambient_samples;
     A.criterion = p->hit_criterion;
     A.step_dist = p->step_distribution;
+    A.sub = p->resolution == 2 ? 2 : 1;
     A.ns_recip = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)(p->steps + 1));  // steps >= 1
     A.noise = p->noise;
     A.seed = p->seed;
@@ -381,6 +385,7 @@ void ssvb_default_params(ssvb_params* p) {
     p->max_radius_px = 0.0f;
     p->min_step_q4 = 16;
     p->step_distribution = SSVB_STEPS_UNIFORM;
+    p->resolution = 1;
     p->hit_criterion = SSVB_HIT_ROUND;
     p->noise = SSVB_NOISE_HASH;
     p->seed = 0;
@@ -470,6 +475,8 @@ ssvb_status ssvb_validate(const ssvb_image* depth, const ssvb_image* normal, con
     if ((s = check_out_pitch(out->ambient_pitch_bytes, (int64_t)W * 12, "ambient"))) return s;
     if (out->masks && (s = check_out_pitch(out->masks_pitch_bytes, (int64_t)W * params->slices * 4, "masks")))
         return s;
+    if (out->masks && params->resolution == 2)
+        return fail(SSVB_ERR_INVALID_ARG, "slice masks exist only for computed pixels: not with half resolution");
     return SSVB_OK;
 }
 
@@ -491,6 +498,7 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     hipError_t e = hipSuccess;
     if (ctx->ring_pending[r]) e = hipEventSynchronize(ctx->ring_ev[r]);
     if (e == hipSuccess) e = launch_plain(A, ctx->d_ring + r * kRingStride, ctx->frame_grid, (hipStream_t)hip_stream);
+    if (e == hipSuccess && A.sub == 2) e = launch_upsample(A, (hipStream_t)hip_stream);
     if (e == hipSuccess) e = hipEventRecord(ctx->ring_ev[r], (hipStream_t)hip_stream);
     if (e == hipSuccess) ctx->ring_pending[r] = true;
     if (prev != ctx->device) (void)hipSetDevice(prev);
@@ -505,6 +513,8 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
         const ssvb_frame& F = frames[f];
         ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
         if (s) return fail(s, "frame %d: %s", f, last_error().c_str());
+        if (F.params.resolution != 1)
+            return fail(SSVB_ERR_UNSUPPORTED, "frame %d: batches run at full resolution", f);
     }
     int prev = 0;
     (void)hipGetDevice(&prev);

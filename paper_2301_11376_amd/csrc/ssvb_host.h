@@ -57,6 +57,8 @@ void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames,
 // workgroups.
 hipError_t launch_plain(const FrameArgs& A, uint32_t* queues, int grid, hipStream_t stream);
 int frame_blocks_per_cu();
+// Half resolution: fill the pixels with an odd coordinate from the computed ones.
+hipError_t launch_upsample(const FrameArgs& A, hipStream_t stream);
 hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream);
 hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t stream);
 hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, int grid,

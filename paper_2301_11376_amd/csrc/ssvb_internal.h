@@ -59,6 +59,9 @@ struct FrameArgs {
     // launch shape: tile_w x tile_h pixels per workgroup; tiles are walked in vertical
     // strips of `strip` tiles, and the walk is cut into one contiguous run per XCD
     int32_t tile_w, tile_h, tiles_x, tiles_y, strip;
+    // pixels the gather computes: every pixel (sub = 1), or those with both coordinates
+    // even (sub = 2, half resolution; the upsampler fills the rest)
+    int32_t sub;
     // lanes per pixel: the N_d slices of a pixel are split over lp adjacent lanes;
     // tile_w * tile_h * lp = 256 threads per workgroup
     int32_t lp;

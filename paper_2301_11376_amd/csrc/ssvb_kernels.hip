@@ -586,8 +586,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             int tx, ty;
             walk_tile(F, first + item, tx, ty);
             const int lp = F.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
-            const int x = tx * F.tile_w + px % F.tile_w;
-            const int y = ty * F.tile_h + px / F.tile_w;
+            const int x = (tx * F.tile_w + px % F.tile_w) * F.sub;
+            const int y = (ty * F.tile_h + px / F.tile_w) * F.sub;
             if (x < F.W && y < F.H) gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT>(F, L, x, y, li, lp, nullptr, nullptr);
         }
     }
@@ -648,12 +648,61 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 if (item >= count) break;
                 int tx, ty;
                 walk_tile(A, first + item, tx, ty);
-                const int x = tx * A.tile_w + px % A.tile_w;
-                const int y = ty * A.tile_h + px / A.tile_w;
+                const int x = (tx * A.tile_w + px % A.tile_w) * A.sub;
+                const int y = (ty * A.tile_h + px / A.tile_w) * A.sub;
                 if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1>(A, L, x, y, li, lp, nullptr, nullptr);
             }
         }
     }
+}
+
+// Half resolution: every pixel with an odd coordinate takes the average of its 1, 2 or
+// 4 nearest computed (even, even) pixels, weighted bilinear x (1e-3 + exp(-(dz /
+// (0.05 z))^2)); background neighbours are left out; a background pixel, or one with no
+// computed foreground neighbour, gets AO = 1, GI = 0, ambient = 0.  Reads only computed
+// pixels and writes only the others, so it works in place on the outputs.
+__global__ __launch_bounds__(kBlock) void upsample_half(FrameArgs A) {
+    const int x = (int)(blockIdx.x * 16 + threadIdx.x % 16), y = (int)(blockIdx.y * 16 + threadIdx.x / 16);
+    if (x >= A.W || y >= A.H || ((x | y) & 1) == 0) return;
+    const float z = depth_load(A, depth_off(A, x, y));
+    float sw = 0.0f, sa = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, m0 = 0.0f, m1 = 0.0f, m2 = 0.0f;
+    if (is_geometry(z)) {
+        const int x0 = x & ~1, y0 = y & ~1;
+        const int nx = (x & 1) && x + 1 < A.W ? 2 : 1, ny = (y & 1) && y + 1 < A.H ? 2 : 1;
+        const float bx = nx == 2 ? 0.5f : 1.0f, by = ny == 2 ? 0.5f : 1.0f;
+        const float inv = 1.0f / (0.05f * z);
+        for (int j = 0; j < ny; ++j) {
+            for (int i = 0; i < nx; ++i) {
+                const int xn = x0 + 2 * i, yn = y0 + 2 * j;
+                const float zn = depth_load(A, depth_off(A, xn, yn));
+                if (!is_geometry(zn)) continue;
+                const float d = (z - zn) * inv;
+                const float w = bx * by * (1e-3f + expf(-d * d));
+                const GMEM float* g = (const GMEM float*)((const GMEM char*)A.gi + (int64_t)yn * A.gi_pitch) + 3 * xn;
+                const GMEM float* m = (const GMEM float*)((const GMEM char*)A.amb + (int64_t)yn * A.amb_pitch) + 3 * xn;
+                sw += w;
+                sa = fmaf(w, *(const GMEM float*)((const GMEM char*)A.ao + (int64_t)yn * A.ao_pitch + 4 * xn), sa);
+                s0 = fmaf(w, g[0], s0);
+                s1 = fmaf(w, g[1], s1);
+                s2 = fmaf(w, g[2], s2);
+                m0 = fmaf(w, m[0], m0);
+                m1 = fmaf(w, m[1], m1);
+                m2 = fmaf(w, m[2], m2);
+            }
+        }
+    }
+    float ao = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    if (sw > 0.0f) {
+        const float r = 1.0f / sw;
+        ao = sa * r;
+        g0 = s0 * r, g1 = s1 * r, g2 = s2 * r;
+        a0 = m0 * r, a1 = m1 * r, a2 = m2 * r;
+    }
+    *(GMEM float*)((GMEM char*)A.ao + (int64_t)y * A.ao_pitch + 4 * (int64_t)x) = ao;
+    GMEM float* g = (GMEM float*)((GMEM char*)A.gi + (int64_t)y * A.gi_pitch) + 3 * (int64_t)x;
+    g[0] = g0, g[1] = g1, g[2] = g2;
+    GMEM float* m = (GMEM float*)((GMEM char*)A.amb + (int64_t)y * A.amb_pitch) + 3 * (int64_t)x;
+    m[0] = a0, m[1] = a1, m[2] = a2;
 }
 
 __global__ void reset_queues(uint32_t* q) {
@@ -707,6 +756,11 @@ hipError_t launch_plain(const FrameArgs& A, uint32_t* queues, int grid, hipStrea
         if (tinf) launch_fmt<SSVB_HIT_PSEUDOCODE, true>(A, queues, grid, stream);
         else launch_fmt<SSVB_HIT_PSEUDOCODE, false>(A, queues, grid, stream);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample(const FrameArgs& A, hipStream_t stream) {
+    hipLaunchKernelGGL(upsample_half, dim3((A.W + 15) / 16, (A.H + 15) / 16), dim3(kBlock), 0, stream, A);
     return hipGetLastError();
 }
 

@@ -386,6 +386,7 @@ ssvb_status ssvb_server_submit(ssvb_server* S, const ssvb_frame* frame, uint64_t
     ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
     if (s) return s;
     if (F.out.masks) return fail(SSVB_ERR_INVALID_ARG, "served requests do not return slice masks");
+    if (F.params.resolution != 1) return fail(SSVB_ERR_UNSUPPORTED, "served requests run at full resolution");
     Request r;
     r.caller = F;
     r.lay = layout_of(F);

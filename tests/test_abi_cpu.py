@@ -45,7 +45,7 @@ def test_status_strings(B):
 def test_default_params(B):
     p = B.default_params()
     assert (p.slices, p.steps, p.sectors, p.ambient_samples, p.min_step_q4) == (4, 16, 32, 4, 16)
-    assert (p.radius, p.thickness, p.hit_criterion, p.noise, p.step_distribution) == (1.0, 0.5, 0, 0, 0)
+    assert (p.radius, p.thickness, p.hit_criterion, p.noise, p.step_distribution, p.resolution) == (1.0, 0.5, 0, 0, 0, 1)
     d = B.Params()
     assert (d.slices, d.steps, d.sectors, d.ambient_samples, d.min_step_q4) == (4, 16, 32, 4, 16)
 
@@ -85,6 +85,7 @@ def test_validate_accepts_good_frames(B):
     assert status(B, frame(B)) == 0
     assert status(B, frame(B, p=setter("thickness", math.inf))) == 0
     assert status(B, frame(B, p=setter("step_distribution", 1))) == 0
+    assert status(B, frame(B, p=setter("resolution", 2))) == 0
     assert status(B, frame(B, W=16384, H=1)) == 0
     assert status(B, frame(B, W=0, H=0, d=setter("ptr", None), n=setter("ptr", None),
                            o=setter("ao", None))) == 0
@@ -114,6 +115,8 @@ BAD = {
     "min step 17": dict(p=setter("min_step_q4", 17)),
     "criterion 2": dict(p=setter("hit_criterion", 2)),
     "step distribution 2": dict(p=setter("step_distribution", 2)),
+    "resolution 3": dict(p=setter("resolution", 3)),
+    "resolution 0": dict(p=setter("resolution", 0)),
     "noise 5": dict(p=setter("noise", 5)),
     "wide image": dict(c=setter("width", 16385)),
     "zero focal": dict(c=setter("fx", 0.0)),
@@ -126,6 +129,12 @@ BAD = {
 def test_validate_rejects(B, case):
     assert status(B, frame(B, **BAD[case])) == 1, case
     assert B.lib().ssvb_last_error().decode() != ""
+
+
+def test_validate_half_resolution_without_masks(B):
+    def half(p):
+        p.resolution = 2
+    assert status(B, frame(B, p=half, o=setter("masks", FAKE))) == 1
 
 
 def test_validate_unsupported_sectors(B):

@@ -311,3 +311,40 @@ def test_many_launches_two_streams(ctx):
     for i, o in enumerate(outs):
         for k in ("ao", "gi", "ambient"):
             assert torch.equal(o[k], ref[k]), (i, k)
+
+
+HALF_CASES = {
+    "uniform": dict(slices=3, steps=6, radius=1.2, thickness=0.4, noise=O.NOISE_HASH, seed=31),
+    "table2_f": dict(slices=2, steps=16, radius=4.0, thickness=0.2, noise=O.NOISE_R2, seed=32,
+                     step_distribution=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(HALF_CASES))
+@pytest.mark.parametrize("size", [(64, 48), (67, 45)])
+def test_half_resolution(ctx, name, size):
+    """Half resolution: the gathered (even, even) pixels are the full-resolution gather's,
+    bit for bit (whose parity with the oracle is checked first); the GPU's FP32 upsampler
+    matches the oracle's FP64 one applied to the same gathered values; the whole image
+    matches the oracle's half-resolution result."""
+    import torch
+    gb, cam, sc = tiny(*size)
+    kw = dict(HALF_CASES[name], ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    log(f"half resolution {name} {size}")
+    _, full = run_case(ctx, gb, cam, **kw)
+    bc, oc = PY.cams(cam)
+    bp, op = PY.params(resolution=2, **kw)
+    t = PY.to_device(gb)
+    half = ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp)
+    torch.cuda.synchronize()
+    half = {k: v.cpu().numpy() for k, v in half.items()}
+    for k in ("ao", "gi", "ambient"):
+        assert np.array_equal(half[k][0::2, 0::2].view(np.uint32), full[k][0::2, 0::2].view(np.uint32)), k
+    a, g, m = O.bilateral_upsample(gb["depth"], half["ao"].astype(np.float64), half["gi"].astype(np.float64),
+                                   half["ambient"].astype(np.float64))
+    err = max(np.abs(half["ao"] - a).max(), np.abs(half["gi"] - g).max(), np.abs(half["ambient"] - m).max())
+    log(f"  upsampler max |FP32 - FP64| = {err:.3e}")
+    assert err <= 1e-5
+    ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op)
+    for k in ("ao", "gi", "ambient"):
+        assert np.abs(half[k] - ref[k]).max() <= 1e-3, k
