@@ -1,8 +1,8 @@
 """Benchmark of the visibility-bitmask gather on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2_1080p]
-                [--no-batch] [--no-serve] [--no-autotune] [--serve-requests N]
-                [--serve-sweep] [--no-cpu-baseline]
+                [--no-batch] [--no-serve] [--no-autotune] [--no-table2]
+                [--serve-requests N] [--serve-sweep] [--no-cpu-baseline]
 
 One step = one pass of the whole hot path (ssvb_compute: AO, GI and ambient of one
 frame) over a seeded synthetic 1920x1080 G-buffer already resident in HBM.  Prints one
@@ -213,6 +213,40 @@ def batch_leg(ctx, pool, autotune):
     return res
 
 
+# Section 4.3, Table 2 (1920x1080, thickness 0.2): samples per side, radius, step
+# distribution, and the paper's sampling time on its GPU (context only)
+TABLE2 = [("a", 8, 1.0, "uniform", 1, 0.9), ("b", 8, 4.0, "uniform", 1, 1.7), ("c", 16, 4.0, "uniform", 1, 2.3),
+          ("d", 16, 4.0, "quadratic", 1, 2.6), ("e", 32, 4.0, "quadratic", 1, 4.0),
+          ("f", 16, 4.0, "quadratic", 2, 0.97)]
+
+
+def table2_leg(ctx, t, c, scene, slices):
+    """The rows of Table 2 on the 1080p G-buffer: N_s, radius, step distribution and
+    resolution from the table, `slices` slices, thickness 0.2, R2 noise; median of 20
+    launches each (row f: the half-resolution gather plus the upsampling pass)."""
+    import torch
+    from paper_2301_11376_amd import Params, NOISE_R2, STEPS_UNIFORM, STEPS_QUADRATIC
+    H, W = t["depth"].shape
+    out = {"ao": torch.empty((H, W), device="cuda"), "gi": torch.empty((H, W, 3), device="cuda"),
+           "ambient": torch.empty((H, W, 3), device="cuda")}
+    stream = torch.cuda.current_stream()
+    rows = []
+    for name, ns, radius, dist, res, paper_ms in TABLE2:
+        p = Params(slices=slices, steps=ns, radius=radius, thickness=0.2, noise=NOISE_R2, seed=7,
+                   step_distribution=STEPS_QUADRATIC if dist == "quadratic" else STEPS_UNIFORM,
+                   resolution=res, ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
+        fn = lambda: ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
+        fn()
+        med, mn, _ = timed(fn, stream, 20)
+        samples = ((W + res - 1) // res) * ((H + res - 1) // res) * slices * 2 * ns
+        rows.append({"row": name, "steps_per_side": ns, "radius": radius, "steps": dist,
+                     "resolution": "half" if res == 2 else "full", "ms": med,
+                     "gsamples_s": samples / med / 1e6, "paper_sampling_ms_rtx2080": paper_ms})
+    return {"workload": f"1920x1080 G-buffer of the headline workload, {slices} slices, thickness 0.2, R2 noise; "
+                        "Table 2's sample counts read as steps per side; the paper's times are for its own GI "
+                        "shader on an RTX 2080 (context, not a target)", "rows": rows}
+
+
 def serve_leg(ctx, pool, n_requests, rates):
     """Poisson stream through the request loop; G-buffers device-resident in a pool, the
     loop stages each request into its 64 GB arena and copies results to the request's
@@ -345,6 +379,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-table2", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-sweep", action="store_true", help="also serve at 0.5 and 0.9 of saturation")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -451,6 +486,10 @@ def main():
     }
     if cpu is not None:
         result["cpu_baseline"] = cpu
+    if not args.no_table2 and args.workload == "c2_1080p":
+        result["table2"] = table2_leg(ctx, t, c, scene, slices=1)
+        print("table2: " + ", ".join(f"{r['row']} {r['ms']:.3f} ms" for r in result["table2"]["rows"]),
+              file=sys.stderr, flush=True)
     if not args.no_batch:
         result["batch"] = batch_leg(ctx, pool, autotune=not args.no_autotune)
     if not args.no_serve:
