@@ -247,6 +247,25 @@ def table2_leg(ctx, t, c, scene, slices):
                         "shader on an RTX 2080 (context, not a target)", "rows": rows}
 
 
+def sectors_leg(ctx, t, c, p):
+    """The headline frame with 128 visibility sectors against 32 (Section 4.1 reports a
+    5-10 % overhead for 128 on its GPU); median of 20 launches each."""
+    import dataclasses
+    import torch
+    H, W = t["depth"].shape
+    out = {"ao": torch.empty((H, W), device="cuda"), "gi": torch.empty((H, W, 3), device="cuda"),
+           "ambient": torch.empty((H, W, 3), device="cuda")}
+    stream = torch.cuda.current_stream()
+    ms = {}
+    for nb in (32, 128):
+        q = dataclasses.replace(p, sectors=nb)
+        fn = lambda: ctx.compute(t["depth"], t["normal"], t["radiance"], c, q, out=out)
+        fn()
+        ms[nb] = timed(fn, stream, 20)[0]
+    return {"ms_32": ms[32], "ms_128": ms[128], "overhead": ms[128] / ms[32] - 1.0,
+            "paper_overhead": "5-10 % (Section 4.1, its GPU)"}
+
+
 def serve_leg(ctx, pool, n_requests, rates):
     """Poisson stream through the request loop; G-buffers device-resident in a pool, the
     loop stages each request into its 64 GB arena and copies results to the request's
@@ -489,6 +508,9 @@ def main():
     if not args.no_table2 and args.workload == "c2_1080p":
         result["table2"] = table2_leg(ctx, t, c, scene, slices=1)
         print("table2: " + ", ".join(f"{r['row']} {r['ms']:.3f} ms" for r in result["table2"]["rows"]),
+              file=sys.stderr, flush=True)
+        result["sectors128"] = sectors_leg(ctx, t, c, p)
+        print(f"sectors: 32 {result['sectors128']['ms_32']:.3f} ms, 128 {result['sectors128']['ms_128']:.3f} ms",
               file=sys.stderr, flush=True)
     if not args.no_batch:
         result["batch"] = batch_leg(ctx, pool, autotune=not args.no_autotune)

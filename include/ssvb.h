@@ -37,7 +37,7 @@ extern "C" {
 typedef enum {
     SSVB_OK = 0,
     SSVB_ERR_INVALID_ARG = 1,   /* a pointer, size, pitch or parameter is out of range */
-    SSVB_ERR_UNSUPPORTED = 2,   /* valid request the GPU path does not implement (N_b != 32) */
+    SSVB_ERR_UNSUPPORTED = 2,   /* valid request the GPU path does not implement (e.g. N_b 64) */
     SSVB_ERR_OUT_OF_MEMORY = 3, /* device allocation failed, or a request exceeds a budget */
     SSVB_ERR_DEVICE = 4,        /* a HIP runtime call failed */
     SSVB_ERR_BUSY = 5,          /* the resource is in use (server slot or queue full) */
@@ -94,8 +94,9 @@ typedef struct {
 /* Sampling parameters (Algorithm 1; Sections 3.1-3.3).
  *  slices           N_d, hemisphere slices per pixel, 1..64
  *  steps            N_s, depth samples per side of each slice, 1..1024
- *  sectors          N_b, bits of the visibility mask; the GPU path requires 32
- *  ambient_samples  N_a, ambient subregions per slice, divides 32
+ *  sectors          N_b, bits of the visibility mask: 32 or 128 (128: ssvb_compute only;
+ *                   Section 4.1 reports 32 as enough and 128 as 5-10 % slower)
+ *  ambient_samples  N_a, ambient subregions per slice, at most 32, divides N_b
  *  radius           world-space radius of the screen-aligned hemisphere, > 0
  *  thickness        t0 >= 0 (+inf allowed: GTAO without falloff, Section 3.1)
  *  thickness_slope  k >= 0: each pixel uses t = t0 + k * depth (Section 3.1)
@@ -127,9 +128,10 @@ typedef struct {
 } ssvb_params;
 
 /* Outputs, FP32, device memory.  ao [H][W]; gi and ambient [H][W][3]; masks, if not
- * NULL, [H][W][N_d] uint32 with bit k = sector k (sector k spans angles
- * [-pi/2 + k pi/32, -pi/2 + (k+1) pi/32] from the projected normal, k increasing toward
- * the slice direction).  Pitches in bytes, 0 = dense.  AO is visibility (1 = open). */
+ * NULL, [H][W][N_d][N_b / 32] uint32 with sector k in bit k % 32 of word k / 32 (sector k
+ * spans angles [-pi/2 + k pi/N_b, -pi/2 + (k+1) pi/N_b] from the projected normal, k
+ * increasing toward the slice direction).  Pitches in bytes, 0 = dense.  AO is
+ * visibility (1 = open). */
 typedef struct {
     float* ao;
     float* gi;

@@ -272,7 +272,8 @@ class Context:
                    "gi": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
                    "ambient": torch.empty((H, W, 3), dtype=torch.float32, device=dev)}
             if masks:
-                out["masks"] = torch.empty((H, W, params.slices), dtype=torch.int32, device=dev)
+                out["masks"] = torch.empty((H, W, params.slices * (params.sectors // 32)), dtype=torch.int32,
+                                           device=dev)
         o = ssvb_outputs(out["ao"].data_ptr(), out["gi"].data_ptr(), out["ambient"].data_ptr(),
                          out["masks"].data_ptr() if out.get("masks") is not None else None,
                          out["ao"].stride(0) * 4, out["gi"].stride(0) * 4, out["ambient"].stride(0) * 4,
@@ -284,13 +285,14 @@ class Context:
         return out
 
     @staticmethod
-    def alloc_outputs(H, W, slices, device, masks=False):
+    def alloc_outputs(H, W, slices, device, masks=False, sectors=32):
+        """Output tensors; masks (if asked) hold N_d x N_b / 32 words per pixel."""
         import torch
         out = {"ao": torch.empty((H, W), dtype=torch.float32, device=device),
                "gi": torch.empty((H, W, 3), dtype=torch.float32, device=device),
                "ambient": torch.empty((H, W, 3), dtype=torch.float32, device=device)}
         if masks:
-            out["masks"] = torch.empty((H, W, slices), dtype=torch.int32, device=device)
+            out["masks"] = torch.empty((H, W, slices * (sectors // 32)), dtype=torch.int32, device=device)
         return out
 
     @staticmethod

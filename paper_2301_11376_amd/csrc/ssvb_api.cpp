@@ -119,10 +119,11 @@ ssvb_status check_camera_params(const ssvb_camera* cam, const ssvb_params* p) {
     if (p->steps < 1 || p->steps > kMaxSteps)
         return fail(SSVB_ERR_INVALID_ARG, "steps %d outside [1, %d]", p->steps, kMaxSteps);
     if (p->sectors <= 0) return fail(SSVB_ERR_INVALID_ARG, "sectors %d must be > 0", p->sectors);
-    if (p->sectors != kSectors) return fail(SSVB_ERR_UNSUPPORTED, "sectors %d: the GPU path implements 32", p->sectors);
+    if (p->sectors != 32 && p->sectors != 128)
+        return fail(SSVB_ERR_UNSUPPORTED, "sectors %d: the GPU path implements 32 and 128", p->sectors);
     const int na = p->ambient_samples;
-    if (na < 1 || na > 32 || (32 % na) != 0)
-        return fail(SSVB_ERR_INVALID_ARG, "ambient_samples %d must divide 32", na);
+    if (na < 1 || na > 32 || (p->sectors % na) != 0)
+        return fail(SSVB_ERR_INVALID_ARG, "ambient_samples %d must be at most 32 and divide the sector count", na);
     if (!(finite(p->radius) && p->radius > 0)) return fail(SSVB_ERR_INVALID_ARG, "radius must be finite and > 0");
     if (!(p->thickness >= 0)) return fail(SSVB_ERR_INVALID_ARG, "thickness must be >= 0 (inf allowed)");
     if (!(finite(p->thickness_slope) && p->thickness_slope >= 0))
@@ -208,7 +209,7 @@ void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, c
         A.ao_pitch = out->ao_pitch_bytes ? out->ao_pitch_bytes : (int64_t)W * 4;
         A.gi_pitch = out->gi_pitch_bytes ? out->gi_pitch_bytes : (int64_t)W * 12;
         A.amb_pitch = out->ambient_pitch_bytes ? out->ambient_pitch_bytes : (int64_t)W * 12;
-        A.masks_pitch = out->masks_pitch_bytes ? out->masks_pitch_bytes : (int64_t)W * p->slices * 4;
+        A.masks_pitch = out->masks_pitch_bytes ? out->masks_pitch_bytes : (int64_t)W * p->slices * (p->sectors / 32) * 4;
     }
     A.fx = cam->fx;
     A.fy = cam->fy;
@@ -222,6 +223,7 @@ void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, c
     A.nd = p->slices;
     A.ns = p->steps;
     A.na = p->ambient_samples;
+    A.nb = p->sectors;
     A.criterion = p->hit_criterion;
     A.step_dist = p->step_distribution;
     A.sub = p->resolution == 2 ? 2 : 1;
@@ -248,7 +250,7 @@ void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, c
         A.amb_sb[k] = (float)sin(beta);
     }
     A.lut = tab ? tab->d_lut : nullptr;
-    A.half_sector = tab ? tab->d_half : nullptr;
+    A.half_sector = tab ? (p->sectors == 128 ? tab->d_half128 : tab->d_half) : nullptr;
     LaunchShape shape{32, 8, 4, 1};
     if (tab) {
         if (tab->forced) {
@@ -412,12 +414,15 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
         return hip_fail(e, "hipSetDevice");
     }
     load_tune_cache(ctx);
-    double2 half[129];
+    double2 half[129], half128[513];
     for (int h = -64; h <= 64; ++h) half[h + 64] = make_double2(cos(M_PI * h / 64.0), sin(M_PI * h / 64.0));
+    for (int h = -256; h <= 256; ++h) half128[h + 256] = make_double2(cos(M_PI * h / 256.0), sin(M_PI * h / 256.0));
     e = hipMalloc((void**)&ctx->tab.d_lut, sizeof ctx->h_lut);
     if (e == hipSuccess) e = hipMemcpy(ctx->tab.d_lut, ctx->h_lut, sizeof ctx->h_lut, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->tab.d_half, sizeof half);
     if (e == hipSuccess) e = hipMemcpy(ctx->tab.d_half, half, sizeof half, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->tab.d_half128, sizeof half128);
+    if (e == hipSuccess) e = hipMemcpy(ctx->tab.d_half128, half128, sizeof half128, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_ring, kRing * kRingStride * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(ctx->d_ring, 0, kRing * kRingStride * sizeof(uint32_t));
     for (int k = 0; k < kRing && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ctx->ring_ev[k], hipEventDisableTiming);
@@ -431,6 +436,7 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
     if (e != hipSuccess) {
         if (ctx->tab.d_lut) (void)hipFree(ctx->tab.d_lut);
         if (ctx->tab.d_half) (void)hipFree(ctx->tab.d_half);
+        if (ctx->tab.d_half128) (void)hipFree(ctx->tab.d_half128);
         if (ctx->d_ring) (void)hipFree(ctx->d_ring);
         for (int k = 0; k < kRing; ++k)
             if (ctx->ring_ev[k]) (void)hipEventDestroy(ctx->ring_ev[k]);
@@ -449,6 +455,7 @@ ssvb_status ssvb_destroy(ssvb_ctx* ctx) {
     free_batch(ctx);
     if (ctx->tab.d_lut) (void)hipFree(ctx->tab.d_lut);
     if (ctx->tab.d_half) (void)hipFree(ctx->tab.d_half);
+    if (ctx->tab.d_half128) (void)hipFree(ctx->tab.d_half128);
     if (ctx->d_ring) (void)hipFree(ctx->d_ring);
     for (int k = 0; k < kRing; ++k)
         if (ctx->ring_ev[k]) (void)hipEventDestroy(ctx->ring_ev[k]);
@@ -473,7 +480,8 @@ ssvb_status ssvb_validate(const ssvb_image* depth, const ssvb_image* normal, con
     if ((s = check_out_pitch(out->ao_pitch_bytes, (int64_t)W * 4, "ao"))) return s;
     if ((s = check_out_pitch(out->gi_pitch_bytes, (int64_t)W * 12, "gi"))) return s;
     if ((s = check_out_pitch(out->ambient_pitch_bytes, (int64_t)W * 12, "ambient"))) return s;
-    if (out->masks && (s = check_out_pitch(out->masks_pitch_bytes, (int64_t)W * params->slices * 4, "masks")))
+    if (out->masks && (s = check_out_pitch(out->masks_pitch_bytes,
+                                           (int64_t)W * params->slices * (params->sectors / 32) * 4, "masks")))
         return s;
     if (out->masks && params->resolution == 2)
         return fail(SSVB_ERR_INVALID_ARG, "slice masks exist only for computed pixels: not with half resolution");
@@ -515,6 +523,8 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
         if (s) return fail(s, "frame %d: %s", f, last_error().c_str());
         if (F.params.resolution != 1)
             return fail(SSVB_ERR_UNSUPPORTED, "frame %d: batches run at full resolution", f);
+        if (F.params.sectors != 32)
+            return fail(SSVB_ERR_UNSUPPORTED, "frame %d: batches run with 32 sectors", f);
     }
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -650,6 +660,7 @@ ssvb_status ssvb_debug_endpoints(ssvb_ctx* ctx, const ssvb_image* depth, const s
     if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
     ssvb_status s = check_camera_params(camera, params);
     if (s) return s;
+    if (params->sectors != 32) return fail(SSVB_ERR_UNSUPPORTED, "the endpoint hook reports 32-sector coordinates");
     const int W = camera->width, H = camera->height;
     if ((s = check_image(depth, "depth", W, H, true))) return s;
     if ((s = check_image(normal, "normal", W, H, false))) return s;

@@ -18,7 +18,8 @@ using ShapeKey = std::tuple<int, int, int, int, int>;
 // What the frame constants need from a context: device tables and launch shapes.
 struct FrameTables {
     int2* d_lut = nullptr;      // slice directions
-    double2* d_half = nullptr;  // cos, sin of h pi / 64, h = -64..64
+    double2* d_half = nullptr;     // cos, sin of h pi / 64, h = -64..64 (32 sectors)
+    double2* d_half128 = nullptr;  // cos, sin of h pi / 256, h = -256..256 (128 sectors)
     bool forced = false;
     LaunchShape force{32, 8, 4, 1};
     std::map<ShapeKey, LaunchShape> tuned;

@@ -8,7 +8,6 @@
 
 namespace ssvb {
 
-constexpr int kSectors = 32;          // N_b on the GPU: one 32-bit mask per slice
 constexpr int kLutSize = 4096;        // slice directions quantised to pi / 4096
 constexpr int kLutOne = 4096;         // fixed-point 1.0 of the direction table
 constexpr int kLatticeCapPx = 16383;  // hard cap on the projected radius, pixels
@@ -40,6 +39,7 @@ struct FrameArgs {
     float Rvw[9];           // view -> world rotation (ambient probe)
     // sampling
     int32_t nd, ns, na;
+    int32_t nb;             // sectors: 32 or 128
     int32_t criterion, noise;
     int32_t step_dist;      // ssvb_step_distribution
     uint32_t ns_recip;      // floor(2^32 / (N_s + 1)), for quadratic steps
@@ -54,7 +54,7 @@ struct FrameArgs {
     float amb_sb[32];       // sin of the same
     // slice-direction table (device), (Dx, Dy) pairs
     const int2* lut;
-    // cos and sin of h pi / 64 for h = -64..64 (device, FP64), index h + 64
+    // cos and sin of h pi / (2 N_b) for h = -2 N_b .. 2 N_b (device, FP64), index h + 2 N_b
     const double2* half_sector;
     // launch shape: tile_w x tile_h pixels per workgroup; tiles are walked in vertical
     // strips of `strip` tiles, and the walk is cut into one contiguous run per XCD

@@ -24,8 +24,8 @@
 
 namespace ssvb {
 
-constexpr float kInvPi32 = 10.185916357881302f;  // 32 / pi
-constexpr float kGuard = 1.0f / 32768.0f;       // sectors; ~3e-6 rad
+constexpr float kInvPi = 0.318309886183790672f;   // 1 / pi; N_b / pi = N_b * kInvPi exactly (N_b = 2^k)
+constexpr float kGuard = 1.0f / 32768.0f;       // sectors at N_b = 32 (~3e-6 rad); scaled by N_b / 32
 #ifndef SSVB_BATCH
 #define SSVB_BATCH 1
 #endif
@@ -108,7 +108,65 @@ __device__ __forceinline__ uint32_t low_bits(int k) { return k >= 32 ? 0xFFFFFFF
 // bits [a, b) of a 32-bit mask; empty when b <= a
 __device__ __forceinline__ uint32_t range_bits(int a, int b) { return low_bits(b) & ~low_bits(a); }
 
-__device__ __forceinline__ bool near_integer(float v) { return fabsf(v - rintf(v)) < kGuard; }
+// Within the guard band of an integer sector coordinate (the FP32 error in sectors grows
+// with N_b, so the band does too).
+template <int NB>
+__device__ __forceinline__ bool near_integer(float v) { return fabsf(v - rintf(v)) < kGuard * (NB / 32); }
+
+// Visibility mask of one slice: N_b sectors in N_b / 32 words, sector k in bit k % 32 of
+// word k / 32.
+template <int NB>
+struct SMask {
+    static constexpr int W = NB / 32;
+    uint32_t w[W];
+};
+
+template <int NB>
+__device__ __forceinline__ SMask<NB> mask_none() {
+    SMask<NB> m;
+#pragma unroll
+    for (int i = 0; i < SMask<NB>::W; ++i) m.w[i] = 0u;
+    return m;
+}
+
+// sectors [a, b) for 0 <= a, b <= N_b
+template <int NB>
+__device__ __forceinline__ SMask<NB> mask_range(int a, int b) {
+    SMask<NB> m;
+    if constexpr (NB == 32) {
+        m.w[0] = range_bits(a, b);
+    } else {
+#pragma unroll
+        for (int i = 0; i < SMask<NB>::W; ++i)
+            m.w[i] = range_bits(min(max(a - 32 * i, 0), 32), min(max(b - 32 * i, 0), 32));
+    }
+    return m;
+}
+
+// m & ~B
+template <int NB>
+__device__ __forceinline__ SMask<NB> mask_and_not(const SMask<NB>& m, const SMask<NB>& B) {
+    SMask<NB> r;
+#pragma unroll
+    for (int i = 0; i < SMask<NB>::W; ++i) r.w[i] = m.w[i] & ~B.w[i];
+    return r;
+}
+
+template <int NB>
+__device__ __forceinline__ int mask_popc(const SMask<NB>& m) {
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < SMask<NB>::W; ++i) c += __popc(m.w[i]);
+    return c;
+}
+
+template <int NB>
+__device__ __forceinline__ bool mask_any(const SMask<NB>& m) {
+    uint32_t o = 0u;
+#pragma unroll
+    for (int i = 0; i < SMask<NB>::W; ++i) o |= m.w[i];
+    return o != 0u;
+}
 
 // atan2(y, x) for y >= 0 and any x (including -inf), in [0, pi].  Octant reduction to
 // r = min / max in [0, 1] and an odd minimax polynomial of degree 13 for atan(r) on
@@ -138,7 +196,7 @@ __device__ __forceinline__ float atan2_pos(float y, float x) {
 struct SliceF {
     float ex, ey, ez;   // unit tangent of the slice toward +d
     float nv, ne;       // centre normal in (v, e)
-    float K;            // sector coordinate of the direction v: 16.5 - gamma * 32 / pi
+    float K;            // sector coordinate of the direction v: N_b / 2 + 1/2 - gamma N_b / pi
     float avq, aeq;     // (D3 . v) / 16 and (D3 . e) / 16: per 1/16-px offset unit
     float cg, sg;       // unit projected normal (cos gamma, sin gamma)
 };
@@ -148,6 +206,7 @@ struct ExactLds {
     double R[kBlock], tp[kBlock], av[kBlock], ae[kBlock], cg[kBlock], sg[kBlock];
 };
 
+template <int NB>
 __device__ __forceinline__ SliceF slice_constants(const FrameArgs& A, double rpx, double rpy, int2 D, float3 n,
                                                   ExactLds& L, int t) {
     const double R = sqrt(rpx * rpx + rpy * rpy + 1.0);
@@ -178,7 +237,7 @@ __device__ __forceinline__ SliceF slice_constants(const FrameArgs& A, double rpx
     }
     S.cg = (float)cg;
     S.sg = (float)sg;
-    S.K = fmaf(-gamma, kInvPi32, 16.5f);
+    S.K = fmaf(-gamma, (float)NB * kInvPi, (float)(NB / 2) + 0.5f);
     S.avq = (float)(av * 0.0625);
     S.aeq = (float)(ae * 0.0625);
     L.av[t] = av;
@@ -192,26 +251,29 @@ __device__ __forceinline__ SliceF slice_constants(const FrameArgs& A, double rpx
 // exact decisions near a sector boundary
 // ---------------------------------------------------------------------------------------
 // Is the direction (sv, se) (in the slice, from v toward e) at or counter-clockwise of
-// the direction at angle h pi / 64 from the projected normal (cg, sg)?
+// the direction at angle h pi / (2 N_b) from the projected normal (cg, sg)?
 // Products are rounded separately (no contraction), so a cross product of two identical
 // directions is exactly zero.
+template <int NB>
 __device__ __forceinline__ bool at_or_above(const FrameArgs& A, int h, double cg, double sg, double sv, double se) {
 #pragma clang fp contract(off)
-    const GMEM double* hs = (const GMEM double*)A.half_sector + 2 * (h + 64);  // cos, sin of h pi / 64
+    // cos, sin of h pi / (2 N_b), h = -2 N_b .. 2 N_b
+    const GMEM double* hs = (const GMEM double*)A.half_sector + 2 * (h + 2 * NB);
     const double2 cs = make_double2(hs[0], hs[1]);
     const double dv = cs.x * cg - cs.y * sg, de = cs.y * cg + cs.x * sg;
     return dv * se - de * sv >= 0.0;
 }
 
-// Exact floor of the FP32 sector coordinate `y` (ROUND: y = 32 u + 1/2; PSEUDOCODE: y =
-// 32 u) of an endpoint with direction (sv, se), given that y is near the integer m.  The
-// angle is clamped to the hemisphere first, so the floor never drops below 0.
+// Exact floor of the FP32 sector coordinate `y` (ROUND: y = N_b u + 1/2; PSEUDOCODE:
+// y = N_b u) of an endpoint with direction (sv, se), given that y is near the integer m.
+// The angle is clamped to the hemisphere first, so the floor never drops below 0.
+template <int NB>
 __device__ __forceinline__ int exact_floor(const FrameArgs& A, bool round, float y, double cg, double sg, double sv,
                                            double se) {
     const int m = (int)rintf(y);
-    // boundary y = m sits at theta = (m - 16.5) pi / 32 (ROUND) or (m - 16) pi / 32
-    const int h = round ? 2 * m - 33 : 2 * m - 32;
-    return at_or_above(A, h, cg, sg, sv, se) ? m : max(m - 1, 0);
+    // boundary y = m sits at theta = (m - N_b/2 - 1/2) pi / N_b (ROUND) or (m - N_b/2) pi / N_b
+    const int h = round ? 2 * m - (NB + 1) : 2 * m - NB;
+    return at_or_above<NB>(A, h, cg, sg, sv, se) ? m : max(m - 1, 0);
 }
 
 // Direction of a clamped endpoint: the hemisphere edge it was clamped to (side -1 below
@@ -243,43 +305,46 @@ __device__ __forceinline__ void store_background(const FrameArgs& A, int x, int 
     g[0] = g[1] = g[2] = 0.0f;
     m[0] = m[1] = m[2] = 0.0f;
     if (A.masks) {
-        GMEM uint32_t* mk = (GMEM uint32_t*)((GMEM char*)A.masks + (int64_t)y * A.masks_pitch) + (int64_t)x * A.nd;
-        for (int i = 0; i < A.nd; ++i) mk[i] = 0u;
+        const int words = A.nd * (A.nb / 32);
+        GMEM uint32_t* mk = (GMEM uint32_t*)((GMEM char*)A.masks + (int64_t)y * A.masks_pitch) + (int64_t)x * words;
+        for (int i = 0; i < words; ++i) mk[i] = 0u;
     }
 }
 
 // One sample of the march: sector range, newly covered sectors, indirect light.
-template <int CRIT, bool TINF, int FMT>
+template <int CRIT, bool TINF, int FMT, int NB>
 __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S, const ExactLds& L, int t, float zp,
                                              float R, float vx, float vy, float vz, float tp, int s, int o, int X,
-                                             int Y, bool ok, float zs, uint32_t& B, float& gir, float& gig,
+                                             int Y, bool ok, float zs, SMask<NB>& B, float& gir, float& gig,
                                              float& gib) {
+    constexpr float hi_edge = (float)NB + 0.5f;
+    constexpr float guard = kGuard * (NB / 32);
     ok = ok && is_geometry(zs);
     const float of = (float)o;
-    const float sk = s > 0 ? kInvPi32 : -kInvPi32;
+    const float sk = s > 0 ? (float)NB * kInvPi : -(float)NB * kInvPi;
     // slice-plane coordinates of delta = s_f - p: c along v, h = |delta . e|
     const float c = fmaf(zs, of * (s > 0 ? S.avq : -S.avq), -R * (zs - zp));
     const float h = zs * (of * S.aeq);
     // front and back angles from v (the back sample lies t farther along -v)
     const float af = atan2_pos(h, c);
     const float ab = TINF ? 3.14159265358979324f : atan2_pos(h, c - tp);
-    const float yf = fminf(fmaxf(fmaf(af, sk, S.K), 0.5f), 32.5f);
-    const float yb = fminf(fmaxf(fmaf(ab, sk, S.K), 0.5f), 32.5f);
+    const float yf = fminf(fmaxf(fmaf(af, sk, S.K), 0.5f), hi_edge);
+    const float yb = fminf(fmaxf(fmaf(ab, sk, S.K), 0.5f), hi_edge);
     const bool round = CRIT < 0 ? A.criterion == SSVB_HIT_ROUND : CRIT == SSVB_HIT_ROUND;
     int a, b;
     if (round) {
         int kf = (int)floorf(yf), kb = (int)floorf(yb);
-        if ((near_integer(yf) | near_integer(yb)) && ok) {
+        if ((near_integer<NB>(yf) | near_integer<NB>(yb)) && ok) {
             // FP64 decision of the endpoint(s) next to a boundary
             const double zsd = zs, zpd = zp;
             const double lam = (double)(s * o) * 0.0625;
             const double cd = -(zsd - zpd) * L.R[t] + zsd * lam * L.av[t];
             const double he = zsd * lam * L.ae[t];
             const double cg = L.cg[t], sg = L.sg[t];
-            if (near_integer(yf)) kf = exact_floor(A, round, yf, cg, sg, cd, he);
-            if (near_integer(yb)) {
-                if (TINF || isinf(L.tp[t])) kb = exact_floor(A, round, yb, cg, sg, -1.0, 0.0);
-                else kb = exact_floor(A, round, yb, cg, sg, cd - L.tp[t], he);
+            if (near_integer<NB>(yf)) kf = exact_floor<NB>(A, round, yf, cg, sg, cd, he);
+            if (near_integer<NB>(yb)) {
+                if (TINF || isinf(L.tp[t])) kb = exact_floor<NB>(A, round, yb, cg, sg, -1.0, 0.0);
+                else kb = exact_floor<NB>(A, round, yb, cg, sg, cd - L.tp[t], he);
             }
         }
         a = min(kf, kb);
@@ -291,7 +356,7 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
         int kf = (int)floorf(yf - 0.5f), kb = (int)floorf(yb - 0.5f);
         const float wf = hi - lo;
         int w = (int)ceilf(fmaxf(wf, 0.0f));
-        if ((near_integer(yf - 0.5f) | near_integer(yb - 0.5f) | near_integer(wf)) && ok) {
+        if ((near_integer<NB>(yf - 0.5f) | near_integer<NB>(yb - 0.5f) | near_integer<NB>(wf)) && ok) {
 #pragma clang fp contract(off)
             const double zsd = zs, zpd = zp;
             const double lam = (double)(s * o) * 0.0625;
@@ -300,17 +365,17 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
             const double cg = L.cg[t], sg = L.sg[t];
             const bool binf = TINF || isinf(L.tp[t]);
             const double bv = binf ? -1.0 : cd - L.tp[t], be = binf ? 0.0 : he;
-            if (near_integer(yf - 0.5f)) kf = exact_floor(A, round, yf - 0.5f, cg, sg, cd, he);
-            if (near_integer(yb - 0.5f)) kb = exact_floor(A, round, yb - 0.5f, cg, sg, bv, be);
-            if (near_integer(wf)) {
+            if (near_integer<NB>(yf - 0.5f)) kf = exact_floor<NB>(A, round, yf - 0.5f, cg, sg, cd, he);
+            if (near_integer<NB>(yb - 0.5f)) kb = exact_floor<NB>(A, round, yb - 0.5f, cg, sg, bv, be);
+            if (near_integer<NB>(wf)) {
                 // width = ceil of the angle between the two clamped endpoint directions; an
                 // endpoint near a hemisphere edge is clamped (or not) exactly
                 const float yfr = fmaf(af, sk, S.K), ybr = TINF ? yb : fmaf(ab, sk, S.K);
                 int sf = 0, sb = 0;  // +1 above the +pi/2 edge, -1 below the -pi/2 edge
-                if (yfr >= 32.5f + kGuard || (yfr > 32.5f - kGuard && at_or_above(A, 32, cg, sg, cd, he))) sf = 1;
-                if (yfr <= 0.5f - kGuard || (yfr < 0.5f + kGuard && !at_or_above(A, -32, cg, sg, cd, he))) sf = -1;
-                if (ybr >= 32.5f + kGuard || (ybr > 32.5f - kGuard && at_or_above(A, 32, cg, sg, bv, be))) sb = 1;
-                if (ybr <= 0.5f - kGuard || (ybr < 0.5f + kGuard && !at_or_above(A, -32, cg, sg, bv, be))) sb = -1;
+                if (yfr >= hi_edge + guard || (yfr > hi_edge - guard && at_or_above<NB>(A, NB, cg, sg, cd, he))) sf = 1;
+                if (yfr <= 0.5f - guard || (yfr < 0.5f + guard && !at_or_above<NB>(A, -NB, cg, sg, cd, he))) sf = -1;
+                if (ybr >= hi_edge + guard || (ybr > hi_edge - guard && at_or_above<NB>(A, NB, cg, sg, bv, be))) sb = 1;
+                if (ybr <= 0.5f - guard || (ybr < 0.5f + guard && !at_or_above<NB>(A, -NB, cg, sg, bv, be))) sb = -1;
                 if (sf != 0 && sf == sb) {
                     w = 0;  // both endpoints on the same edge
                 } else {
@@ -320,8 +385,8 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
                     const double lv = s > 0 ? fv : bv2, le = s > 0 ? fe : be2;
                     const double hv = s > 0 ? bv2 : fv, hev = s > 0 ? be2 : fe;
                     const int m = max((int)rintf(wf), 0);
-                    // rotate the low end by m pi / 32
-                    const GMEM double* hs = (const GMEM double*)A.half_sector + 2 * (2 * m + 64);
+                    // rotate the low end by m pi / N_b
+                    const GMEM double* hs = (const GMEM double*)A.half_sector + 2 * (2 * m + 2 * NB);
                     const double2 cs = make_double2(hs[0], hs[1]);
                     const double rv = cs.x * lv - cs.y * le, re = cs.y * lv + cs.x * le;
                     w = (rv * hev - re * hv <= 0.0) ? m : m + 1;
@@ -329,11 +394,11 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
             }
         }
         a = min(kf, kb);
-        b = min(a + w, 32);
+        b = min(a + w, NB);
     }
-    const uint32_t m = ok ? range_bits(a, b) : 0u;
-    const uint32_t fresh = m & ~B;
-    if (fresh) {
+    const SMask<NB> m = ok ? mask_range<NB>(a, b) : mask_none<NB>();
+    const SMask<NB> fresh = mask_and_not<NB>(m, B);
+    if (mask_any<NB>(fresh)) {
         // indirect light from the newly covered sectors (Algorithm 1; Section 3.3)
         const float3 nj = load3<FMT < 0 ? -1 : (FMT & 1)>(A.normal, A.normal_pitch, A.normal_ch, A.normal_f16, X, Y);
         const float hs = s > 0 ? h : -h;
@@ -341,7 +406,7 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
         const float njv = nj.x * vx + nj.y * vy + nj.z * vz;
         const float nje = nj.x * S.ex + nj.y * S.ey + nj.z * S.ez;
         const float ndj = fmaf(njv, c, nje * hs);
-        const float w = (float)__popc(fresh) * (1.0f / 32.0f) * fmaxf(ndp, 0.0f) * fmaxf(-ndj, 0.0f) *
+        const float w = (float)mask_popc<NB>(fresh) * (1.0f / (float)NB) * fmaxf(ndp, 0.0f) * fmaxf(-ndj, 0.0f) *
                         __builtin_amdgcn_rcpf(fmaf(c, c, h * h));
         if (w > 0.0f) {
             const float3 cj = load3<FMT < 0 ? -1 : (FMT >> 1)>(A.radiance, A.radiance_pitch, A.radiance_ch,
@@ -351,7 +416,8 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
             gib = fmaf(w, cj.z, gib);
         }
     }
-    B |= m;
+#pragma unroll
+    for (int k = 0; k < SMask<NB>::W; ++k) B.w[k] |= m.w[k];
 }
 
 // One pixel of the gather.
@@ -365,7 +431,7 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
 // newly covered count, as a side-by-side march would produce it.
 //  li/lp  this lane's index among the lp lanes that share the pixel (adjacent lanes, lp a
 //         power of two); lane li takes slices li, li + lp, ...
-template <int CRIT, int MODE, bool TINF, int FMT>
+template <int CRIT, int MODE, bool TINF, int FMT, int NB = 32>
 __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int li, int lp,
                                              int32_t* dbg_i, float* dbg_f) {
     const int t = (int)threadIdx.x;
@@ -424,8 +490,8 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
             }
             continue;
         }
-        const SliceF S = slice_constants(A, rpx, rpy, D, n, L, t);
-        uint32_t B = 0u;
+        const SliceF S = slice_constants<NB>(A, rpx, rpy, D, n, L, t);
+        SMask<NB> B = mask_none<NB>();
 
         // steps are taken kBatch at a time: the depth loads of the whole batch (both
         // sides) are issued first, then the samples are consumed near to far
@@ -459,36 +525,38 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
                         const float z = zs[u][side];
                         if (!(ok && is_geometry(z))) continue;
                         const float of = (float)o;
-                        const float sk = side ? -kInvPi32 : kInvPi32;
+                        const float sk = side ? -(float)NB * kInvPi : (float)NB * kInvPi;
                         const float c = fmaf(z, of * (side ? -S.avq : S.avq), -R * (z - zp));
                         const float h = z * (of * S.aeq);
                         const float af = atan2_pos(h, c);
                         const float ab = atan2_pos(h, c - tp);
-                        const float yf = fminf(fmaxf(fmaf(af, sk, S.K), 0.5f), 32.5f);
-                        const float yb = fminf(fmaxf(fmaf(ab, sk, S.K), 0.5f), 32.5f);
+                        const float yf = fminf(fmaxf(fmaf(af, sk, S.K), 0.5f), (float)NB + 0.5f);
+                        const float yb = fminf(fmaxf(fmaf(ab, sk, S.K), 0.5f), (float)NB + 0.5f);
                         const float lo = fminf(yf, yb), hi = fmaxf(yf, yb);
                         float* d = dbg_f + ((((int64_t)i * 2 + side) * A.ns + j) * 2);
                         const bool round = CRIT < 0 ? A.criterion == SSVB_HIT_ROUND : CRIT == SSVB_HIT_ROUND;
                         d[0] = round ? lo : lo - 0.5f;
                         d[1] = round ? hi : hi - lo;
                     } else {
-                        march_sample<CRIT, TINF, FMT>(A, S, L, t, zp, R, vx, vy, vz, tp, s, o, X, Y, ok,
+                        march_sample<CRIT, TINF, FMT, NB>(A, S, L, t, zp, R, vx, vy, vz, tp, s, o, X, Y, ok,
                                                       zs[u][side], B, gir, gig, gib);
                     }
                 }
             }
         }
         if (MODE != MODE_COMPUTE) continue;
-        ao_acc += 1.0f - (float)__popc(B) * (1.0f / 32.0f);
+        ao_acc += 1.0f - (float)mask_popc<NB>(B) * (1.0f / (float)NB);
         if (A.masks) {
-            GMEM uint32_t* mk = (GMEM uint32_t*)((GMEM char*)A.masks + (int64_t)y * A.masks_pitch) + (int64_t)x * A.nd;
-            mk[i] = B;
+            GMEM uint32_t* mk = (GMEM uint32_t*)((GMEM char*)A.masks + (int64_t)y * A.masks_pitch) +
+                                (int64_t)x * A.nd * SMask<NB>::W;
+#pragma unroll
+            for (int k = 0; k < SMask<NB>::W; ++k) mk[i * SMask<NB>::W + k] = B.w[k];
         }
         // directionally occluded ambient (Section 3.2)
-        const int per = 32 / A.na;
+        const int per = NB / A.na;
         for (int kk = 0; kk < A.na; ++kk) {
-            const uint32_t open = ~B & range_bits(kk * per, (kk + 1) * per);
-            if (!open) continue;
+            const SMask<NB> open = mask_and_not<NB>(mask_range<NB>(kk * per, (kk + 1) * per), B);
+            if (!mask_any<NB>(open)) continue;
             const float cps = S.cg * A.amb_cb[kk] - S.sg * A.amb_sb[kk];
             const float sps = S.sg * A.amb_cb[kk] + S.cg * A.amb_sb[kk];
             const float dvx = cps * vx + sps * S.ex, dvy = cps * vy + sps * S.ey, dvz = cps * vz + sps * S.ez;
@@ -509,7 +577,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
                              b6 * Sh[19] + b7 * Sh[22] + b8 * Sh[25];
             const float Lb = b0 * Sh[2] + b1 * Sh[5] + b2 * Sh[8] + b3 * Sh[11] + b4 * Sh[14] + b5 * Sh[17] +
                              b6 * Sh[20] + b7 * Sh[23] + b8 * Sh[26];
-            const float fr = (float)__popc(open) * (1.0f / 32.0f);
+            const float fr = (float)mask_popc<NB>(open) * (1.0f / (float)NB);
             amr = fmaf(fr, Lr, amr);
             amg = fmaf(fr, Lg, amg);
             amb = fmaf(fr, Lb, amb);
@@ -560,7 +628,7 @@ __device__ __forceinline__ uint32_t grab(uint32_t* q, uint32_t* s_item) {
 // of its own XCD first and then takes what is left in the others, so dies that finish
 // early help the slow ones.  q[0..7] are the queue heads, q[8] counts finished
 // workgroups: the last one to finish sets all nine back to zero for the next launch.
-template <int CRIT, bool TINF, int FMT>
+template <int CRIT, bool TINF, int FMT, int NB = 32>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void gather_frame(
     FrameArgs A, uint32_t* __restrict__ q) {
     __shared__ ExactLds L;
@@ -588,7 +656,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             const int lp = F.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
             const int x = (tx * F.tile_w + px % F.tile_w) * F.sub;
             const int y = (ty * F.tile_h + px / F.tile_w) * F.sub;
-            if (x < F.W && y < F.H) gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT>(F, L, x, y, li, lp, nullptr, nullptr);
+            if (x < F.W && y < F.H) gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT, NB>(F, L, x, y, li, lp, nullptr, nullptr);
         }
     }
     if (threadIdx.x == 0) {
@@ -728,13 +796,13 @@ int batch_blocks_per_cu() {
 }
 static dim3 grid16(const FrameArgs& A) { return dim3((A.W + 15) / 16, (A.H + 15) / 16); }
 
-template <int CRIT, bool TINF, int FMT>
+template <int CRIT, bool TINF, int FMT, int NB = 32>
 static void launch_main(const FrameArgs& A, uint32_t* q, int grid, hipStream_t stream) {
     // no more workgroups than the frame has tiles (rounded to whole XCD rounds)
     const uint32_t nt = (uint32_t)A.tiles_x * A.tiles_y;
     const uint32_t need = kXcds * ((nt + kXcds - 1) / kXcds);
     const uint32_t nwg = need < (uint32_t)grid ? need : (uint32_t)grid;
-    hipLaunchKernelGGL((gather_frame<CRIT, TINF, FMT>), dim3(nwg), dim3(kBlock), 0, stream, A, q);
+    hipLaunchKernelGGL((gather_frame<CRIT, TINF, FMT, NB>), dim3(nwg), dim3(kBlock), 0, stream, A, q);
 }
 
 template <int CRIT, bool TINF>
@@ -749,6 +817,15 @@ static void launch_fmt(const FrameArgs& A, uint32_t* q, int grid, hipStream_t st
 
 hipError_t launch_plain(const FrameArgs& A, uint32_t* queues, int grid, hipStream_t stream) {
     const bool tinf = isinf(A.t0);
+    if (A.nb == 128) {
+        // 128 sectors: one kernel for the common case (ROUND, finite thickness, FP32), one
+        // that decides criterion and element types at run time
+        if (A.criterion == SSVB_HIT_ROUND && !tinf && !A.normal_f16 && !A.radiance_f16)
+            launch_main<SSVB_HIT_ROUND, false, 0, 128>(A, queues, grid, stream);
+        else
+            launch_main<-1, false, -1, 128>(A, queues, grid, stream);
+        return hipGetLastError();
+    }
     if (A.criterion == SSVB_HIT_ROUND) {
         if (tinf) launch_fmt<SSVB_HIT_ROUND, true>(A, queues, grid, stream);
         else launch_fmt<SSVB_HIT_ROUND, false>(A, queues, grid, stream);

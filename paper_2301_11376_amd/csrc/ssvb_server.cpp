@@ -387,6 +387,7 @@ ssvb_status ssvb_server_submit(ssvb_server* S, const ssvb_frame* frame, uint64_t
     if (s) return s;
     if (F.out.masks) return fail(SSVB_ERR_INVALID_ARG, "served requests do not return slice masks");
     if (F.params.resolution != 1) return fail(SSVB_ERR_UNSUPPORTED, "served requests run at full resolution");
+    if (F.params.sectors != 32) return fail(SSVB_ERR_UNSUPPORTED, "served requests run with 32 sectors");
     Request r;
     r.caller = F;
     r.lay = layout_of(F);

@@ -18,7 +18,23 @@ import oracle as O
 TOL_FP32 = 1e-3
 MASK_AGREEMENT = 0.999
 TIE_RAD = 1e-6                       # a mismatch must come from an endpoint this close
-TIE_SECTORS = TIE_RAD * 32 / math.pi  # the same distance in sector units
+
+
+def tie_sectors(nb):
+    """TIE_RAD in sector units of an N_b-sector mask."""
+    return TIE_RAD * nb / math.pi
+
+
+def packed_masks(m):
+    """Oracle masks as the GPU stores them: uint32 [n, N_d] for N_b = 32 already; for more
+    sectors a bool [n, N_d, N_b] array becomes [n, N_d * N_b / 32] words, sector k in bit
+    k % 32 of word k / 32."""
+    m = np.asarray(m)
+    if m.dtype != bool:
+        return m
+    n, nd, nb = m.shape
+    w = m.reshape(n, nd, nb // 32, 32).astype(np.uint64) << np.arange(32, dtype=np.uint64)
+    return w.sum(axis=-1).astype(np.uint32).reshape(n, nd * (nb // 32))
 
 
 def cams(cam):
@@ -62,6 +78,8 @@ def compare(gpu, ref, gb, ocam, oprm, pixels=None, tol=TOL_FP32, report=None):
         ref = {k: flat(v) for k, v in ref.items() if k in ("ao", "gi", "ambient", "masks", "valid")}
     else:
         ys, xs = pixels
+    if "masks" in ref:
+        ref = dict(ref, masks=packed_masks(ref["masks"]))
     g = {k: gpu[k][ys, xs] for k in ("ao", "gi", "ambient", "masks") if k in gpu}
     mask_eq = np.all(g["masks"] == ref["masks"], axis=-1) if "masks" in g else np.ones(len(ys), bool)
     err_ao = np.abs(g["ao"] - ref["ao"])
@@ -100,7 +118,7 @@ def explain_pixel(gpu, gb, ocam, oprm, y, x, tol):
                   return_endpoints=True)
     ep = r["endpoints"][0]
     dist = np.abs(ep - np.round(ep))
-    near = np.argwhere(np.isfinite(ep) & (dist < TIE_SECTORS))
+    near = np.argwhere(np.isfinite(ep) & (dist < tie_sectors(oprm.sectors)))
     if len(near) == 0 or len(near) > 10:
         return False
     for flips in itertools.product((0, 1), repeat=len(near)):
@@ -113,7 +131,7 @@ def explain_pixel(gpu, gb, ocam, oprm, y, x, tol):
                 bias[(0,) + tuple(pos)] = 1 if v < np.round(v) else -1
         rr = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam, oprm, pixels=([y], [x]),
                        return_masks=True, index_bias=bias)
-        if not np.array_equal(rr["masks"][0], gpu["masks"][y, x]):
+        if not np.array_equal(packed_masks(rr["masks"])[0], gpu["masks"][y, x]):
             continue
         if (abs(rr["ao"][0] - gpu["ao"][y, x]) <= tol and np.abs(rr["gi"][0] - gpu["gi"][y, x]).max() <= tol
                 and np.abs(rr["ambient"][0] - gpu["ambient"][y, x]).max() <= tol):

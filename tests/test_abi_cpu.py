@@ -139,6 +139,22 @@ def test_validate_half_resolution_without_masks(B):
 
 def test_validate_unsupported_sectors(B):
     assert status(B, frame(B, p=setter("sectors", 64))) == 2
+    assert status(B, frame(B, p=setter("sectors", 128))) == 0
+
+
+def test_validate_sectors128_layouts(B):
+    def s128(p):
+        p.sectors = 128
+    # masks: N_d x 4 words per pixel
+    assert status(B, frame(B, p=s128, o=setter("masks", FAKE))) == 0
+    def short_pitch(o):
+        o.masks = FAKE
+        o.masks_pitch_bytes = 64 * 2 * 4  # one word per slice: too short for 128 sectors
+    assert status(B, frame(B, p=s128, o=short_pitch)) == 1
+    def amb(p):
+        p.sectors = 128
+        p.ambient_samples = 64           # more than 32 subregions
+    assert status(B, frame(B, p=amb)) == 1
 
 
 def test_validate_nan_probe(B):

@@ -155,6 +155,12 @@ VARIANTS = {
     "zero_thickness": dict(slices=2, steps=6, radius=1.5, thickness=0.0, noise=O.NOISE_HASH, seed=19),
     "quadratic_steps": dict(slices=3, steps=12, radius=2.0, thickness=0.3, noise=O.NOISE_R2, seed=20,
                             step_distribution=1),
+    "sectors128": dict(slices=3, steps=8, radius=1.5, thickness=0.4, noise=O.NOISE_HASH, seed=41, sectors=128),
+    "sectors128_pseudocode_tinf": dict(slices=2, steps=10, radius=2.0, thickness=INF, noise=O.NOISE_R2, seed=42,
+                                       sectors=128, hit_criterion=1, ambient_samples=16),
+    "sectors128_slope_quadratic": dict(slices=4, steps=6, radius=1.0, thickness=0.1, thickness_slope=0.05,
+                                       noise=O.NOISE_HASH, seed=43, sectors=128, step_distribution=1,
+                                       ambient_samples=32),
     "quadratic_pseudocode_tinf": dict(slices=2, steps=8, radius=1.5, thickness=INF, noise=O.NOISE_HASH, seed=21,
                                       step_distribution=1, hit_criterion=1),
 }
@@ -348,3 +354,18 @@ def test_half_resolution(ctx, name, size):
     ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op)
     for k in ("ao", "gi", "ambient"):
         assert np.abs(half[k] - ref[k]).max() <= 1e-3, k
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+def test_sectors128_full_frame(ctx, fp16):
+    """128 sectors on the 128x128 workload (FP32, and FP16 normals/radiance for the
+    run-time element-type kernel), every pixel against the oracle."""
+    gb, cam, w, scene = workload("c1_128")
+    if fp16:
+        gb = dict(gb, normal=gb["normal"].astype(np.float16), radiance=gb["radiance"].astype(np.float16))
+    log(f"128 sectors, 128x128, fp16={fp16}")
+    rep = {}
+    run_case(ctx, gb, cam, report=rep, slices=w["slices"], steps=w["steps"], radius=w["radius"],
+             thickness=w["thickness"], noise=O.NOISE_HASH, seed=w["seed"], sectors=128,
+             ambient_sh=tuple(scene.ambient_sh.reshape(-1)))
+    log(f"  {rep}")
