@@ -71,8 +71,9 @@ __device__ __forceinline__ uint32_t jitter8(const FrameArgs& A, int x, int y, in
 // steps (Section 4.3: denser near the pixel): the reach q (N_s + 1) times
 // ((j + 1 + xi) / (N_s + 1))^2, in integers: ((q a^2) >> 16) * floor(2^32 / (N_s + 1))
 // >> 32 with a = 256 (j + 1) + xi8 (q a^2 < 2^44, the second product < 2^50).
+template <bool QUAD>
 __device__ __forceinline__ int step_offset(const FrameArgs& A, int q, int jit, int xi8, int j) {
-    if (A.step_dist == SSVB_STEPS_UNIFORM) return q * (j + 1) + jit;
+    if (!QUAD) return q * (j + 1) + jit;
     const uint64_t a = (uint64_t)(uint32_t)((j + 1) * 256 + xi8);
     const uint64_t t = ((uint64_t)(uint32_t)q * (a * a)) >> 16;
     return (int)((t * (uint64_t)A.ns_recip) >> 32);
@@ -431,9 +432,9 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
 // newly covered count, as a side-by-side march would produce it.
 //  li/lp  this lane's index among the lp lanes that share the pixel (adjacent lanes, lp a
 //         power of two); lane li takes slices li, li + lp, ...
-template <int CRIT, int MODE, bool TINF, int FMT, int NB = 32>
-__device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int li, int lp,
-                                             int32_t* dbg_i, float* dbg_f) {
+template <int CRIT, int MODE, bool TINF, int FMT, int NB, bool QUAD>
+__device__ __forceinline__ void gather_pixel_steps(const FrameArgs& A, ExactLds& L, int x, int y, int li, int lp,
+                                                   int32_t* dbg_i, float* dbg_f) {
     const int t = (int)threadIdx.x;
     const float zp = depth_load(A, depth_off(A, x, y));
     const bool geom = is_geometry(zp);
@@ -482,7 +483,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
             for (int side = 0; side < 2; ++side) {
                 const int s = side ? -1 : 1;
                 for (int j = 0; j < A.ns; ++j) {
-                    const int o = step_offset(A, q, jit, xi8, j);
+                    const int o = step_offset<QUAD>(A, q, jit, xi8, j);
                     int32_t* d = dbg_i + ((((int64_t)i * 2 + side) * A.ns + j) * 2);
                     d[0] = (x16 + s * o * D.x) >> 16;
                     d[1] = (y16 + s * o * D.y) >> 16;
@@ -499,7 +500,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
             float zs[kBatch][2];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
-                const int o = step_offset(A, q, jit, xi8, j0 + u);
+                const int o = step_offset<QUAD>(A, q, jit, xi8, j0 + u);
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
                     const int so = side ? -o : o;
@@ -513,7 +514,7 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
             for (int u = 0; u < kBatch; ++u) {
                 const int j = j0 + u;
                 if (j >= A.ns) break;
-                const int o = step_offset(A, q, jit, xi8, j);
+                const int o = step_offset<QUAD>(A, q, jit, xi8, j);
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
                     const int s = side ? -1 : 1;
@@ -605,6 +606,17 @@ __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, in
     m[0] = amr * inv_nd;
     m[1] = amg * inv_nd;
     m[2] = amb * inv_nd;
+}
+
+// The step distribution is uniform per frame: decide it once per pixel, outside the
+// step loops (inside them the compiler would evaluate both placements and select).
+template <int CRIT, int MODE, bool TINF, int FMT, int NB = 32>
+__device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int li, int lp,
+                                             int32_t* dbg_i, float* dbg_f) {
+    if (A.step_dist == SSVB_STEPS_QUADRATIC)
+        gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, true>(A, L, x, y, li, lp, dbg_i, dbg_f);
+    else
+        gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, false>(A, L, x, y, li, lp, dbg_i, dbg_f);
 }
 
 // The XCD this wave runs on (hardware register XCC_ID; the die's own L2 serves it).
