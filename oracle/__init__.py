@@ -25,6 +25,7 @@ from .ssvb_oracle import (  # noqa: F401
     step_offset_q4,
     compute,
     bilateral_upsample,
+    inject_bounce,
     UPSAMPLE_SIGMA,
     UPSAMPLE_FLOOR,
     sh_eval,

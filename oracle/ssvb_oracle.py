@@ -61,6 +61,9 @@ listed again in the design notes):
       pixels with weights bilinear x (1e-3 + exp(-((z - z_n) / (0.05 z))^2)), background
       neighbours excluded; a background pixel, or one with no computed foreground
       neighbour, outputs AO = 1, GI = 0, ambient = 0.
+  R23 multi-bounce (Section 4.3: the indirect light is injected into the light buffer of
+      the next frame, its intensity "balanced"): next light = direct + g albedo * GI per
+      pixel and channel, with a gain g in [0, 1] as the balance.
 """
 from __future__ import annotations
 
@@ -257,6 +260,15 @@ def _bits(lo, hi, nb):
 # ----------------------------------------------------------------------------------------
 # the method
 # ----------------------------------------------------------------------------------------
+
+def inject_bounce(direct, albedo, gi, gain):
+    """Light buffer of the next frame (Section 4.3, reading R23): direct + gain * albedo *
+    GI, per pixel and RGB channel, in FP64.  ``direct`` and ``albedo`` are [H, W, C >= 3]
+    (FP32 or FP16, upcast exactly), ``gi`` [H, W, 3]."""
+    d = np.asarray(direct)[..., :3].astype(np.float64)
+    a = np.asarray(albedo)[..., :3].astype(np.float64)
+    return d + float(np.float32(gain)) * a * np.asarray(gi, dtype=np.float64)
+
 
 UPSAMPLE_SIGMA = 0.05    # relative depth scale of the upsampling weights (R22)
 UPSAMPLE_FLOOR = 1e-3    # weight floor: depth-incompatible neighbours still blend

@@ -739,6 +739,40 @@ def pin_half_resolution(O):
     assert np.allclose(rp["ambient"], np.asarray(C), rtol=1e-7, atol=0)
 
 
+def pin_multi_bounce(O):
+    """Multi-bounce (Section 4.3; reading R23): gain 0 or zero GI leaves the direct light;
+    GI is linear and non-negative in the light buffer, so feeding it back frame after
+    frame on the crease (floor facing a lit wall, fixed seed) makes each pixel's GI grow
+    monotonically, with positive increments that shrink (a contraction: gain x albedo
+    x coupling < 1) to a fixed point."""
+    cam = make_camera(48, 32, fov_y_deg=70, pitch_deg=-30)
+    gb = crease_gbuffer(cam, D=3.0, alpha=math.radians(60))
+    d = gb["radiance"].astype(np.float64)
+    albedo = np.full(d.shape, 0.7)
+    gi0 = np.ones(d.shape[:2] + (3,))
+    assert np.array_equal(O.inject_bounce(d, albedo, gi0, 0.0), d[..., :3])
+    assert np.array_equal(O.inject_bounce(d, albedo, 0 * gi0, 0.8), d[..., :3])
+    # a black surface reflects nothing; the reflected part scales with the albedo
+    assert np.array_equal(O.inject_bounce(d, 0 * albedo, gi0, 0.8), d[..., :3])
+    half = O.inject_bounce(d, 0.5 * albedo, gi0, 0.8) - d[..., :3]
+    assert np.allclose(O.inject_bounce(d, albedo, gi0, 0.8) - d[..., :3], 2 * half, rtol=1e-14, atol=0)
+    prm = O.Params(slices=4, steps=8, radius=2.0, thickness=INF, noise=O.NOISE_FIXED)
+    light = gb["radiance"]
+    sums, prev = [], None
+    for _ in range(6):
+        r = O.compute(gb["depth"], gb["normal"], light, ocam(O, cam), prm)
+        gi = r["gi"]
+        if prev is not None:
+            assert np.all(gi >= prev - 1e-12)       # more light never lowers GI
+        prev = gi
+        sums.append(gi.sum())
+        light = O.inject_bounce(gb["radiance"], albedo, gi, 0.9)
+    inc = np.diff(sums)
+    assert sums[0] > 0 and np.all(inc > 0)
+    assert np.all(inc[1:] / inc[:-1] < 1.0)
+    assert inc[-1] < 1e-6 * sums[-1]
+
+
 def pin_noise_statistics(O):
     """Rotations and jitters are uniform (chi-square) and the slices of one pixel are
     spread evenly over pi; the R2 rotation is a low-discrepancy dither."""
@@ -799,4 +833,5 @@ ALL_PINS = [
     pin_noise_statistics,
     pin_quadratic_steps,
     pin_half_resolution,
+    pin_multi_bounce,
 ]

@@ -58,6 +58,8 @@ MUTATIONS = {
     "upsampling not normalised": ("sao / sw, sgi / sw, samb / sw", "sao, sgi, samb"),
     "upsampling takes the far neighbour twice": ("[(y - 1, 0.5), (y + 1, 0.5)]", "[(y + 1, 0.5), (y + 1, 0.5)]"),
     "half resolution samples odd pixels": ("np.arange(0, H, 2), np.arange(0, W, 2)", "np.arange(1, H, 2), np.arange(1, W, 2)"),
+    "bounce ignores the albedo": ("return d + float(np.float32(gain)) * a * np.asarray", "return d + float(np.float32(gain)) * np.asarray"),
+    "bounce replaces the direct light": ("return d + float(np.float32(gain))", "return 0 * d + float(np.float32(gain))"),
     "background samples kept": ("ok &= np.isfinite(z_s) & (z_s > 0)", "ok &= np.isfinite(z_s)"),
     "step floor not clamped": ("return np.clip(q, q_min, q_max)", "return np.clip(q, 1, q_max)"),
 }
