@@ -219,6 +219,19 @@ ssvb_status ssvb_get_launch(ssvb_ctx* ctx, const ssvb_camera* camera, const ssvb
 ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stream, ssvb_launch* best,
                           float* best_ms);
 
+/* Multi-bounce indirect light (Section 4.3: the indirect light is injected into the light
+ * buffer used by the next frame, with its intensity balanced): writes, per pixel and RGB
+ * channel, next = direct + gain * albedo * gi.  direct and albedo: images of width x height
+ * (F32 or F16, 3 or 4 channels); gi: FP32 [height][width][3] as ssvb_compute writes it,
+ * row pitch gi_pitch_bytes (0 = dense); next: an image of the same channel count as
+ * direct (F32 or F16; F16 rounds to nearest even), its fourth channel, if any, copied
+ * from direct.  next may be direct itself (each element is read before it is written).
+ * gain finite and >= 0 (>= 1 lets repeated bounces grow without bound).  Asynchronous
+ * on hip_stream; validated before anything is launched. */
+ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, const ssvb_image* direct,
+                               const ssvb_image* albedo, const float* gi, int64_t gi_pitch_bytes, float gain,
+                               const ssvb_image* next, void* hip_stream);
+
 /* ---------------------------------------------------------------------------------
  * Request loop.  A server owns an arena of device memory (its HBM budget) and a
  * scheduler thread.  Submitted frames wait in arrival order until their footprint fits

@@ -30,7 +30,7 @@ EXPORTED = [
     "ssvb_validate", "ssvb_compute", "ssvb_compute_batch", "ssvb_set_launch", "ssvb_get_launch",
     "ssvb_autotune", "ssvb_debug_lattice", "ssvb_debug_endpoints", "ssvb_debug_direction_table",
     "ssvb_debug_noise_constants", "ssvb_server_create", "ssvb_server_submit", "ssvb_server_poll",
-    "ssvb_server_wait", "ssvb_server_release", "ssvb_server_stats", "ssvb_server_destroy",
+    "ssvb_server_wait", "ssvb_server_release", "ssvb_server_stats", "ssvb_server_destroy", "ssvb_inject_bounce",
 ]
 
 
@@ -131,6 +131,9 @@ def lib() -> ctypes.CDLL:
     L.ssvb_debug_direction_table.argtypes = [V, P(ctypes.c_int32)]
     L.ssvb_debug_noise_constants.restype = None
     L.ssvb_debug_noise_constants.argtypes = [P(ctypes.c_uint32)]
+    L.ssvb_inject_bounce.restype = I
+    L.ssvb_inject_bounce.argtypes = [V, I, I, P(ssvb_image), P(ssvb_image), V, ctypes.c_int64, ctypes.c_float,
+                                     P(ssvb_image), V]
     U64, D = ctypes.c_uint64, ctypes.c_double
     L.ssvb_server_create.restype = I
     L.ssvb_server_create.argtypes = [V, U64, I, P(V)]
@@ -314,6 +317,19 @@ class Context:
         for i, it in enumerate(items):
             arr[i] = self.frame(*it)
         check(lib().ssvb_compute_batch(self.handle, arr, len(items), _stream_ptr(stream)), "ssvb_compute_batch")
+
+    def inject_bounce(self, direct, albedo, gi, gain, out=None, stream=None):
+        """Light buffer for the next frame: direct + gain * albedo * gi (multi-bounce).
+        ``out`` defaults to a new tensor shaped and typed like ``direct``."""
+        import torch
+        H, W = direct.shape[:2]
+        if out is None:
+            out = torch.empty_like(direct)
+        d, a, o = image_of(direct), image_of(albedo), image_of(out)
+        check(lib().ssvb_inject_bounce(self.handle, W, H, ctypes.byref(d), ctypes.byref(a), gi.data_ptr(),
+                                       gi.stride(0) * 4, float(gain), ctypes.byref(o), _stream_ptr(stream)),
+              "ssvb_inject_bounce")
+        return out
 
     def set_launch(self, shape=None):
         """Force a launch shape (tile_w, tile_h, strip, lanes_per_pixel); None: automatic."""

@@ -639,6 +639,38 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
     return SSVB_OK;
 }
 
+ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, const ssvb_image* direct,
+                               const ssvb_image* albedo, const float* gi, int64_t gi_pitch_bytes, float gain,
+                               const ssvb_image* next, void* hip_stream) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    if (width < 0 || height < 0 || width > kMaxDim || height > kMaxDim)
+        return fail(SSVB_ERR_INVALID_ARG, "image %dx%d outside [0, %d]", width, height, kMaxDim);
+    if (!(finite(gain) && gain >= 0.0f)) return fail(SSVB_ERR_INVALID_ARG, "gain must be finite and >= 0");
+    ssvb_status s;
+    if ((s = check_image(direct, "direct", width, height, false))) return s;
+    if ((s = check_image(albedo, "albedo", width, height, false))) return s;
+    if ((s = check_image(next, "next", width, height, false))) return s;
+    if (next->channels != direct->channels)
+        return fail(SSVB_ERR_INVALID_ARG, "next has %d channels, direct %d", next->channels, direct->channels);
+    if ((int64_t)width * height == 0) return SSVB_OK;
+    if (!gi || (uintptr_t)gi % 4) return fail(SSVB_ERR_INVALID_ARG, "gi: NULL or misaligned");
+    if ((s = check_out_pitch(gi_pitch_bytes, (int64_t)width * 12, "gi"))) return s;
+    auto pitch = [&](const ssvb_image* im) {
+        return im->pitch_bytes ? im->pitch_bytes : (int64_t)width * im->channels * elem_size(im->dtype);
+    };
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (prev != ctx->device) (void)hipSetDevice(ctx->device);
+    const hipError_t e = launch_inject_bounce(
+        (const char*)direct->ptr, pitch(direct), direct->channels, direct->dtype == SSVB_F16, (const char*)albedo->ptr,
+        pitch(albedo), albedo->channels, albedo->dtype == SSVB_F16, gi,
+        gi_pitch_bytes ? gi_pitch_bytes : (int64_t)width * 12, (char*)next->ptr, pitch(next), next->channels,
+        next->dtype == SSVB_F16, width, height, gain, (hipStream_t)hip_stream);
+    if (prev != ctx->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "bounce launch");
+    return SSVB_OK;
+}
+
 ssvb_status ssvb_debug_lattice(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_camera* camera,
                                const ssvb_params* params, int32_t* xy_out, void* hip_stream) {
     if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");

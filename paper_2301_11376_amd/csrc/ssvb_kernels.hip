@@ -785,6 +785,48 @@ __global__ __launch_bounds__(kBlock) void upsample_half(FrameArgs A) {
     m[0] = a0, m[1] = a1, m[2] = a2;
 }
 
+// Multi-bounce: next = direct + gain * albedo * gi per pixel and RGB channel (FP32
+// arithmetic); one thread per pixel, each element read before it is written, so `next`
+// may be `direct`.
+struct BounceArgs {
+    const char* direct;
+    const char* albedo;
+    const float* gi;
+    char* next;
+    int64_t direct_pitch, albedo_pitch, gi_pitch, next_pitch;
+    int32_t W, H, direct_ch, albedo_ch, next_ch;
+    int32_t direct_f16, albedo_f16, next_f16;
+    float gain;
+};
+
+__global__ __launch_bounds__(kBlock) void inject_bounce(BounceArgs B) {
+    const int x = (int)(blockIdx.x * 64 + threadIdx.x % 64), y = (int)(blockIdx.y * 4 + threadIdx.x / 64);
+    if (x >= B.W || y >= B.H) return;
+    const float3 d = load3<-1>(B.direct, B.direct_pitch, B.direct_ch, B.direct_f16, x, y);
+    const float3 a = load3<-1>(B.albedo, B.albedo_pitch, B.albedo_ch, B.albedo_f16, x, y);
+    const GMEM float* g = (const GMEM float*)((const GMEM char*)B.gi + (int64_t)y * B.gi_pitch) + 3 * (int64_t)x;
+    const float r0 = fmaf(B.gain * a.x, g[0], d.x), r1 = fmaf(B.gain * a.y, g[1], d.y),
+                r2 = fmaf(B.gain * a.z, g[2], d.z);
+    GMEM char* row = (GMEM char*)B.next + (int64_t)y * B.next_pitch;
+    if (B.next_f16) {
+        GMEM _Float16* o = (GMEM _Float16*)row + (int64_t)x * B.next_ch;
+        if (B.next_ch == 4) {
+            const GMEM _Float16* ds = (const GMEM _Float16*)((const GMEM char*)B.direct + (int64_t)y * B.direct_pitch);
+            const GMEM float* df = (const GMEM float*)((const GMEM char*)B.direct + (int64_t)y * B.direct_pitch);
+            o[3] = B.direct_f16 ? ds[4 * x + 3] : (_Float16)df[4 * x + 3];
+        }
+        o[0] = (_Float16)r0, o[1] = (_Float16)r1, o[2] = (_Float16)r2;
+    } else {
+        GMEM float* o = (GMEM float*)row + (int64_t)x * B.next_ch;
+        if (B.next_ch == 4) {
+            const GMEM _Float16* ds = (const GMEM _Float16*)((const GMEM char*)B.direct + (int64_t)y * B.direct_pitch);
+            const GMEM float* df = (const GMEM float*)((const GMEM char*)B.direct + (int64_t)y * B.direct_pitch);
+            o[3] = B.direct_f16 ? (float)ds[4 * x + 3] : df[4 * x + 3];
+        }
+        o[0] = r0, o[1] = r1, o[2] = r2;
+    }
+}
+
 __global__ void reset_queues(uint32_t* q) {
     for (int i = (int)threadIdx.x; i < kBatchQueues; i += (int)blockDim.x) q[i] = 0u;
 }
@@ -850,6 +892,16 @@ hipError_t launch_plain(const FrameArgs& A, uint32_t* queues, int grid, hipStrea
 
 hipError_t launch_upsample(const FrameArgs& A, hipStream_t stream) {
     hipLaunchKernelGGL(upsample_half, dim3((A.W + 15) / 16, (A.H + 15) / 16), dim3(kBlock), 0, stream, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject_bounce(const char* direct, int64_t direct_pitch, int direct_ch, int direct_f16,
+                                const char* albedo, int64_t albedo_pitch, int albedo_ch, int albedo_f16,
+                                const float* gi, int64_t gi_pitch, char* next, int64_t next_pitch, int next_ch,
+                                int next_f16, int W, int H, float gain, hipStream_t stream) {
+    const BounceArgs B{direct, albedo, gi, next, direct_pitch, albedo_pitch, gi_pitch, next_pitch,
+                       W, H, direct_ch, albedo_ch, next_ch, direct_f16, albedo_f16, next_f16, gain};
+    hipLaunchKernelGGL(inject_bounce, dim3((W + 63) / 64, (H + 3) / 4), dim3(kBlock), 0, stream, B);
     return hipGetLastError();
 }
 
