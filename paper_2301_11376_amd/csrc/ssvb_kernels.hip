@@ -103,11 +103,11 @@ __device__ __forceinline__ float3 load3(const char* base, int64_t pitch, int ch,
 
 __device__ __forceinline__ bool is_geometry(float z) { return z > 0.0f && z < INFINITY; }
 
-// bits [0, k) for 0 <= k <= 32
-__device__ __forceinline__ uint32_t low_bits(int k) { return k >= 32 ? 0xFFFFFFFFu : ((1u << k) - 1u); }
+// bits [0, k) for 0 <= k <= 32 (the 64-bit shift makes k = 32 need no special case)
+__device__ __forceinline__ uint32_t low_bits(int k) { return (uint32_t)(1ull << k) - 1u; }
 
-// bits [a, b) of a 32-bit mask; empty when b <= a
-__device__ __forceinline__ uint32_t range_bits(int a, int b) { return low_bits(b) & ~low_bits(a); }
+// bits [a, b) of a 32-bit mask, for 0 <= a <= b <= 32 (every caller orders its ends)
+__device__ __forceinline__ uint32_t range_bits(int a, int b) { return low_bits(b) - low_bits(a); }
 
 // Within the guard band of an integer sector coordinate (the FP32 error in sectors grows
 // with N_b, so the band does too).
@@ -130,7 +130,7 @@ __device__ __forceinline__ SMask<NB> mask_none() {
     return m;
 }
 
-// sectors [a, b) for 0 <= a, b <= N_b
+// sectors [a, b) for 0 <= a <= b <= N_b
 template <int NB>
 __device__ __forceinline__ SMask<NB> mask_range(int a, int b) {
     SMask<NB> m;
