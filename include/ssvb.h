@@ -240,11 +240,13 @@ ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, con
  * (depth FP32, the normal and radiance buffers as given, AO + GI + ambient FP32).
  * An admitted frame holds that much of the arena until it has finished: its buffers that
  * are in host memory are copied into it on a copy stream (results copied back), buffers
- * already in this device's memory are read and written in place.  As soon as one of the server's compute
- * streams is idle, every admitted frame not yet started (at most 64) runs as one round
- * of the persistent batch kernel, so frames that arrive while a round is on the device
- * join the next one and rounds on different streams overlap.  Each frame's results are
- * those ssvb_compute writes for it with the launch shape of its class.
+ * already in this device's memory are read and written in place.  As soon as one of the
+ * server's compute streams is idle, every admitted frame not yet started (at most 64)
+ * forms one round on it: the frames' persistent single-frame launches back to back, then
+ * one completion event.  Frames that arrive while a round is on the device join the next
+ * one, and rounds on different streams overlap.  Every mode of ssvb_compute is served
+ * (128 sectors, half resolution; not slice masks).  Each frame's results are those
+ * ssvb_compute writes for it with the launch shape of its class.
  * Ownership: the frame's input and output pointers (device memory, or host memory that
  * should be pinned for the copies to be asynchronous) must stay valid, and the inputs
  * unchanged, until the request has finished; the outputs are written before `done` is

@@ -1,10 +1,11 @@
 // Request loop of the visibility-bitmask gather: frames are admitted by their HBM
 // footprint into a device arena owned by the server (FIFO); buffers in host memory are
 // staged through the arena on a copy stream, buffers already in device memory are used
-// in place; admitted frames are run in rounds of up to 64 through the persistent batch
-// kernel on two or more compute streams, so that a round can start while another is
-// still on the device.  Each request is stamped with its completion time once its
-// results are in the caller's buffers.
+// in place; admitted frames are run in rounds of up to 64 on two or more compute streams,
+// so that a round can start while another is still on the device.  A round enqueues its
+// frames back to back as persistent single-frame launches (the fastest kernel for each
+// frame's mode, 128 sectors and half resolution included).  Each request is stamped with
+// its completion time once its results are in the caller's buffers.
 #include <string.h>
 
 #include <algorithm>
@@ -89,10 +90,11 @@ struct ssvb_server {
     char* arena = nullptr;
     Admission adm;
     int nstreams = 0;
-    int grid = 0;
-    hipStream_t copy_stream = nullptr, cap_stream = nullptr;
+    int grid = 0;  // persistent workgroups of a single-frame launch
+    hipStream_t copy_stream = nullptr;
     hipStream_t streams[kMaxStreams] = {};
-    BatchSlot slots[kMaxStreams];
+    hipEvent_t done[kMaxStreams] = {};      // recorded after each round on its stream
+    uint32_t* counters[kMaxStreams] = {};   // queue counters: one set of 16 per frame of a round
     Round rounds[kMaxStreams];
     hipEvent_t staged = nullptr;  // recorded on copy_stream after each admission pass
 
@@ -149,15 +151,15 @@ hipError_t stage(ssvb_server* S, Request& r, uint64_t off) {
 
 hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs) {
     hipStream_t s = S->streams[k];
-    BatchSlot& B = S->slots[k];
-    std::vector<ssvb_frame> frames;
-    frames.reserve(rs.size());
-    for (const Request* r : rs) frames.push_back(r->staged);
-    // the slot's previous replay has completed (its round was retired), so its pinned
-    // descriptor table may be rewritten
-    build_batch(&S->tab, B.h_desc, frames.data(), (int)frames.size());
     hipError_t e = hipStreamWaitEvent(s, S->staged, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(B.exec, s);
+    // the stream's previous round has retired, so every counter set is back at zero
+    for (size_t j = 0; j < rs.size() && e == hipSuccess; ++j) {
+        const ssvb_frame& F = rs[j]->staged;
+        FrameArgs A;
+        fill_frame(A, &S->tab, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
+        e = launch_plain(A, S->counters[k] + 16 * j, S->grid, s);
+        if (e == hipSuccess && A.sub == 2) e = launch_upsample(A, s);
+    }
     for (const Request* r : rs) {
         if (e != hipSuccess) break;
         if (r->out_in_place) continue;  // the kernel wrote the caller's buffers
@@ -175,7 +177,7 @@ hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs) 
             e = hipMemcpy2DAsync(c[i].dst, c[i].pitch ? (size_t)c[i].pitch : c[i].row, c[i].src, c[i].row, c[i].row,
                                  (size_t)H, hipMemcpyDefault, s);
     }
-    if (e == hipSuccess) e = hipEventRecord(B.done, s);
+    if (e == hipSuccess) e = hipEventRecord(S->done[k], s);
     return e;
 }
 
@@ -202,7 +204,7 @@ void run(ssvb_server* S) {
         hipError_t q[kMaxStreams];
         if (nbusy) {
             lk.unlock();
-            for (int i = 0; i < nbusy; ++i) q[i] = hipEventQuery(S->slots[busy[i]].done);
+            for (int i = 0; i < nbusy; ++i) q[i] = hipEventQuery(S->done[busy[i]]);
             lk.lock();
         }
         const Clock::time_point now = Clock::now();
@@ -316,12 +318,12 @@ ssvb_status fatal_status(const ssvb_server* S) {
 
 void destroy_resources(ssvb_server* S) {
     for (int k = 0; k < kMaxStreams; ++k) {
-        free_slot(S->slots[k]);
+        if (S->done[k]) (void)hipEventDestroy(S->done[k]);
+        if (S->counters[k]) (void)hipFree(S->counters[k]);
         if (S->streams[k]) (void)hipStreamDestroy(S->streams[k]);
     }
     if (S->staged) (void)hipEventDestroy(S->staged);
     if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
-    if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
     if (S->arena) (void)hipFree(S->arena);
 }
 
@@ -349,13 +351,18 @@ ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t
     (void)hipSetDevice(S->device);
     hipError_t e = hipMalloc((void**)&S->arena, S->adm.arena().size());
     const bool oom = e == hipErrorOutOfMemory;
-    if (e == hipSuccess) e = batch_grid_size(S->device, &S->grid);
+    if (e == hipSuccess) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, S->device);
+        S->grid = prop.multiProcessorCount * frame_blocks_per_cu();
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->staged, hipEventDisableTiming);
     for (int k = 0; k < streams && e == hipSuccess; ++k) {
         e = hipStreamCreateWithFlags(&S->streams[k], hipStreamNonBlocking);
-        if (e == hipSuccess) e = init_slot(S->slots[k], S->grid, S->cap_stream);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&S->done[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc((void**)&S->counters[k], kMaxBatch * 16 * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemset(S->counters[k], 0, kMaxBatch * 16 * sizeof(uint32_t));
     }
     // a round waits on `staged` even before anything was staged: record it once
     if (e == hipSuccess) e = hipEventRecord(S->staged, S->copy_stream);
@@ -386,8 +393,6 @@ ssvb_status ssvb_server_submit(ssvb_server* S, const ssvb_frame* frame, uint64_t
     ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
     if (s) return s;
     if (F.out.masks) return fail(SSVB_ERR_INVALID_ARG, "served requests do not return slice masks");
-    if (F.params.resolution != 1) return fail(SSVB_ERR_UNSUPPORTED, "served requests run at full resolution");
-    if (F.params.sectors != 32) return fail(SSVB_ERR_UNSUPPORTED, "served requests run with 32 sectors");
     Request r;
     r.caller = F;
     r.lay = layout_of(F);

@@ -337,3 +337,28 @@ def test_mixed_residency(ctx):
             same(host(out), ref, mix)
     finally:
         srv.close()
+
+
+def test_served_modes(ctx):
+    """128 sectors, half resolution and quadratic steps are served like any frame: the
+    results equal ssvb_compute's bit for bit, in one mixed round or alone."""
+    import torch
+    from paper_2301_11376_amd import Server
+    items = make_items(SPECS[:4])
+    extra = [dict(sectors=128), dict(resolution=2), dict(step_distribution=1, sectors=128), dict(resolution=2,
+                                                                                               step_distribution=1)]
+    srv = Server(ctx, 512 << 20, streams=2)
+    try:
+        reqs = []
+        for (gb, cam, kw), ex in zip(items, extra):
+            kw = dict(kw, **ex)
+            t, bc, bp, out = device_request(gb, cam, kw)
+            torch.cuda.synchronize()
+            reqs.append((srv.submit(t["depth"], t["normal"], t["radiance"], bc, bp, out), out, gb, cam, kw))
+        for tk, out, gb, cam, kw in reqs:
+            srv.wait(tk, 60000)
+            same(host(out), plain(ctx, gb, cam, kw), kw)
+            srv.release(tk)
+        assert srv.stats()["failed"] == 0
+    finally:
+        srv.close()
