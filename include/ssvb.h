@@ -94,8 +94,8 @@ typedef struct {
 /* Sampling parameters (Algorithm 1; Sections 3.1-3.3).
  *  slices           N_d, hemisphere slices per pixel, 1..64
  *  steps            N_s, depth samples per side of each slice, 1..1024
- *  sectors          N_b, bits of the visibility mask: 32 or 128 (128: ssvb_compute only;
- *                   Section 4.1 reports 32 as enough and 128 as 5-10 % slower)
+ *  sectors          N_b, bits of the visibility mask: 32 or 128 (Section 4.1 reports 32
+ *                   as enough and 128 as 5-10 % slower)
  *  ambient_samples  N_a, ambient subregions per slice, at most 32, divides N_b
  *  radius           world-space radius of the screen-aligned hemisphere, > 0
  *  thickness        t0 >= 0 (+inf allowed: GTAO without falloff, Section 3.1)
@@ -109,8 +109,7 @@ typedef struct {
  *                   G-buffer), every other pixel averages its 1, 2 or 4 nearest gathered
  *                   pixels with weights bilinear x (1e-3 + exp(-((z - z_n)/(0.05 z))^2))
  *                   (background neighbours excluded; none left: AO 1, GI 0, ambient 0).
- *                   ssvb_compute only (batches and servers: SSVB_ERR_UNSUPPORTED); no
- *                   slice masks.
+ *                   No slice masks.
  *  hit_criterion    ssvb_hit_criterion
  *  noise, seed      ssvb_noise and its 32-bit seed
  *  ambient_sh       L2 real spherical-harmonic probe, world space, [9][3]
@@ -193,11 +192,12 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
                          const ssvb_image* radiance, const ssvb_camera* camera,
                          const ssvb_params* params, const ssvb_outputs* out, void* hip_stream);
 
-/* Many frames of mixed size, slice/step counts, criteria and element types in one
- * replay of a captured HIP graph (descriptor upload, queue reset, one persistent kernel
- * that works through the frames in the given order), asynchronous on `hip_stream`.  Each
- * frame's outputs equal, bit for bit, what ssvb_compute writes for it with the same
- * launch shape.  Frames are processed in chunks of 64.  The library keeps two descriptor
+/* Many frames of mixed size, slice/step counts, criteria, mask widths, resolutions and
+ * element types in one replay of a captured HIP graph (descriptor upload, queue reset, a
+ * persistent kernel per mask width present that works through its frames in the given
+ * order, then the half-resolution fill if any frame asks for it), asynchronous on
+ * `hip_stream`.  Each frame's outputs equal, bit for bit, what ssvb_compute writes for
+ * it with the same launch shape.  Frames are processed in chunks of 64.  The library keeps two descriptor
  * slots, so a call may block until the batch submitted two chunks earlier has finished.
  * Returns SSVB_ERR_INVALID_ARG naming the first invalid frame. */
 ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t n, void* hip_stream);

@@ -35,7 +35,7 @@ struct ssvb_ctx {
     uint64_t next_ring = 0;
     // batched path
     bool batch_ready = false;
-    int batch_grid = 0;
+    int batch_grid[2] = {0, 0};
     hipStream_t cap_stream = nullptr;
     BatchSlot slot[kBatchSlots];
     uint64_t next_slot = 0;
@@ -275,34 +275,51 @@ void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames,
     }
 }
 
-hipError_t batch_grid_size(int device, int* grid) {
+hipError_t batch_grid_size(int device, int grid[2]) {
     hipDeviceProp_t prop;
     hipError_t e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) return e;
-    const int per_cu = batch_blocks_per_cu();
-    *grid = ((prop.multiProcessorCount * per_cu + kXcds - 1) / kXcds) * kXcds;
+    for (int i = 0; i < 2; ++i) {
+        const int per_cu = batch_blocks_per_cu(i ? 128 : 32);
+        grid[i] = ((prop.multiProcessorCount * per_cu + kXcds - 1) / kXcds) * kXcds;
+    }
     return hipSuccess;
 }
 
-hipError_t init_slot(BatchSlot& s, int grid, hipStream_t cap_stream) {
+hipError_t init_slot(BatchSlot& s) {
     hipError_t e = hipHostMalloc((void**)&s.h_desc, sizeof(BatchDesc), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&s.d_desc, sizeof(BatchDesc));
     if (e == hipSuccess) e = hipMalloc((void**)&s.d_queues, kBatchQueues * sizeof(uint32_t));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-    memset(s.h_desc, 0, sizeof(BatchDesc));
-    e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
-    const hipError_t ce = capture_batch(s.d_desc, s.h_desc, s.d_queues, grid, cap_stream);
-    e = hipStreamEndCapture(cap_stream, &s.graph);
-    if (ce != hipSuccess) e = ce;
-    if (e == hipSuccess) e = hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) memset(s.h_desc, 0, sizeof(BatchDesc));
     return e;
 }
 
+hipError_t slot_graph(BatchSlot& s, int kinds, const int grid[2], hipStream_t cap_stream, hipGraphExec_t* exec) {
+    if (!s.exec[kinds]) {
+        hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        const hipError_t ce = capture_batch(s.d_desc, s.h_desc, s.d_queues, grid, kinds, cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cap_stream, &g);
+        if (ce != hipSuccess) e = ce;
+        if (e == hipSuccess) e = hipGraphInstantiate(&s.exec[kinds], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            s.exec[kinds] = nullptr;
+            return e;
+        }
+        s.graph[kinds] = g;
+    }
+    *exec = s.exec[kinds];
+    return hipSuccess;
+}
+
 void free_slot(BatchSlot& s) {
-    if (s.exec) (void)hipGraphExecDestroy(s.exec);
-    if (s.graph) (void)hipGraphDestroy(s.graph);
+    for (int i = 0; i < kBatchKinds; ++i) {
+        if (s.exec[i]) (void)hipGraphExecDestroy(s.exec[i]);
+        if (s.graph[i]) (void)hipGraphDestroy(s.graph[i]);
+    }
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.d_queues) (void)hipFree(s.d_queues);
     if (s.d_desc) (void)hipFree(s.d_desc);
@@ -338,9 +355,9 @@ void load_tune_cache(ssvb_ctx* ctx) {
 
 ssvb_status init_batch(ssvb_ctx* ctx) {
     if (ctx->batch_ready) return SSVB_OK;
-    hipError_t e = batch_grid_size(ctx->device, &ctx->batch_grid);
+    hipError_t e = batch_grid_size(ctx->device, ctx->batch_grid);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
-    for (int k = 0; k < kBatchSlots && e == hipSuccess; ++k) e = init_slot(ctx->slot[k], ctx->batch_grid, ctx->cap_stream);
+    for (int k = 0; k < kBatchSlots && e == hipSuccess; ++k) e = init_slot(ctx->slot[k]);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(SSVB_ERR_OUT_OF_MEMORY, "batch buffers")
                                                           : hip_fail(e, "batch set-up");
     ctx->batch_ready = true;
@@ -521,10 +538,6 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
         const ssvb_frame& F = frames[f];
         ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
         if (s) return fail(s, "frame %d: %s", f, last_error().c_str());
-        if (F.params.resolution != 1)
-            return fail(SSVB_ERR_UNSUPPORTED, "frame %d: batches run at full resolution", f);
-        if (F.params.sectors != 32)
-            return fail(SSVB_ERR_UNSUPPORTED, "frame %d: batches run with 32 sectors", f);
     }
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -534,15 +547,21 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
     for (int f0 = 0; st == SSVB_OK && f0 < n; f0 += kMaxBatch) {
         // frames with no pixels launch nothing
         std::vector<ssvb_frame> chunk;
-        for (int f = f0; f < std::min(n, f0 + kMaxBatch); ++f)
-            if ((int64_t)frames[f].camera.width * frames[f].camera.height > 0) chunk.push_back(frames[f]);
+        int kinds = 0;
+        for (int f = f0; f < std::min(n, f0 + kMaxBatch); ++f) {
+            const ssvb_frame& F = frames[f];
+            if ((int64_t)F.camera.width * F.camera.height == 0) continue;
+            chunk.push_back(F);
+            kinds |= (F.params.sectors == 128 ? kBatch128 : kBatch32) | (F.params.resolution == 2 ? kBatchHalf : 0);
+        }
         if (chunk.empty()) continue;
         BatchSlot& S = ctx->slot[ctx->next_slot++ % kBatchSlots];
-        hipError_t e = hipSuccess;
-        if (S.pending) e = hipEventSynchronize(S.done);  // the slot's last upload is done
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = slot_graph(S, kinds, ctx->batch_grid, ctx->cap_stream, &exec);
+        if (e == hipSuccess && S.pending) e = hipEventSynchronize(S.done);  // the slot's last upload is done
         if (e == hipSuccess) {
             build_batch(&ctx->tab, S.h_desc, chunk.data(), (int)chunk.size());
-            e = hipGraphLaunch(S.exec, stream);
+            e = hipGraphLaunch(exec, stream);
         }
         if (e == hipSuccess) e = hipEventRecord(S.done, stream);
         if (e != hipSuccess) st = hip_fail(e, "batch launch");

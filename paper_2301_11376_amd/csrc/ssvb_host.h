@@ -32,17 +32,20 @@ struct BatchSlot {
     BatchDesc* h_desc = nullptr;
     BatchDesc* d_desc = nullptr;
     uint32_t* d_queues = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[kBatchKinds] = {};  // captured on first use of each set of kinds
+    hipGraphExec_t exec[kBatchKinds] = {};
     hipEvent_t done = nullptr;
     bool pending = false;
 };
 
-// Workgroups of the persistent batch kernel on `device`: resident blocks per CU times
-// CUs, rounded up to a multiple of the XCD count.
-hipError_t batch_grid_size(int device, int* grid);
-// Allocate a slot and capture its graph on `cap_stream`.
-hipError_t init_slot(BatchSlot& s, int grid, hipStream_t cap_stream);
+// Workgroups of the persistent batch kernels on `device` (index 0: 32 sectors, 1: 128):
+// resident blocks per CU times CUs, rounded up to a multiple of the XCD count.
+hipError_t batch_grid_size(int device, int grid[2]);
+// Allocate a slot's descriptor and queue buffers.
+hipError_t init_slot(BatchSlot& s);
+// The slot's graph for the set of frame kinds `kinds` (kBatch32 | kBatch128 |
+// kBatchHalf), captured on `cap_stream` the first time it is asked for.
+hipError_t slot_graph(BatchSlot& s, int kinds, const int grid[2], hipStream_t cap_stream, hipGraphExec_t* exec);
 void free_slot(BatchSlot& s);
 
 // Frame constants (FP64 derivation, one rounding to FP32) and the launch shape from
@@ -67,9 +70,9 @@ hipError_t launch_inject_bounce(const char* direct, int64_t direct_pitch, int di
 hipError_t launch_upsample(const FrameArgs& A, hipStream_t stream);
 hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream);
 hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t stream);
-hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, int grid,
-                         hipStream_t s);
-int batch_blocks_per_cu();
+hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, const int grid[2],
+                         int kinds, hipStream_t s);
+int batch_blocks_per_cu(int sectors);
 
 // The device and the frame tables of a context.
 int ctx_device(const ssvb_ctx* ctx);

@@ -95,6 +95,8 @@ __device__ __forceinline__ void walk_tile(const FrameArgs& A, uint32_t ord, int&
 // ---------------------------------------------------------------------------------------
 constexpr int kMaxBatch = 64;  // frames per descriptor table (larger batches are chunked)
 constexpr int kBatchQueues = kMaxBatch * kXcds;  // one queue head per frame and XCD
+// kinds of frame in a batch; each set of kinds has its own captured graph
+constexpr int kBatch32 = 1, kBatch128 = 2, kBatchHalf = 4, kBatchKinds = 8;
 
 // Frames of one persistent launch and the order they are worked through.  Queue
 // f * kXcds + k holds run k of frame f's tile walk (the walk cut into kXcds equal runs).

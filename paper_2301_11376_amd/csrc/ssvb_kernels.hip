@@ -706,7 +706,10 @@ __global__ __launch_bounds__(kBlock) void debug_endpoints(FrameArgs A, float* ou
 // Many frames, persistent workgroups, frame by frame in the descriptor's order: for each
 // frame a workgroup drains its own XCD's run of the frame, then whatever is left of the
 // frame's other runs, and moves on to the next frame without waiting for the rest (as
-// back-to-back single-frame launches would, with their tails overlapped).
+// back-to-back single-frame launches would, with their tails overlapped).  One instance
+// per mask width: an instance skips the frames of the other width, so the 32-sector
+// instance keeps its register budget.
+template <int NB>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void gather_batch(
     const BatchDesc* __restrict__ D, uint32_t* __restrict__ queues) {
     __shared__ ExactLds L;
@@ -716,6 +719,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     for (int oi = 0; oi < n; ++oi) {
         const int f = D->order[oi];
         const FrameArgs& A = D->frames[f];
+        if (A.nb != NB) continue;
         const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
         const uint32_t per = (nt + kXcds - 1) / kXcds;
         const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
@@ -730,7 +734,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 walk_tile(A, first + item, tx, ty);
                 const int x = (tx * A.tile_w + px % A.tile_w) * A.sub;
                 const int y = (ty * A.tile_h + px / A.tile_w) * A.sub;
-                if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1>(A, L, x, y, li, lp, nullptr, nullptr);
+                if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1, NB>(A, L, x, y, li, lp, nullptr, nullptr);
             }
         }
     }
@@ -741,8 +745,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 // (0.05 z))^2)); background neighbours are left out; a background pixel, or one with no
 // computed foreground neighbour, gets AO = 1, GI = 0, ambient = 0.  Reads only computed
 // pixels and writes only the others, so it works in place on the outputs.
-__global__ __launch_bounds__(kBlock) void upsample_half(FrameArgs A) {
-    const int x = (int)(blockIdx.x * 16 + threadIdx.x % 16), y = (int)(blockIdx.y * 16 + threadIdx.x / 16);
+__device__ __forceinline__ void upsample_pixel(const FrameArgs& A, int x, int y) {
     if (x >= A.W || y >= A.H || ((x | y) & 1) == 0) return;
     const float z = depth_load(A, depth_off(A, x, y));
     float sw = 0.0f, sa = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, m0 = 0.0f, m1 = 0.0f, m2 = 0.0f;
@@ -783,6 +786,23 @@ __global__ __launch_bounds__(kBlock) void upsample_half(FrameArgs A) {
     g[0] = g0, g[1] = g1, g[2] = g2;
     GMEM float* m = (GMEM float*)((GMEM char*)A.amb + (int64_t)y * A.amb_pitch) + 3 * (int64_t)x;
     m[0] = a0, m[1] = a1, m[2] = a2;
+}
+
+__global__ __launch_bounds__(kBlock) void upsample_half(FrameArgs A) {
+    upsample_pixel(A, (int)(blockIdx.x * 16 + threadIdx.x % 16), (int)(blockIdx.y * 16 + threadIdx.x / 16));
+}
+
+// The same pass over every half-resolution frame of a batch: a fixed grid whose blocks
+// stride over each frame's 16 x 16 pixel blocks.
+__global__ __launch_bounds__(kBlock) void upsample_batch(const BatchDesc* __restrict__ D) {
+    const int n = D->n_frames;
+    for (int f = 0; f < n; ++f) {
+        const FrameArgs& A = D->frames[f];
+        if (A.sub != 2) continue;
+        const int bx = (A.W + 15) / 16, nblk = bx * ((A.H + 15) / 16);
+        for (int b = (int)blockIdx.x; b < nblk; b += (int)gridDim.x)
+            upsample_pixel(A, (b % bx) * 16 + (int)(threadIdx.x % 16), (b / bx) * 16 + (int)(threadIdx.x / 16));
+    }
 }
 
 // Multi-bounce: next = direct + gain * albedo * gi per pixel and RGB channel (FP32
@@ -834,19 +854,22 @@ __global__ void reset_queues(uint32_t* q) {
 // ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
-hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, int grid,
-                         hipStream_t s) {
+hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, const int grid[2],
+                         int kinds, hipStream_t s) {
     hipError_t e = hipMemcpyAsync((void*)d_desc, h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reset_queues, dim3(1), dim3(256), 0, s, d_queues);
-    hipLaunchKernelGGL(gather_batch, dim3(grid), dim3(kBlock), 0, s, d_desc, d_queues);
+    if (kinds & kBatch32) hipLaunchKernelGGL(gather_batch<32>, dim3(grid[0]), dim3(kBlock), 0, s, d_desc, d_queues);
+    if (kinds & kBatch128) hipLaunchKernelGGL(gather_batch<128>, dim3(grid[1]), dim3(kBlock), 0, s, d_desc, d_queues);
+    if (kinds & kBatchHalf) hipLaunchKernelGGL(upsample_batch, dim3(grid[0]), dim3(kBlock), 0, s, d_desc);
     return hipGetLastError();
 }
 
-int batch_blocks_per_cu() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gather_batch, kBlock, 0) != hipSuccess || nb < 1) nb = 2;
-    return nb;
+int batch_blocks_per_cu(int nb) {
+    int n = 0;
+    const hipError_t e = nb == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gather_batch<128>, kBlock, 0)
+                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gather_batch<32>, kBlock, 0);
+    return e == hipSuccess && n >= 1 ? n : 2;
 }
 static dim3 grid16(const FrameArgs& A) { return dim3((A.W + 15) / 16, (A.H + 15) / 16); }
 

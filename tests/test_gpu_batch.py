@@ -58,11 +58,29 @@ MIXED = [
                                ambient_samples=8, step_distribution=1)),
 ]
 
+# 128-sector and half-resolution frames, mixed in with 32-sector full-resolution ones
+MODES = [
+    (80, 50, 7, False, 3, dict(slices=3, steps=6, radius=1.5, thickness=0.3, noise=O.NOISE_HASH, seed=7,
+                               sectors=128, ambient_samples=8)),
+    (71, 47, 8, True, 4, dict(slices=2, steps=6, radius=1.8, thickness=0.4, noise=O.NOISE_R2, seed=8,
+                              resolution=2)),
+    (64, 41, 9, False, 3, dict(slices=2, steps=5, radius=1.2, thickness=INF, noise=O.NOISE_HASH, seed=9,
+                               sectors=128, resolution=2, hit_criterion=1)),
+    (57, 38, 10, True, 3, dict(slices=4, steps=4, radius=1.0, thickness=0.2, noise=O.NOISE_FIXED,
+                               sectors=128, step_distribution=1)),
+]
+
 
 def run_plain(ctx, gb, cam, kw):
     bc, _ = PY.cams(cam)
     bp, _ = PY.params(**kw)
-    return PY.gpu_run(ctx, gb, bc, bp)
+    return PY.gpu_run(ctx, gb, bc, bp, masks=kw.get("resolution", 1) == 1)
+
+
+def assert_same(g, ref, what):
+    assert set(g) == set(ref), what
+    for k in g:
+        assert np.array_equal(g[k].view(np.uint8), ref[k].view(np.uint8)), (what, k)
 
 
 def run_batch(ctx, items):
@@ -74,7 +92,8 @@ def run_batch(ctx, items):
         H, W = gb["depth"].shape
         bc, _ = PY.cams(cam)
         bp, _ = PY.params(**kw)
-        out = Context.alloc_outputs(H, W, kw["slices"], "cuda", masks=True)
+        out = Context.alloc_outputs(H, W, kw["slices"], "cuda", masks=kw.get("resolution", 1) == 1,
+                                    sectors=kw.get("sectors", 32))
         for v in out.values():
             v.fill_(-7)
         args.append((t["depth"], t["normal"], t["radiance"], bc, bp, out))
@@ -84,7 +103,8 @@ def run_batch(ctx, items):
     res = []
     for out in outs:
         r = {k: v.cpu().numpy() for k, v in out.items()}
-        r["masks"] = r["masks"].view(np.uint32)
+        if "masks" in r:
+            r["masks"] = r["masks"].view(np.uint32)
         res.append(r)
     return res
 
@@ -94,20 +114,38 @@ def test_batch_equals_plain_bitwise(ctx):
     log(f"batch of {len(items)} mixed frames")
     got = run_batch(ctx, items)
     for (gb, cam, kw), g in zip(items, got):
-        ref = run_plain(ctx, gb, cam, kw)
-        for k in ("ao", "gi", "ambient", "masks"):
-            assert np.array_equal(g[k].view(np.uint8), ref[k].view(np.uint8)), (cam.width, cam.height, k)
+        assert_same(g, run_plain(ctx, gb, cam, kw), (cam.width, cam.height))
+
+
+@pytest.mark.parametrize("mix", ["modes", "mixed+modes", "half-only", "128-only"])
+def test_batch_modes_equal_plain_bitwise(ctx, mix):
+    """Batches holding 128-sector and half-resolution frames (each set of frame kinds
+    replays its own graph): every frame as ssvb_compute writes it."""
+    specs = {"modes": MODES, "mixed+modes": [m for pair in zip(MIXED, MODES) for m in pair] + MIXED[4:],
+             "half-only": [MODES[1], MODES[2]], "128-only": [MODES[0], MODES[3]]}[mix]
+    items = scene_frames(specs)
+    log(f"batch {mix}: {len(items)} frames")
+    got = run_batch(ctx, items)
+    for (gb, cam, kw), g in zip(items, got):
+        assert_same(g, run_plain(ctx, gb, cam, kw), (cam.width, cam.height, kw.get("sectors", 32),
+                                                     kw.get("resolution", 1)))
 
 
 def test_batch_against_oracle(ctx):
-    items = scene_frames(MIXED[:4])
+    items = scene_frames(MIXED[:4] + MODES)
     got = run_batch(ctx, items)
     for (gb, cam, kw), g in zip(items, got):
-        log(f"batch frame {cam.width}x{cam.height} vs oracle")
+        log(f"batch frame {cam.width}x{cam.height} sectors {kw.get('sectors', 32)} "
+            f"resolution {kw.get('resolution', 1)} vs oracle")
         _, oc = PY.cams(cam)
         _, op = PY.params(**kw)
-        ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, return_masks=True)
-        PY.compare(g, ref, gb, oc, op)
+        if kw.get("resolution", 1) == 2:
+            ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op)
+            for k in ("ao", "gi", "ambient"):
+                assert np.abs(g[k] - ref[k]).max() <= 1e-3, k
+        else:
+            ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, return_masks=True)
+            PY.compare(g, ref, gb, oc, op)
 
 
 def test_batch_chunks_and_repeats(ctx):
