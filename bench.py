@@ -146,6 +146,27 @@ def timed(fn, stream, reps):
     return float(np.median(ts)), float(np.min(ts)), ts
 
 
+def stream_copy_gbs(mib=1024, reps=20):
+    """Measured device-to-device copy bandwidth (bytes read + written per second), the
+    practical ceiling beside the 8 TB/s spec figure: median of `reps` event-timed copies."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    s = torch.cuda.current_stream()
+    for a, b in ev:
+        a.record(s)
+        dst.copy_(src)
+        b.record(s)
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    del src, dst
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def batch_leg(ctx, pool, autotune):
     """64 mixed frames: 64 plain launches on one stream against one graph launch of the
     persistent batch kernel, both with the autotuned shape of each frame's class."""
@@ -476,6 +497,8 @@ def main():
     samples, abytes = algorithmic_bytes(W, H, kw["slices"], kw["steps"], w["fp16"])
     kernel_ms = float(per_launch_ms.mean())
     achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    copy_gbs = stream_copy_gbs()
+    floor_bytes = W * H * ((4 + 6 + 6 if w["fp16"] else 4 + 12 + 12) + 28)
     print(f"timed {args.steps} steps: {ms:.3f} ms/frame wall, kernel mean {kernel_ms:.3f} ms "
           f"(p50 {np.percentile(per_launch_ms, 50):.3f}, p99 {np.percentile(per_launch_ms, 99):.3f})",
           file=sys.stderr, flush=True)
@@ -501,7 +524,10 @@ def main():
                       "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
-                     "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": abytes},
+                     "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": abytes,
+                     "stream_copy_gbs": copy_gbs, "frac_of_stream_copy": achieved / copy_gbs,
+                     "compulsory_floor_bytes": floor_bytes,
+                     "compulsory_floor_ms": floor_bytes / (HBM_PEAK_GBS * 1e9) * 1e3},
     }
     if cpu is not None:
         result["cpu_baseline"] = cpu

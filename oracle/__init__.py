@@ -26,6 +26,8 @@ from .ssvb_oracle import (  # noqa: F401
     compute,
     bilateral_upsample,
     inject_bounce,
+    denoise,
+    DENOISE_KERNEL,
     UPSAMPLE_SIGMA,
     UPSAMPLE_FLOOR,
     sh_eval,

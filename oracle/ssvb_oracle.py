@@ -64,6 +64,16 @@ listed again in the design notes):
   R23 multi-bounce (Section 4.3: the indirect light is injected into the light buffer of
       the next frame, its intensity "balanced"): next light = direct + g albedo * GI per
       pixel and channel, with a gain g in [0, 1] as the balance.
+  R24 denoising (Section 4.1 and Table 2 time a denoising pass after the gather, 0.33 ms
+      at full and 0.1 ms at half resolution, but do not describe it): an edge-aware
+      a-trous filter.  P passes (1 to 3); pass i averages each foreground pixel's AO, GI
+      and ambient over the 5 x 5 taps p + 2^i (a, b) g, a, b in -2..2 (g = 1, or 2 at half
+      resolution, where the filter runs on the gathered even/even grid), with weights
+      h_a h_b exp(-(n_p . (P_q - P_p) / (sigma z_p))^2) max(0, n_p . n_q)^k, h = (1, 4,
+      6, 4, 1) / 16, P = z r(x, y) the view-space position and n the unit normal; the
+      centre's own weight is h_0^2; taps off the image or on background are left out and
+      the weights renormalised; a background pixel keeps its input.  At half resolution
+      the R22 upsampler then refills the pixels with an odd coordinate.
 """
 from __future__ import annotations
 
@@ -304,6 +314,62 @@ def bilateral_upsample(depth, ao, gi, amb):
                 ao_o[y, x], gi_o[y, x], amb_o[y, x] = sao / sw, sgi / sw, samb / sw
             else:
                 ao_o[y, x], gi_o[y, x], amb_o[y, x] = 1.0, 0.0, 0.0
+    return ao_o, gi_o, amb_o
+
+
+DENOISE_KERNEL = (1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16)  # B3 spline (R24)
+
+
+def denoise(depth, normal, cam: Camera, ao, gi, amb, passes=2, normal_power=16, plane_sigma=0.05,
+            resolution=1):
+    """Edge-aware a-trous denoising of the gather's outputs (reading R24), in FP64.
+    ``depth`` [H, W], ``normal`` [H, W, C >= 3] (FP16 upcast exactly), ``ao`` [H, W], ``gi``
+    / ``amb`` [H, W, 3].  Returns (ao, gi, amb)."""
+    H, W = depth.shape
+    g = 2 if resolution == 2 else 1
+    z = np.asarray(depth, dtype=np.float32).astype(np.float64)[::g, ::g]
+    fg = np.isfinite(z) & (z > 0)
+    n = np.asarray(normal)[::g, ::g, :3].astype(np.float64)
+    n = n / np.linalg.norm(n, axis=-1, keepdims=True).clip(1e-300)
+    gh, gw = z.shape
+    ys, xs = np.meshgrid(np.arange(gh) * g, np.arange(gw) * g, indexing="ij")
+    fx, fy, cx, cy = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy))
+    ray = np.stack([(xs + 0.5 - cx) / fx, -(ys + 0.5 - cy) / fy, -np.ones_like(z)], axis=-1)
+    pos = np.where(fg, z, 0.0)[..., None] * ray
+    zp = np.where(fg, z, 1.0)    # background pixels keep their input; any scale will do
+    sig = np.concatenate([np.asarray(ao, np.float64)[::g, ::g, None], np.asarray(gi, np.float64)[::g, ::g],
+                          np.asarray(amb, np.float64)[::g, ::g]], axis=-1)
+    inv_scale = 0.0 if math.isinf(plane_sigma) else 1.0 / float(np.float32(plane_sigma))
+    for i in range(passes):
+        s = 1 << i
+        acc = (DENOISE_KERNEL[2] ** 2) * sig
+        wsum = np.full((gh, gw), DENOISE_KERNEL[2] ** 2)
+        for b in range(-2, 3):
+            for a in range(-2, 3):
+                if a == 0 and b == 0:
+                    continue
+                dy, dx = b * s, a * s
+                # q = p + (dx, dy) grid cells; p ranges over the cells whose q is on the grid
+                py0, py1 = max(0, -dy), min(gh, gh - dy)
+                px0, px1 = max(0, -dx), min(gw, gw - dx)
+                if py0 >= py1 or px0 >= px1:
+                    continue
+                P_p = pos[py0:py1, px0:px1]
+                n_p = n[py0:py1, px0:px1]
+                Q = (slice(py0 + dy, py1 + dy), slice(px0 + dx, px1 + dx))
+                dist = np.sum(n_p * (pos[Q] - P_p), axis=-1) * inv_scale / zp[py0:py1, px0:px1]
+                w = (DENOISE_KERNEL[a + 2] * DENOISE_KERNEL[b + 2] * np.exp(-dist * dist)
+                     * np.maximum(0.0, np.sum(n_p * n[Q], axis=-1)) ** normal_power)
+                w = np.where(fg[Q], w, 0.0)
+                acc[py0:py1, px0:px1] += w[..., None] * sig[Q]
+                wsum[py0:py1, px0:px1] += w
+        sig = np.where(fg[..., None], acc / wsum[..., None], sig)
+    ao_o = np.array(ao, dtype=np.float64)
+    gi_o = np.array(gi, dtype=np.float64)
+    amb_o = np.array(amb, dtype=np.float64)
+    ao_o[::g, ::g], gi_o[::g, ::g], amb_o[::g, ::g] = sig[..., 0], sig[..., 1:4], sig[..., 4:7]
+    if g == 2:
+        ao_o, gi_o, amb_o = bilateral_upsample(depth, ao_o, gi_o, amb_o)
     return ao_o, gi_o, amb_o
 
 

@@ -739,6 +739,124 @@ def pin_half_resolution(O):
     assert np.allclose(rp["ambient"], np.asarray(C), rtol=1e-7, atol=0)
 
 
+def _atrous_kernel(s):
+    """The 5 x 5 B3-spline kernel (1, 4, 6, 4, 1)/16 squared, taps spread s cells apart."""
+    h = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0
+    K = np.zeros((4 * s + 1, 4 * s + 1))
+    K[::s, ::s] = np.outer(h, h)
+    return K
+
+
+def _label_pass(sig, labels, cross, s):
+    """One pass of the expected filter where a tap's weight depends only on the labels of
+    the pixel and the tap: out_p = sum_l C[L_p, l] corr(sig [L = l])_p / sum_l C[L_p, l]
+    corr([L = l])_p, zero-padded correlations from scipy; label -1 is background (never a
+    tap, keeps its input)."""
+    from scipy.ndimage import correlate
+    K = _atrous_kernel(s)
+    out = sig.copy()
+    n_l = cross.shape[0]
+    num = np.zeros((n_l,) + sig.shape)
+    den = np.zeros((n_l,) + labels.shape)
+    for l in range(n_l):
+        m = (labels == l).astype(np.float64)
+        den[l] = correlate(m, K, mode="constant", cval=0.0)
+        for c in range(sig.shape[-1]):
+            num[l, ..., c] = correlate(sig[..., c] * m, K, mode="constant", cval=0.0)
+    for lp in range(n_l):
+        sel = labels == lp
+        nn = sum(cross[lp, l] * num[l] for l in range(n_l))
+        dd = sum(cross[lp, l] * den[l] for l in range(n_l))
+        out[sel] = nn[sel] / dd[sel][..., None]
+    return out
+
+
+def _denoise_expected(sig, labels, cross, passes):
+    for i in range(passes):
+        sig = _label_pass(sig, labels, cross, 1 << i)
+    return sig
+
+
+def _run_denoise(O, gb, cam, sig, **kw):
+    a, g, m = O.denoise(gb["depth"], gb["normal"], ocam(O, cam), sig[..., 0], sig[..., 1:4], sig[..., 4:7], **kw)
+    return np.concatenate([a[..., None], g, m], -1)
+
+
+def pin_denoise(O):
+    """Denoising (reading R24) against scipy's normalised correlation: on a plane every tap
+    weight is the kernel's, so each pass is the zero-padded correlation with the B3
+    kernel spread 2^i apart, divided by the correlation of ones (fronto-parallel and
+    tilted planes, 1 to 3 passes, both resolutions); across a depth step or a normal
+    crease the weight falls to exp(-d^2) or max(0, n_p . n_q)^k per side; background
+    pixels are never taps and keep their input; a constant image stays constant."""
+    rng = np.random.default_rng(21)
+    cam = make_camera(13, 11, fov_y_deg=90, pitch_deg=0)
+    H, W = 11, 13
+    sig = rng.uniform(0.0, 1.0, (H, W, 7))
+    one = np.zeros((1, 1)) + 1.0
+    # planes: fronto-parallel and tilted (every tap on the plane: plane distance 0)
+    for nrm, P0 in (((0, 0, 1), (0, 0, -4.0)), ((0, 0.6, 0.8), (0, 0, -5.0)), ((0.3, -0.3, 0.8), (0, 0, -3.0))):
+        gb = plane_gbuffer(cam, nrm, P0)
+        assert np.all(gb["depth"] > 0)
+        for passes in (1, 2, 3):
+            got = _run_denoise(O, gb, cam, sig, passes=passes)
+            want = _denoise_expected(sig, np.zeros((H, W), int), one, passes)
+            assert np.allclose(got, want, atol=1e-9, rtol=0), (nrm, passes)
+        # half resolution: the filter on the even/even grid, then the upsampler
+        got = _run_denoise(O, gb, cam, sig, passes=2, resolution=2)
+        grid = _denoise_expected(sig[::2, ::2], np.zeros(((H + 1) // 2, (W + 1) // 2), int), one, 2)
+        assert np.allclose(got[::2, ::2], grid, atol=1e-9, rtol=0), nrm
+        full = sig.copy()
+        full[::2, ::2] = grid
+        a, g, m = O.bilateral_upsample(gb["depth"], full[..., 0], full[..., 1:4], full[..., 4:7])
+        assert np.allclose(got, np.concatenate([a[..., None], g, m], -1), atol=1e-12, rtol=0)
+    # depth steps on fronto-parallel layers: far apart (no bleed) and close (Gaussian falloff)
+    xs = np.arange(W)[None, :] * np.ones((H, 1))
+    lab = (xs >= 6).astype(int)
+    nz = np.zeros((H, W, 3), np.float32)
+    nz[..., 2] = 1.0
+    for z1, z2 in ((2.0, 3.0), (4.0, 4.2)):
+        depth = np.where(lab == 0, z1, z2).astype(np.float32)
+        zz = (float(np.float32(z1)), float(np.float32(z2)))
+        sigma = float(np.float32(0.05))
+        d01 = (zz[1] - zz[0]) / (sigma * zz[0])   # plane distance of a layer-1 tap from layer 0
+        d10 = (zz[1] - zz[0]) / (sigma * zz[1])
+        cross = np.array([[1.0, math.exp(-d01 * d01)], [math.exp(-d10 * d10), 1.0]])
+        gb = {"depth": depth, "normal": nz}
+        got = _run_denoise(O, gb, cam, sig, passes=2)
+        assert np.allclose(got, _denoise_expected(sig, lab, cross, 2), atol=1e-9, rtol=0), (z1, z2)
+    # normal creases at constant depth with the plane term off (sigma = inf): a tap of the
+    # other normal weighs max(0, n_p . n_q)^k
+    depth = np.full((H, W), 4.0, np.float32)
+    for n2, kpow in (((0, 0.6, 0.8), 2), ((0, 0.6, 0.8), 0), ((0, -0.6, -0.8), 2), ((1, 0, 0), 3)):
+        nrm = np.where((lab == 0)[..., None], (0.0, 0.0, 1.0), n2).astype(np.float32)
+        c = max(0.0, float(np.dot(np.asarray(n2, np.float32).astype(np.float64), (0, 0, 1)) /
+                           np.linalg.norm(np.asarray(n2, np.float32).astype(np.float64))))
+        cross = np.array([[1.0, c ** kpow], [c ** kpow, 1.0]])
+        gb = {"depth": depth, "normal": nrm}
+        got = _run_denoise(O, gb, cam, sig, passes=2, normal_power=kpow, plane_sigma=float("inf"))
+        assert np.allclose(got, _denoise_expected(sig, lab, cross, 2), atol=1e-9, rtol=0), (n2, kpow)
+    # background hole and border: background keeps its input and is never a tap
+    gb = plane_gbuffer(cam, (0, 0, 1), (0, 0, -4.0))
+    depth = gb["depth"].copy()
+    depth[3:6, 4:9] = 0.0
+    depth[0, 0] = np.inf
+    bg = (depth <= 0) | ~np.isfinite(depth)
+    lab = np.where(bg, -1, 0)
+    for sigma in (0.05, float("inf")):   # with the plane term off only the exclusion keeps them out
+        got = _run_denoise(O, dict(gb, depth=depth), cam, sig, passes=2, plane_sigma=sigma)
+        assert np.array_equal(got[bg], sig[bg])
+        assert np.allclose(got, _denoise_expected(sig, lab, one, 2), atol=1e-9, rtol=0), sigma
+    # a constant image on a real scene stays constant
+    gbs, cams, _ = tiny_scene()
+    Hs, Ws = gbs["depth"].shape
+    const = np.broadcast_to(np.array([0.7, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6]), (Hs, Ws, 7)).copy()
+    for res in (1, 2):
+        got = _run_denoise(O, gbs, cams, const, passes=3, resolution=res)
+        fgs = np.isfinite(gbs["depth"]) & (gbs["depth"] > 0)
+        assert np.allclose(got[fgs], const[fgs], atol=1e-12, rtol=0), res
+
+
 def pin_multi_bounce(O):
     """Multi-bounce (Section 4.3; reading R23): gain 0 or zero GI leaves the direct light;
     GI is linear and non-negative in the light buffer, so feeding it back frame after
@@ -834,4 +952,5 @@ ALL_PINS = [
     pin_quadratic_steps,
     pin_half_resolution,
     pin_multi_bounce,
+    pin_denoise,
 ]

@@ -62,6 +62,23 @@ MUTATIONS = {
     "bounce replaces the direct light": ("return d + float(np.float32(gain))", "return 0 * d + float(np.float32(gain))"),
     "background samples kept": ("ok &= np.isfinite(z_s) & (z_s > 0)", "ok &= np.isfinite(z_s)"),
     "step floor not clamped": ("return np.clip(q, q_min, q_max)", "return np.clip(q, 1, q_max)"),
+    "denoise kernel not the B3 spline": ("(1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16)",
+                                         "(1.0 / 9, 2.0 / 9, 3.0 / 9, 2.0 / 9, 1.0 / 9)"),
+    "a-trous spacing not doubled": ("s = 1 << i", "s = 1 + i"),
+    "denoise weight from the depth difference": ("np.sum(n_p * (pos[Q] - P_p), axis=-1) * inv_scale",
+                                                 "(z[Q] - z[py0:py1, px0:px1]) * inv_scale"),
+    "plane distance not relative to depth": ("* inv_scale / zp[py0:py1, px0:px1]", "* inv_scale"),
+    "plane falloff not Gaussian": ("np.exp(-dist * dist)", "np.exp(-np.abs(dist))"),
+    "normal weight not clamped": ("np.maximum(0.0, np.sum(n_p * n[Q], axis=-1)) ** normal_power",
+                                  "np.sum(n_p * n[Q], axis=-1) ** normal_power"),
+    "denoise keeps background taps": ("w = np.where(fg[Q], w, 0.0)", "w = np.where(True, w, 0.0)"),
+    "denoise centre weight one": ("wsum = np.full((gh, gw), DENOISE_KERNEL[2] ** 2)", "wsum = np.full((gh, gw), 1.0)"),
+    "denoise grid positions at half resolution": ("np.arange(gh) * g, np.arange(gw) * g",
+                                                  "np.arange(gh), np.arange(gw)"),
+    "denoise tap taken from the pixel": ("acc[py0:py1, px0:px1] += w[..., None] * sig[Q]",
+                                         "acc[py0:py1, px0:px1] += w[..., None] * sig[py0:py1, px0:px1]"),
+    "denoise background overwritten": ("sig = np.where(fg[..., None], acc / wsum[..., None], sig)",
+                                       "sig = acc / wsum[..., None]"),
 }
 
 
