@@ -232,6 +232,41 @@ ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, con
                                const ssvb_image* albedo, const float* gi, int64_t gi_pitch_bytes, float gain,
                                const ssvb_image* next, void* hip_stream);
 
+/* Parameters of ssvb_denoise.
+ *  passes        1..3: pass i averages over 5 x 5 taps 2^i cells apart
+ *  normal_power  k in 0..128: a tap weighs max(0, n_p . n_q)^k by its normal
+ *  plane_sigma   > 0 (+inf: no plane term): a tap weighs exp(-d^2) by its plane
+ *                distance d = n_p . (P_q - P_p) / (plane_sigma z_p), P the view-space
+ *                position z r(x, y) of the pixel centre
+ *  resolution    1: every pixel; 2: the outputs of a half-resolution ssvb_compute (the
+ *                filter runs on the pixels with both coordinates even, then the
+ *                half-resolution fill of ssvb_params.resolution refills the others) */
+typedef struct {
+    int32_t passes;
+    int32_t normal_power;
+    float plane_sigma;
+    int32_t resolution;
+} ssvb_denoise_params;
+
+/* passes 2, normal_power 16, plane_sigma 0.05, resolution 1 */
+void ssvb_default_denoise_params(ssvb_denoise_params* p);
+
+/* Edge-aware a-trous denoising of AO, GI and ambient (Section 4.1 and Table 2 time a
+ * denoising pass after the gather without describing it; this filter is the library's
+ * own): each pass replaces every foreground pixel's seven values by the average over its
+ * taps with weights h_a h_b exp(-d^2) max(0, n_p . n_q)^k, h = (1, 4, 6, 4, 1) / 16,
+ * the pixel's own weight h_0^2; taps off the image or on background (depth <= 0 or not
+ * finite) are left out; background pixels keep their input.  depth and normal as for
+ * ssvb_compute (the normal renormalised); camera: width, height, fx, fy, cx, cy.  `in`,
+ * `tmp` and `out` hold AO, GI and ambient as ssvb_compute writes them (masks must be
+ * NULL); the passes alternate between tmp and out so that the last one writes out; tmp
+ * is needed for 2 or 3 passes (NULL members allowed for 1).  The three sets must not
+ * overlap.  `in` is not modified.  Asynchronous on hip_stream; validated before anything
+ * is launched. */
+ssvb_status ssvb_denoise(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal,
+                         const ssvb_camera* camera, const ssvb_outputs* in, const ssvb_outputs* tmp,
+                         const ssvb_outputs* out, const ssvb_denoise_params* params, void* hip_stream);
+
 /* ---------------------------------------------------------------------------------
  * Request loop.  A server owns an arena of device memory (its HBM budget) and a
  * scheduler thread.  Submitted frames wait in arrival order until their footprint fits

@@ -31,6 +31,7 @@ EXPORTED = [
     "ssvb_autotune", "ssvb_debug_lattice", "ssvb_debug_endpoints", "ssvb_debug_direction_table",
     "ssvb_debug_noise_constants", "ssvb_server_create", "ssvb_server_submit", "ssvb_server_poll",
     "ssvb_server_wait", "ssvb_server_release", "ssvb_server_stats", "ssvb_server_destroy", "ssvb_inject_bounce",
+    "ssvb_default_denoise_params", "ssvb_denoise",
 ]
 
 
@@ -63,6 +64,11 @@ class ssvb_outputs(ctypes.Structure):
 class ssvb_frame(ctypes.Structure):
     _fields_ = [("depth", ssvb_image), ("normal", ssvb_image), ("radiance", ssvb_image), ("camera", ssvb_camera),
                 ("params", ssvb_params), ("out", ssvb_outputs)]
+
+
+class ssvb_denoise_params(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("normal_power", ctypes.c_int32), ("plane_sigma", ctypes.c_float),
+                ("resolution", ctypes.c_int32)]
 
 
 class ssvb_launch(ctypes.Structure):
@@ -134,6 +140,11 @@ def lib() -> ctypes.CDLL:
     L.ssvb_inject_bounce.restype = I
     L.ssvb_inject_bounce.argtypes = [V, I, I, P(ssvb_image), P(ssvb_image), V, ctypes.c_int64, ctypes.c_float,
                                      P(ssvb_image), V]
+    L.ssvb_default_denoise_params.restype = None
+    L.ssvb_default_denoise_params.argtypes = [P(ssvb_denoise_params)]
+    L.ssvb_denoise.restype = I
+    L.ssvb_denoise.argtypes = [V, P(ssvb_image), P(ssvb_image), P(ssvb_camera), P(ssvb_outputs), P(ssvb_outputs),
+                               P(ssvb_outputs), P(ssvb_denoise_params), V]
     U64, D = ctypes.c_uint64, ctypes.c_double
     L.ssvb_server_create.restype = I
     L.ssvb_server_create.argtypes = [V, U64, I, P(V)]
@@ -329,6 +340,29 @@ class Context:
         check(lib().ssvb_inject_bounce(self.handle, W, H, ctypes.byref(d), ctypes.byref(a), gi.data_ptr(),
                                        gi.stride(0) * 4, float(gain), ctypes.byref(o), _stream_ptr(stream)),
               "ssvb_inject_bounce")
+        return out
+
+    def denoise(self, depth, normal, camera: Camera, src, passes=2, normal_power=16, plane_sigma=0.05,
+                resolution=1, out=None, tmp=None, stream=None):
+        """Edge-aware a-trous denoising of ``src`` (dict ao, gi, ambient as ``compute``
+        returns it); returns ``out`` (new tensors by default).  ``tmp`` holds the
+        intermediate passes (allocated when needed and not given)."""
+        import torch
+
+        def like(s):
+            return {k: torch.empty_like(s[k]) for k in ("ao", "gi", "ambient")}
+
+        if out is None:
+            out = like(src)
+        if tmp is None and passes > 1:
+            tmp = like(src)
+        P = ssvb_denoise_params(int(passes), int(normal_power), float(plane_sigma), int(resolution))
+        d, n, c = image_of(depth), image_of(normal), camera.to_c()
+        i, o = self.outputs_of(src), self.outputs_of(out)
+        t = self.outputs_of(tmp) if tmp is not None else None
+        check(lib().ssvb_denoise(self.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(c), ctypes.byref(i),
+                                 ctypes.byref(t) if t is not None else None, ctypes.byref(o), ctypes.byref(P),
+                                 _stream_ptr(stream)), "ssvb_denoise")
         return out
 
     def set_launch(self, shape=None):

@@ -13,6 +13,7 @@
 #include <tuple>
 #include <vector>
 
+#include "ssvb_denoise.h"
 #include "ssvb_host.h"
 
 using namespace ssvb;
@@ -102,6 +103,43 @@ ssvb_status check_out_pitch(int64_t pitch, int64_t row, const char* name) {
         return fail(SSVB_ERR_INVALID_ARG, "%s: pitch %lld bytes (row needs %lld, multiple of 4)", name,
                     (long long)pitch, (long long)row);
     return SSVB_OK;
+}
+
+// AO / GI / ambient image set of width W: present, 4-byte aligned, pitches that fit
+ssvb_status check_signal(const ssvb_outputs* o, const char* name, int32_t W) {
+    if (!o) return fail(SSVB_ERR_INVALID_ARG, "%s: NULL outputs", name);
+    if (!o->ao || !o->gi || !o->ambient) return fail(SSVB_ERR_INVALID_ARG, "%s: ao, gi and ambient are required", name);
+    if (o->masks) return fail(SSVB_ERR_INVALID_ARG, "%s: masks must be NULL", name);
+    if (((uintptr_t)o->ao | (uintptr_t)o->gi | (uintptr_t)o->ambient) % 4)
+        return fail(SSVB_ERR_INVALID_ARG, "%s: must be 4-byte aligned", name);
+    ssvb_status s;
+    if ((s = check_out_pitch(o->ao_pitch_bytes, (int64_t)W * 4, name))) return s;
+    if ((s = check_out_pitch(o->gi_pitch_bytes, (int64_t)W * 12, name))) return s;
+    if ((s = check_out_pitch(o->ambient_pitch_bytes, (int64_t)W * 12, name))) return s;
+    return SSVB_OK;
+}
+
+// byte ranges [lo, hi) of the three images of a set
+void signal_ranges(const ssvb_outputs* o, int32_t W, int32_t H, uintptr_t lo[3], uintptr_t hi[3]) {
+    const int64_t row[3] = {(int64_t)W * 4, (int64_t)W * 12, (int64_t)W * 12};
+    const int64_t pitch[3] = {o->ao_pitch_bytes ? o->ao_pitch_bytes : row[0],
+                              o->gi_pitch_bytes ? o->gi_pitch_bytes : row[1],
+                              o->ambient_pitch_bytes ? o->ambient_pitch_bytes : row[2]};
+    const uintptr_t base[3] = {(uintptr_t)o->ao, (uintptr_t)o->gi, (uintptr_t)o->ambient};
+    for (int i = 0; i < 3; ++i) {
+        lo[i] = base[i];
+        hi[i] = base[i] + (uintptr_t)(pitch[i] * (H - 1) + row[i]);
+    }
+}
+
+bool sets_overlap(const ssvb_outputs* a, const ssvb_outputs* b, int32_t W, int32_t H) {
+    uintptr_t alo[3], ahi[3], blo[3], bhi[3];
+    signal_ranges(a, W, H, alo, ahi);
+    signal_ranges(b, W, H, blo, bhi);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (alo[i] < bhi[j] && blo[j] < ahi[i]) return true;
+    return false;
 }
 
 ssvb_status check_camera_params(const ssvb_camera* cam, const ssvb_params* p) {
@@ -687,6 +725,105 @@ ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, con
         next->dtype == SSVB_F16, width, height, gain, (hipStream_t)hip_stream);
     if (prev != ctx->device) (void)hipSetDevice(prev);
     if (e != hipSuccess) return hip_fail(e, "bounce launch");
+    return SSVB_OK;
+}
+
+void ssvb_default_denoise_params(ssvb_denoise_params* p) {
+    if (!p) return;
+    p->passes = 2;
+    p->normal_power = 16;
+    p->plane_sigma = 0.05f;
+    p->resolution = 1;
+}
+
+ssvb_status ssvb_denoise(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal, const ssvb_camera* camera,
+                         const ssvb_outputs* in, const ssvb_outputs* tmp, const ssvb_outputs* out,
+                         const ssvb_denoise_params* dp, void* hip_stream) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    if (!camera) return fail(SSVB_ERR_INVALID_ARG, "NULL camera");
+    if (!dp) return fail(SSVB_ERR_INVALID_ARG, "NULL denoise parameters");
+    const int W = camera->width, H = camera->height;
+    if (W < 0 || H < 0 || W > kMaxDim || H > kMaxDim)
+        return fail(SSVB_ERR_INVALID_ARG, "image %dx%d outside [0, %d]", W, H, kMaxDim);
+    if (!(finite(camera->fx) && camera->fx > 0 && finite(camera->fy) && camera->fy > 0))
+        return fail(SSVB_ERR_INVALID_ARG, "focal lengths must be finite and > 0");
+    if (!(finite(camera->cx) && finite(camera->cy))) return fail(SSVB_ERR_INVALID_ARG, "principal point not finite");
+    if (dp->passes < 1 || dp->passes > 3) return fail(SSVB_ERR_INVALID_ARG, "passes %d outside [1, 3]", dp->passes);
+    if (dp->normal_power < 0 || dp->normal_power > 128)
+        return fail(SSVB_ERR_INVALID_ARG, "normal_power %d outside [0, 128]", dp->normal_power);
+    if (!(dp->plane_sigma > 0)) return fail(SSVB_ERR_INVALID_ARG, "plane_sigma must be > 0 (inf allowed)");
+    if (dp->resolution != 1 && dp->resolution != 2)
+        return fail(SSVB_ERR_INVALID_ARG, "resolution divisor %d (need 1 or 2)", dp->resolution);
+    ssvb_status s;
+    if ((s = check_image(depth, "depth", W, H, true))) return s;
+    if ((s = check_image(normal, "normal", W, H, false))) return s;
+    if ((s = check_signal(in, "in", W))) return s;
+    if ((s = check_signal(out, "out", W))) return s;
+    if (dp->passes > 1 && (s = check_signal(tmp, "tmp", W))) return s;
+    if ((int64_t)W * H == 0) return SSVB_OK;
+    if (sets_overlap(in, out, W, H)) return fail(SSVB_ERR_INVALID_ARG, "in and out overlap");
+    if (dp->passes > 1 && (sets_overlap(in, tmp, W, H) || sets_overlap(tmp, out, W, H)))
+        return fail(SSVB_ERR_INVALID_ARG, "tmp overlaps in or out");
+
+    DenoiseArgs D{};
+    D.depth = (const float*)depth->ptr;
+    D.depth_pitch = depth->pitch_bytes ? depth->pitch_bytes : (int64_t)W * 4;
+    D.normal = (const char*)normal->ptr;
+    D.normal_ch = normal->channels;
+    D.normal_f16 = normal->dtype == SSVB_F16;
+    D.normal_pitch = normal->pitch_bytes ? normal->pitch_bytes : (int64_t)W * normal->channels * elem_size(normal->dtype);
+    D.W = W;
+    D.H = H;
+    D.g = dp->resolution;
+    D.gw = (W + D.g - 1) / D.g;
+    D.gh = (H + D.g - 1) / D.g;
+    D.tiles_x = (D.gw + kDenoiseTile - 1) / kDenoiseTile;
+    D.tiles = D.tiles_x * ((D.gh + kDenoiseTile - 1) / kDenoiseTile);
+    D.cx = camera->cx;
+    D.cy = camera->cy;
+    D.inv_fx = (float)(1.0 / camera->fx);
+    D.inv_fy = (float)(1.0 / camera->fy);
+    D.inv_sigma = isinf(dp->plane_sigma) ? 0.0f : (float)(1.0 / (double)dp->plane_sigma);
+    D.normal_power = dp->normal_power;
+    auto set_in = [&](const ssvb_outputs* o) {
+        D.in_ao = o->ao, D.in_gi = o->gi, D.in_amb = o->ambient;
+        D.in_ao_pitch = o->ao_pitch_bytes ? o->ao_pitch_bytes : (int64_t)W * 4;
+        D.in_gi_pitch = o->gi_pitch_bytes ? o->gi_pitch_bytes : (int64_t)W * 12;
+        D.in_amb_pitch = o->ambient_pitch_bytes ? o->ambient_pitch_bytes : (int64_t)W * 12;
+    };
+    auto set_out = [&](const ssvb_outputs* o) {
+        D.out_ao = o->ao, D.out_gi = o->gi, D.out_amb = o->ambient;
+        D.out_ao_pitch = o->ao_pitch_bytes ? o->ao_pitch_bytes : (int64_t)W * 4;
+        D.out_gi_pitch = o->gi_pitch_bytes ? o->gi_pitch_bytes : (int64_t)W * 12;
+        D.out_amb_pitch = o->ambient_pitch_bytes ? o->ambient_pitch_bytes : (int64_t)W * 12;
+    };
+    hipStream_t stream = (hipStream_t)hip_stream;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (prev != ctx->device) (void)hipSetDevice(ctx->device);
+    hipError_t e = hipSuccess;
+    const ssvb_outputs* src = in;
+    for (int i = 0; i < dp->passes && e == hipSuccess; ++i) {
+        // the passes alternate so that the last one writes `out`
+        const ssvb_outputs* dst = ((dp->passes - 1 - i) % 2 == 0) ? out : tmp;
+        set_in(src);
+        set_out(dst);
+        e = launch_denoise(D, i, stream);
+        src = dst;
+    }
+    if (e == hipSuccess && dp->resolution == 2) {
+        FrameArgs A;
+        memset(&A, 0, sizeof A);
+        A.depth = D.depth;
+        A.depth_pitch = D.depth_pitch;
+        A.W = W;
+        A.H = H;
+        A.ao = out->ao, A.gi = out->gi, A.amb = out->ambient;
+        A.ao_pitch = D.out_ao_pitch, A.gi_pitch = D.out_gi_pitch, A.amb_pitch = D.out_amb_pitch;
+        e = launch_upsample(A, stream);
+    }
+    if (prev != ctx->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "denoise launch");
     return SSVB_OK;
 }
 
