@@ -9,7 +9,7 @@
 //
 // One workgroup per 16 x 16-cell output tile.  The tile and its apron of 2 * 2^i cells
 // are staged once in LDS (view-space position, unit normal, the seven signal channels),
-// so every tap is an LDS read; the pass is ALU-bound (about 30 VALU operations per tap).
+// so every tap is an LDS read (48 bytes); the pass is bound by VALU issue and LDS reads.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -33,22 +33,31 @@ __device__ __forceinline__ float ipow(float c, int k) {
     return r;
 }
 
-template <int S>
+// c^k: K2 >= 0 means k = 2^K2 (K2 squarings), else the general square-and-multiply
+template <int K2>
+__device__ __forceinline__ float normal_weight(float c, int k) {
+    if (K2 < 0) return ipow(c, k);
+#pragma unroll
+    for (int i = 0; i < (K2 < 0 ? 0 : K2); ++i) c *= c;
+    return c;
+}
+
+constexpr float kSqrtLog2e = 1.20112240878644980f;  // sqrt(log2(e)): exp(-d^2) = 2^-(d sqrt(log2 e))^2
+
+template <int S, int K2>
 __global__ __launch_bounds__(kThreads) void denoise_pass(DenoiseArgs D) {
     constexpr int E = kDenoiseTile + 4 * S;  // staged tile edge, cells
     constexpr int N = E * E;
-    __shared__ float4 sP[N];  // position xyz, 1 on foreground (0 elsewhere)
-    __shared__ float4 sN[N];  // unit normal xyz, AO
-    __shared__ float4 sG[N];  // GI rgb, ambient r
-    __shared__ float2 sA[N];  // ambient g b
+    __shared__ float4 sA[N];  // depth (0 off the image or on background), unit normal xyz
+    __shared__ float4 sB[N];  // AO, GI rgb
+    __shared__ float4 sC[N];  // ambient rgb, unused
     const int tile = (int)blockIdx.x;
     const int u0 = (tile % D.tiles_x) * kDenoiseTile - 2 * S;
     const int v0 = (tile / D.tiles_x) * kDenoiseTile - 2 * S;
 
     for (int i = (int)threadIdx.x; i < N; i += kThreads) {
         const int u = u0 + i % E, v = v0 + i / E;
-        float4 P = make_float4(0.0f, 0.0f, 0.0f, 0.0f), Nn = P, G = P;
-        float2 Am = make_float2(0.0f, 0.0f);
+        float4 A = make_float4(0.0f, 0.0f, 0.0f, 0.0f), B = A, C = A;
         if (u >= 0 && v >= 0 && u < D.gw && v < D.gh) {
             const int x = u * D.g, y = v * D.g;
             const float z = *(const GMEM float*)((const GMEM char*)D.depth + (int64_t)y * D.depth_pitch + 4 * (int64_t)x);
@@ -63,21 +72,18 @@ __global__ __launch_bounds__(kThreads) void denoise_pass(DenoiseArgs D) {
                     nx = p[0], ny = p[1], nz = p[2];
                 }
                 const float l2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-                const float il = l2 > 0.0f ? 1.0f / sqrtf(l2) : 0.0f;
-                P = make_float4(z * (((float)x + 0.5f - D.cx) * D.inv_fx), -z * (((float)y + 0.5f - D.cy) * D.inv_fy), -z,
-                                1.0f);
-                const float ao = *(const GMEM float*)((const GMEM char*)D.in_ao + (int64_t)y * D.in_ao_pitch + 4 * (int64_t)x);
-                Nn = make_float4(nx * il, ny * il, nz * il, ao);
+                const float il = l2 > 0.0f ? __builtin_amdgcn_rsqf(l2) : 0.0f;
+                A = make_float4(z, nx * il, ny * il, nz * il);
                 const GMEM float* gi = (const GMEM float*)((const GMEM char*)D.in_gi + (int64_t)y * D.in_gi_pitch) + 3 * (int64_t)x;
                 const GMEM float* am = (const GMEM float*)((const GMEM char*)D.in_amb + (int64_t)y * D.in_amb_pitch) + 3 * (int64_t)x;
-                G = make_float4(gi[0], gi[1], gi[2], am[0]);
-                Am = make_float2(am[1], am[2]);
+                B = make_float4(*(const GMEM float*)((const GMEM char*)D.in_ao + (int64_t)y * D.in_ao_pitch + 4 * (int64_t)x),
+                                gi[0], gi[1], gi[2]);
+                C = make_float4(am[0], am[1], am[2], 0.0f);
             }
         }
-        sP[i] = P;
-        sN[i] = Nn;
-        sG[i] = G;
-        sA[i] = Am;
+        sA[i] = A;
+        sB[i] = B;
+        sC[i] = C;
     }
     __syncthreads();
 
@@ -86,54 +92,67 @@ __global__ __launch_bounds__(kThreads) void denoise_pass(DenoiseArgs D) {
     if (u >= D.gw || v >= D.gh) return;
     const int x = u * D.g, y = v * D.g;
     const int c = (ly + 2 * S) * E + lx + 2 * S;
-    const float4 Pp = sP[c];
+    const float4 Ap = sA[c];
     float r[7];
-    if (Pp.w == 0.0f) {
+    if (Ap.x == 0.0f) {
         // background keeps its input
         r[0] = *(const GMEM float*)((const GMEM char*)D.in_ao + (int64_t)y * D.in_ao_pitch + 4 * (int64_t)x);
         const GMEM float* gi = (const GMEM float*)((const GMEM char*)D.in_gi + (int64_t)y * D.in_gi_pitch) + 3 * (int64_t)x;
         const GMEM float* am = (const GMEM float*)((const GMEM char*)D.in_amb + (int64_t)y * D.in_amb_pitch) + 3 * (int64_t)x;
         r[1] = gi[0], r[2] = gi[1], r[3] = gi[2], r[4] = am[0], r[5] = am[1], r[6] = am[2];
     } else {
-        const float4 Np = sN[c];
-        const float4 Gp = sG[c];
-        const float2 Ap = sA[c];
+        const float4 Bp = sB[c];
+        const float4 Cp = sC[c];
+        const float zp = Ap.x, nx = Ap.y, ny = Ap.z, nz = Ap.w;
+        // plane distance of a tap (a, b) cells away, scaled: with r(x, y) the pixel's view
+        // ray, n_p . P_q = z_q (n_p . r_p + a nx S g / fx - b ny S g / fy), so
+        // d = z_q t_ab - z_p t_00 with t linear in a and b
+        const float sc = D.inv_sigma * kSqrtLog2e / zp;
+        const float rx = ((float)x + 0.5f - D.cx) * D.inv_fx, ry = -((float)y + 0.5f - D.cy) * D.inv_fy;
+        const float t0 = fmaf(nx, rx, fmaf(ny, ry, -nz)) * sc;
+        const float tx = nx * (float)(S * D.g) * D.inv_fx * sc;
+        const float ty = -ny * (float)(S * D.g) * D.inv_fy * sc;
+        const float cps = zp * t0;
         constexpr float hc = (6.0f / 16) * (6.0f / 16);
-        const float cp = fmaf(Np.x, Pp.x, fmaf(Np.y, Pp.y, Np.z * Pp.z));  // n_p . P_p
-        const float sc = D.inv_sigma / -Pp.z;                               // 1 / (sigma z_p)
         float sw = hc;
-        float a0 = hc * Np.w, a1 = hc * Gp.x, a2 = hc * Gp.y, a3 = hc * Gp.z, a4 = hc * Gp.w, a5 = hc * Ap.x,
-              a6 = hc * Ap.y;
+        float a0 = hc * Bp.x, a1 = hc * Bp.y, a2 = hc * Bp.z, a3 = hc * Bp.w, a4 = hc * Cp.x, a5 = hc * Cp.y,
+              a6 = hc * Cp.z;
         // one row of five taps per iteration (unrolling all 24 taps would hoist every LDS
         // read and spill)
 #pragma unroll 1
         for (int b = -2; b <= 2; ++b) {
-            const float hb = b == 0 ? 6.0f / 16 : (b == 1 || b == -1) ? 4.0f / 16 : 1.0f / 16;
+            // log2 of the B3 weight of the row
+            const float lhb = b == 0 ? -1.41503749927884382f : (b == 1 || b == -1) ? -2.0f : -4.0f;
             const int row = c + b * S * E;
+            const float tb = fmaf((float)b, ty, t0);
 #pragma unroll
             for (int a = -2; a <= 2; ++a) {
                 if (a == 0 && b == 0) continue;
-                const float ha = a == 0 ? 6.0f / 16 : (a == 1 || a == -1) ? 4.0f / 16 : 1.0f / 16;
+                const float lha = a == 0 ? -1.41503749927884382f : (a == 1 || a == -1) ? -2.0f : -4.0f;
                 const int q = row + a * S;
-                const float4 Pq = sP[q];
-                const float4 Nq = sN[q];
-                const float d = (fmaf(Np.x, Pq.x, fmaf(Np.y, Pq.y, Np.z * Pq.z)) - cp) * sc;
-                const float cn = fmaxf(0.0f, fmaf(Np.x, Nq.x, fmaf(Np.y, Nq.y, Np.z * Nq.z)));
-                const float w = (ha * hb) * Pq.w * __expf(-d * d) * ipow(cn, D.normal_power);
-                const float4 Gq = sG[q];
-                const float2 Aq = sA[q];
+                const float4 Aq = sA[q];
+                const float d = fmaf(Aq.x, fmaf((float)a, tx, tb), -cps);
+                const float cn = fmaxf(0.0f, fmaf(nx, Aq.y, fmaf(ny, Aq.z, nz * Aq.w)));
+                // h_a h_b exp(-d^2) = 2^(log2 h_a + log2 h_b - (d sqrt(log2 e))^2)
+                float w = __builtin_amdgcn_exp2f(fmaf(-d, d, lha + lhb)) * normal_weight<K2>(cn, D.normal_power);
+                // off the image or on background: normal 0, so for k >= 1 the weight is
+                // already 0; k = 0 needs the test
+                if (K2 < 1) w = Aq.x > 0.0f ? w : 0.0f;
+                const float4 Bq = sB[q];
+                const float4 Cq = sC[q];
                 sw += w;
-                a0 = fmaf(w, Nq.w, a0);
-                a1 = fmaf(w, Gq.x, a1);
-                a2 = fmaf(w, Gq.y, a2);
-                a3 = fmaf(w, Gq.z, a3);
-                a4 = fmaf(w, Gq.w, a4);
-                a5 = fmaf(w, Aq.x, a5);
-                a6 = fmaf(w, Aq.y, a6);
+                a0 = fmaf(w, Bq.x, a0);
+                a1 = fmaf(w, Bq.y, a1);
+                a2 = fmaf(w, Bq.z, a2);
+                a3 = fmaf(w, Bq.w, a3);
+                a4 = fmaf(w, Cq.x, a4);
+                a5 = fmaf(w, Cq.y, a5);
+                a6 = fmaf(w, Cq.z, a6);
             }
         }
-        r[0] = a0 / sw, r[1] = a1 / sw, r[2] = a2 / sw, r[3] = a3 / sw, r[4] = a4 / sw, r[5] = a5 / sw,
-        r[6] = a6 / sw;
+        const float inv = __builtin_amdgcn_rcpf(sw);
+        r[0] = a0 * inv, r[1] = a1 * inv, r[2] = a2 * inv, r[3] = a3 * inv, r[4] = a4 * inv, r[5] = a5 * inv,
+        r[6] = a6 * inv;
     }
     *(GMEM float*)((GMEM char*)D.out_ao + (int64_t)y * D.out_ao_pitch + 4 * (int64_t)x) = r[0];
     GMEM float* go = (GMEM float*)((GMEM char*)D.out_gi + (int64_t)y * D.out_gi_pitch) + 3 * (int64_t)x;
@@ -142,14 +161,22 @@ __global__ __launch_bounds__(kThreads) void denoise_pass(DenoiseArgs D) {
     mo[0] = r[4], mo[1] = r[5], mo[2] = r[6];
 }
 
+template <int S>
+void launch_pass(const DenoiseArgs& D, hipStream_t stream) {
+    if (D.normal_power == 16)
+        hipLaunchKernelGGL((denoise_pass<S, 4>), dim3(D.tiles), dim3(kThreads), 0, stream, D);
+    else
+        hipLaunchKernelGGL((denoise_pass<S, -1>), dim3(D.tiles), dim3(kThreads), 0, stream, D);
+}
+
 }  // namespace
 
 hipError_t launch_denoise(const DenoiseArgs& D, int pass, hipStream_t stream) {
     if (D.tiles <= 0) return hipSuccess;
     switch (pass) {
-        case 0: hipLaunchKernelGGL(denoise_pass<1>, dim3(D.tiles), dim3(kThreads), 0, stream, D); break;
-        case 1: hipLaunchKernelGGL(denoise_pass<2>, dim3(D.tiles), dim3(kThreads), 0, stream, D); break;
-        case 2: hipLaunchKernelGGL(denoise_pass<4>, dim3(D.tiles), dim3(kThreads), 0, stream, D); break;
+        case 0: launch_pass<1>(D, stream); break;
+        case 1: launch_pass<2>(D, stream); break;
+        case 2: launch_pass<4>(D, stream); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
