@@ -20,6 +20,7 @@ from .procedural import (
     workload,
     WORKLOADS,
     mixed_batch,
+    small_batch,
     request_stream,
     render_pool,
     as_format,
@@ -38,6 +39,7 @@ __all__ = [
     "workload",
     "WORKLOADS",
     "mixed_batch",
+    "small_batch",
     "request_stream",
     "render_pool",
     "as_format",

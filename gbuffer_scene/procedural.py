@@ -374,6 +374,26 @@ def mixed_batch(seed: int = 4, n_frames: int = 64, pool: int = 4):
     return frames
 
 
+SMALL_RESOLUTIONS = [(256, 144), (320, 180), (480, 270), (640, 360)]
+
+
+def small_batch(seed: int = 6, n_frames: int = 64, pool: int = 2):
+    """Draws of a batch of small frames (probes, thumbnails, distant views): resolution
+    uniform over SMALL_RESOLUTIONS, slices over {2, 4}, steps over {8, 16}, FP32
+    G-buffers, the scene one of ``pool`` seeds per resolution, noise seed = frame index;
+    radius 3, t 0.5, R2."""
+    rng = np.random.default_rng(seed)
+    frames = []
+    for i in range(n_frames):
+        W, H = SMALL_RESOLUTIONS[int(rng.integers(len(SMALL_RESOLUTIONS)))]
+        nd = int(rng.choice([2, 4]))
+        ns = int(rng.choice([8, 16]))
+        sc = POOL_SEED0 + int(rng.integers(pool))
+        frames.append(dict(width=W, height=H, scene_seed=sc, slices=nd, steps=ns, noise_seed=i, fp16=False,
+                           radius=3.0, thickness=0.5, noise="r2"))
+    return frames
+
+
 def request_stream(seed: int = 5, n_requests: int = 2000, pool: int = 2):
     """Draws of a served request stream: resolution uniform over SERVE_RESOLUTIONS, slices
     uniform over 2..8, steps over {8, 16, 32}, FP16 or FP32 normals and radiance with

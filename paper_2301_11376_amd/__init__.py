@@ -7,6 +7,7 @@ the library; the first call that needs it does, and fails loudly if it is missin
 from .binding import (  # noqa: F401
     Camera,
     Context,
+    FrameArray,
     Params,
     SSVBError,
     Server,

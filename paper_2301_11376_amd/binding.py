@@ -255,6 +255,13 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+class FrameArray:
+    """Frames already marshalled for the C ABI (see Context.frames)."""
+
+    def __init__(self, arr, n):
+        self.arr, self.n = arr, n
+
+
 class Context:
     """An ssvb_ctx on one device (torch's current device by default)."""
 
@@ -321,13 +328,29 @@ class Context:
         return ssvb_frame(image_of(depth), image_of(normal), image_of(radiance), camera.to_c(), params.to_c(),
                           self.outputs_of(out))
 
-    def compute_batch(self, items, stream=None):
-        """items: list of (depth, normal, radiance, camera, params, out) with torch device
-        tensors; runs ssvb_compute_batch (one graph replay per 64 frames)."""
+    def frames(self, items):
+        """Marshal (depth, normal, radiance, camera, params, out) tuples once into an
+        ssvb_frame array, for repeated compute_batch / compute_each calls."""
         arr = (ssvb_frame * max(len(items), 1))()
         for i, it in enumerate(items):
             arr[i] = self.frame(*it)
-        check(lib().ssvb_compute_batch(self.handle, arr, len(items), _stream_ptr(stream)), "ssvb_compute_batch")
+        return FrameArray(arr, len(items))
+
+    def compute_batch(self, items, stream=None):
+        """items: list of (depth, normal, radiance, camera, params, out) with torch device
+        tensors, or a FrameArray from frames(); runs ssvb_compute_batch (one graph replay
+        per 64 frames)."""
+        fa = items if isinstance(items, FrameArray) else self.frames(items)
+        check(lib().ssvb_compute_batch(self.handle, fa.arr, fa.n, _stream_ptr(stream)), "ssvb_compute_batch")
+
+    def compute_each(self, fa, stream=None):
+        """One ssvb_compute call per frame of a FrameArray, back to back on one stream."""
+        L, s, h = lib(), _stream_ptr(stream), self.handle
+        for i in range(fa.n):
+            F = fa.arr[i]
+            check(L.ssvb_compute(h, ctypes.byref(F.depth), ctypes.byref(F.normal), ctypes.byref(F.radiance),
+                                 ctypes.byref(F.camera), ctypes.byref(F.params), ctypes.byref(F.out), s),
+                  "ssvb_compute")
 
     def inject_bounce(self, direct, albedo, gi, gain, out=None, stream=None):
         """Light buffer for the next frame: direct + gain * albedo * gi (multi-bounce).
