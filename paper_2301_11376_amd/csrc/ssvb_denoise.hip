@@ -51,7 +51,11 @@ __global__ __launch_bounds__(kThreads) void denoise_pass(DenoiseArgs D) {
     __shared__ float4 sA[N];  // depth (0 off the image or on background), unit normal xyz
     __shared__ float4 sB[N];  // AO, GI rgb
     __shared__ float4 sC[N];  // ambient rgb, unused
-    const int tile = (int)blockIdx.x;
+    // workgroup b runs on XCD b mod 8: give each XCD one contiguous run of tiles (rows of
+    // tiles, so that the aprons it stages overlap in its own L2)
+    const int run = (D.tiles + 7) / 8;
+    const int tile = ((int)blockIdx.x % 8) * run + (int)blockIdx.x / 8;
+    if (tile >= D.tiles) return;
     const int u0 = (tile % D.tiles_x) * kDenoiseTile - 2 * S;
     const int v0 = (tile / D.tiles_x) * kDenoiseTile - 2 * S;
 
@@ -163,10 +167,11 @@ __global__ __launch_bounds__(kThreads) void denoise_pass(DenoiseArgs D) {
 
 template <int S>
 void launch_pass(const DenoiseArgs& D, hipStream_t stream) {
+    const int grid = 8 * ((D.tiles + 7) / 8);  // whole runs, one per XCD
     if (D.normal_power == 16)
-        hipLaunchKernelGGL((denoise_pass<S, 4>), dim3(D.tiles), dim3(kThreads), 0, stream, D);
+        hipLaunchKernelGGL((denoise_pass<S, 4>), dim3(grid), dim3(kThreads), 0, stream, D);
     else
-        hipLaunchKernelGGL((denoise_pass<S, -1>), dim3(D.tiles), dim3(kThreads), 0, stream, D);
+        hipLaunchKernelGGL((denoise_pass<S, -1>), dim3(grid), dim3(kThreads), 0, stream, D);
 }
 
 }  // namespace
