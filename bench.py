@@ -58,15 +58,17 @@ def device_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload_name):
+def measured_traffic(workload_name, shape):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes
-    (scaled by the copy calibration), or None when the device code has changed since."""
+    (scaled by the copy calibration), or None when the device code or the launch shape has
+    changed since."""
     path = os.path.join(ROOT, "profiles", f"gather_frame_{workload_name}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("device_source_sha256") != device_source_sha256() or rec.get("workload") != workload_name:
+    if (rec.get("device_source_sha256") != device_source_sha256() or rec.get("workload") != workload_name
+            or rec.get("launch_shape") != list(shape)):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -525,6 +527,7 @@ def main():
     p = Params(**dict(kw, noise=NOISE_NAMES[w["noise"]]))
     stream = torch.cuda.current_stream()
 
+    shape = ctx.get_launch(c, p, 1 * (w["fp16"]) | 2 * (w["fp16"]))
     for _ in range(args.warmup):
         ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
     torch.cuda.synchronize()
@@ -570,8 +573,9 @@ def main():
         "kernel_ms": {"mean": kernel_ms, "p50": float(np.percentile(per_launch_ms, 50)),
                       "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, shape),
                      "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": abytes,
+                     "launch_shape": list(shape),
                      "stream_copy_gbs": copy_gbs, "frac_of_stream_copy": achieved / copy_gbs,
                      "compulsory_floor_bytes": floor_bytes,
                      "compulsory_floor_ms": floor_bytes / (HBM_PEAK_GBS * 1e9) * 1e3},
