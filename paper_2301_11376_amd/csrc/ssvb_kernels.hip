@@ -432,7 +432,12 @@ __device__ __forceinline__ void march_sample(const FrameArgs& A, const SliceF& S
 // newly covered count, as a side-by-side march would produce it.
 //  li/lp  this lane's index among the lp lanes that share the pixel (adjacent lanes, lp a
 //         power of two); lane li takes slices li, li + lp, ...
-template <int CRIT, int MODE, bool TINF, int FMT, int NB, bool QUAD>
+//  QUAD   quadratic step distribution
+//  FAR    every step is at least one pixel long, so no sample can fall on the centre
+//         texel and its test is left out: the offset is then >= 16/16 px along a
+//         direction of length >= 4095/4096, while a sample in the centre texel lies
+//         within 0.5 px of the centre on both axes, i.e. within 0.71 px
+template <int CRIT, int MODE, bool TINF, int FMT, int NB, bool QUAD, bool FAR>
 __device__ __forceinline__ void gather_pixel_steps(const FrameArgs& A, ExactLds& L, int x, int y, int li, int lp,
                                                    int32_t* dbg_i, float* dbg_f) {
     const int t = (int)threadIdx.x;
@@ -506,7 +511,7 @@ __device__ __forceinline__ void gather_pixel_steps(const FrameArgs& A, ExactLds&
                     const int so = side ? -o : o;
                     const int X = (x16 + so * D.x) >> 16, Y = (y16 + so * D.y) >> 16;
                     const bool ok = j0 + u < A.ns && (unsigned)X < (unsigned)A.W && (unsigned)Y < (unsigned)A.H &&
-                                    !(X == x && Y == y) && geom;
+                                    (FAR || !(X == x && Y == y)) && geom;
                     zs[u][side] = depth_load(A, ok ? depth_off(A, X, Y) : own);
                 }
             }
@@ -520,8 +525,8 @@ __device__ __forceinline__ void gather_pixel_steps(const FrameArgs& A, ExactLds&
                     const int s = side ? -1 : 1;
                     const int so = side ? -o : o;
                     const int X = (x16 + so * D.x) >> 16, Y = (y16 + so * D.y) >> 16;
-                    const bool ok = (unsigned)X < (unsigned)A.W && (unsigned)Y < (unsigned)A.H && !(X == x && Y == y) &&
-                                    geom;
+                    const bool ok = (unsigned)X < (unsigned)A.W && (unsigned)Y < (unsigned)A.H &&
+                                    (FAR || !(X == x && Y == y)) && geom;
                     if (MODE == MODE_ENDPOINTS) {
                         const float z = zs[u][side];
                         if (!(ok && is_geometry(z))) continue;
@@ -613,10 +618,13 @@ __device__ __forceinline__ void gather_pixel_steps(const FrameArgs& A, ExactLds&
 template <int CRIT, int MODE, bool TINF, int FMT, int NB = 32>
 __device__ __forceinline__ void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int li, int lp,
                                              int32_t* dbg_i, float* dbg_f) {
+    // uniform steps are q (j + 1) + jitter >= q >= q_min 1/16 px long
     if (A.step_dist == SSVB_STEPS_QUADRATIC)
-        gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, true>(A, L, x, y, li, lp, dbg_i, dbg_f);
+        gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, true, false>(A, L, x, y, li, lp, dbg_i, dbg_f);
+    else if (A.q_min >= 16)
+        gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, false, true>(A, L, x, y, li, lp, dbg_i, dbg_f);
     else
-        gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, false>(A, L, x, y, li, lp, dbg_i, dbg_f);
+        gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, false, false>(A, L, x, y, li, lp, dbg_i, dbg_f);
 }
 
 // The XCD this wave runs on (hardware register XCC_ID; the die's own L2 serves it).
