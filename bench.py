@@ -317,6 +317,25 @@ def denoise_leg(ctx, t, c, out, steps):
             "algorithmic_bytes": nbytes, "achieved_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
 
 
+def bounce_leg(ctx, t, out, steps):
+    """Multi-bounce injection (next = direct + gain * albedo * GI) on the 1080p frame: the
+    frame's radiance as the direct light, a constant albedo, its GI; median of `steps`
+    event-timed calls; algorithmic bytes 12 + 12 + 12 read and 12 written per pixel (FP32,
+    3 channels)."""
+    import torch
+    H, W = t["depth"].shape
+    albedo = torch.full((H, W, 3), 0.6, device="cuda")
+    nxt = torch.empty_like(t["radiance"])
+    stream = torch.cuda.current_stream()
+    fn = lambda: ctx.inject_bounce(t["radiance"], albedo, out["gi"], 0.8, out=nxt)
+    fn()
+    med, mn, _ = timed(fn, stream, steps)
+    nbytes = W * H * 48
+    gbs = nbytes / (med * 1e-3) / 1e9
+    return {"workload": f"{W}x{H}, FP32 3-channel direct light and albedo, FP32 GI", "ms": med, "ms_min": mn,
+            "algorithmic_bytes": nbytes, "achieved_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+
+
 def sectors_leg(ctx, t, c, p):
     """The headline frame with 128 visibility sectors against 32 (Section 4.1 reports a
     5-10 % overhead for 128 on its GPU); median of 20 launches each."""
@@ -587,6 +606,9 @@ def main():
         print("table2: " + ", ".join(f"{r['row']} {r['ms']:.3f} ms" for r in result["table2"]["rows"]),
               file=sys.stderr, flush=True)
         result["denoise"] = denoise_leg(ctx, t, c, out, 20)
+        result["bounce"] = bounce_leg(ctx, t, out, 20)
+        print(f"bounce: {result['bounce']['ms']:.3f} ms, {result['bounce']['achieved_gbs']:.0f} GB/s",
+              file=sys.stderr, flush=True)
         print(f"denoise: {result['denoise']['ms']:.3f} ms", file=sys.stderr, flush=True)
         result["sectors128"] = sectors_leg(ctx, t, c, p)
         print(f"sectors: 32 {result['sectors128']['ms_32']:.3f} ms, 128 {result['sectors128']['ms_128']:.3f} ms",
