@@ -115,7 +115,19 @@ def cpu_baseline(gb, cam, kw, rows_per_worker=48):
             "sample": f"rows {bands[0][0]}..{bands[-1][1] - 1} of the same frame ({px} px, {samples} samples) "
                       f"in {workers} bands of {rows_per_worker} rows, one single-threaded NumPy FP64 process "
                       f"per band; {wall:.1f} s wall, {sum(per):.1f} s CPU",
-            "single_process_value": samples / sum(per) / 1e9}
+            "single_process_value": samples / sum(per) / 1e9, "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 # ---------------------------------------------------------------------------------------
@@ -588,7 +600,8 @@ def main():
         "config": {"workload": f"{args.workload}: {W}x{H}, {kw['slices']} slices x {kw['steps']} steps per side, "
                                f"N_b 32, radius {kw['radius']}, thickness {kw['thickness']:.4g}, noise {w['noise']}, "
                                f"procedural scene seed {w['seed']} ({w['n_boxes']} boxes, {w['n_planes']} thin planes)",
-                   "samples_per_frame": samples, "pixels": W * H, "parallelism": "single GPU"},
+                   "samples_per_frame": samples, "pixels": W * H, "parallelism": "single GPU",
+                   "device": torch.cuda.get_device_name(dev), "hip": torch.version.hip},
         "kernel_ms": {"mean": kernel_ms, "p50": float(np.percentile(per_launch_ms, 50)),
                       "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
