@@ -163,6 +163,13 @@ VARIANTS = {
                                        ambient_samples=32),
     "quadratic_pseudocode_tinf": dict(slices=2, steps=8, radius=1.5, thickness=INF, noise=O.NOISE_HASH, seed=21,
                                       step_distribution=1, hit_criterion=1),
+    # the largest slice and step counts the library accepts
+    "max_slices": dict(slices=64, steps=2, radius=1.0, thickness=0.3, noise=O.NOISE_HASH, seed=44, ambient_samples=32),
+    "max_slices_128": dict(slices=64, steps=2, radius=1.0, thickness=0.3, noise=O.NOISE_R2, seed=45, sectors=128,
+                           ambient_samples=32),
+    "max_steps": dict(slices=1, steps=1024, radius=6.0, thickness=0.4, noise=O.NOISE_R2, seed=46, min_step_q4=1),
+    "max_steps_quadratic": dict(slices=1, steps=1024, radius=6.0, thickness=INF, noise=O.NOISE_HASH, seed=47,
+                                min_step_q4=1, step_distribution=1),
 }
 
 
