@@ -603,6 +603,7 @@ def main():
                    "samples_per_frame": samples, "pixels": W * H, "parallelism": "single GPU",
                    "device": torch.cuda.get_device_name(dev), "hip": torch.version.hip},
         "kernel_ms": {"mean": kernel_ms, "p50": float(np.percentile(per_launch_ms, 50)),
+                      "p90": float(np.percentile(per_launch_ms, 90)),
                       "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, shape),
@@ -613,6 +614,7 @@ def main():
                      "compulsory_floor_ms": floor_bytes / (HBM_PEAK_GBS * 1e9) * 1e3},
     }
     if cpu is not None:
+        cpu["gpu_speedup"] = result["value"] / cpu["value"]
         result["cpu_baseline"] = cpu
     if not args.no_table2 and args.workload == "c2_1080p":
         result["table2"] = table2_leg(ctx, t, c, scene, slices=1)
