@@ -209,3 +209,56 @@ def test_autotune(ctx):
     assert shape[0] * shape[1] * shape[3] == 256 and ms > 0
     assert ctx.get_launch(bc, bp) == shape
     torch.cuda.synchronize()
+
+
+def test_batch_full_sizes(ctx):
+    """One batch holding the headline frames at full size (1920x1080 FP32 with two sample
+    counts, 3840x2160 FP16 at its 8 x 32 samples, 128x128, and the 1080p frame at half
+    resolution and at 128 sectors): every frame equals its single-frame launch bit for
+    bit, and the oracle agrees on a seeded sample of pixels."""
+    import torch
+    from gbuffer_scene import workload
+    from paper_2301_11376_amd import Context
+    specs = []
+    for name, kw in (("c2_1080p", dict(slices=4, steps=16, radius=3.0, thickness=0.5, noise=O.NOISE_R2, seed=2)),
+                     ("c3_4k_fp16", dict(slices=8, steps=32, radius=8.0, noise=O.NOISE_R2, seed=3)),
+                     ("c1_128", dict(slices=2, steps=8, radius=2.0, thickness=0.5, noise=O.NOISE_HASH, seed=1)),
+                     ("c2_1080p", dict(slices=2, steps=8, radius=3.0, thickness=0.5, noise=O.NOISE_R2, seed=9)),
+                     ("c2_1080p", dict(slices=2, steps=16, radius=4.0, thickness=0.2, noise=O.NOISE_R2, seed=7,
+                                       step_distribution=1, resolution=2)),
+                     ("c2_1080p", dict(slices=2, steps=8, radius=3.0, thickness=0.5, noise=O.NOISE_HASH, seed=5,
+                                       sectors=128))):
+        gb, cam, w, sc = workload(name)
+        kw = dict(kw, ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+        if "thickness" not in kw:
+            kw["thickness"] = w["thickness"]
+        specs.append((gb, cam, kw))
+    log(f"batch of {len(specs)} full-size frames")
+    args, outs = [], []
+    for gb, cam, kw in specs:
+        H, W = gb["depth"].shape
+        t = PY.to_device(gb)
+        bc, _ = PY.cams(cam)
+        bp, _ = PY.params(**kw)
+        out = Context.alloc_outputs(H, W, kw["slices"], "cuda")
+        args.append((t["depth"], t["normal"], t["radiance"], bc, bp, out))
+        outs.append(out)
+    ctx.compute_batch(args)
+    torch.cuda.synchronize()
+    for i, ((gb, cam, kw), out) in enumerate(zip(specs, outs)):
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        ref_plain = run_plain(ctx, gb, cam, dict(kw))
+        ref_plain.pop("masks", None)
+        assert_same(got, ref_plain, (i, cam.width, cam.height))
+        H, W = gb["depth"].shape
+        ys, xs = PY.sample_pixels(H, W, 300, 10 + i)
+        if kw.get("resolution", 1) == 2:
+            # the gathered pixels of a half-resolution frame are the full-resolution gather's
+            ys, xs = ys - ys % 2, xs - xs % 2
+        _, oc = PY.cams(cam)
+        _, op = PY.params(**dict(kw, resolution=1))
+        ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, pixels=(ys, xs))
+        err = max(float(np.abs(got[k][ys, xs] - ref[k]).max()) for k in ("ao", "gi", "ambient"))
+        log(f"  frame {i} {cam.width}x{cam.height} {kw.get('sectors', 32)} sectors, resolution "
+            f"{kw.get('resolution', 1)}: max |error| at {len(ys)} sampled pixels {err:.2e}")
+        assert err <= 1e-3, i
