@@ -311,6 +311,43 @@ void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames,
         fill_frame(D->frames[f], tab, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
         D->order[f] = f;
     }
+    // packed lists of the small frames per mask width: tile-count prefix sums, and runs of
+    // equal sample cost (a tile costs tile pixels x slices x steps)
+    for (int w = 0; w < 2; ++w) {
+        int m = 0;
+        uint32_t tiles = 0;
+        double total = 0.0;
+        D->prefix[w][0] = 0;
+        for (int oi = 0; oi < n; ++oi) {
+            const int f = D->order[oi];
+            const FrameArgs& A = D->frames[f];
+            if ((A.nb == 128) != (w == 1)) continue;
+            D->packed[f] = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y <= kPackTiles;
+            if (!D->packed[f]) continue;
+            D->plist[w][m] = f;
+            tiles += (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+            D->prefix[w][++m] = tiles;
+            total += (double)A.tiles_x * A.tiles_y * A.tile_w * A.tile_h * A.nd * A.ns;
+        }
+        D->pn[w] = m;
+        D->split[w][0] = 0;
+        int k = 1;
+        double acc = 0.0;
+        for (int j = 0; j < m && k < kXcds; ++j) {
+            const FrameArgs& A = D->frames[D->plist[w][j]];
+            const double per_tile = (double)A.tile_w * A.tile_h * A.nd * A.ns;
+            const uint32_t nt = D->prefix[w][j + 1] - D->prefix[w][j];
+            // the tiles of this frame at which the cumulative cost crosses k / kXcds of the total
+            while (k < kXcds && acc + nt * per_tile >= total * k / kXcds) {
+                const double need = total * k / kXcds - acc;
+                uint32_t t = (uint32_t)ceil(need / per_tile);
+                if (t > nt) t = nt;
+                D->split[w][k++] = D->prefix[w][j] + t;
+            }
+            acc += nt * per_tile;
+        }
+        while (k <= kXcds) D->split[w][k++] = tiles;
+    }
 }
 
 hipError_t batch_grid_size(int device, int grid[2]) {
