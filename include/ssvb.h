@@ -194,10 +194,14 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
 
 /* Many frames of mixed size, slice/step counts, criteria, mask widths, resolutions and
  * element types in one replay of a captured HIP graph (descriptor upload, queue reset, a
- * persistent kernel per mask width present that works through its frames in the given
- * order, then the half-resolution fill if any frame asks for it), asynchronous on
- * `hip_stream`.  Each frame's outputs equal, bit for bit, what ssvb_compute writes for
- * it with the same launch shape.  Frames are processed in chunks of 64.  The library keeps two descriptor
+ * persistent kernel per mask width present, then the half-resolution fill if any frame
+ * asks for it), asynchronous on `hip_stream`.  Small frames (at most 8,192 tiles) are
+ * packed into one list of tiles cut into equal-cost runs, one per XCD; larger frames
+ * follow in the given order, each with its own per-XCD runs.  Each frame's outputs equal,
+ * bit for bit, what ssvb_compute writes for it with the same launch shape.  The first
+ * batch with a new set of frame kinds (mask widths, half resolution) captures that set's
+ * graph on the calling thread: meanwhile no other thread may synchronise the whole
+ * device.  Frames are processed in chunks of 64.  The library keeps two descriptor
  * slots, so a call may block until the batch submitted two chunks earlier has finished.
  * Returns SSVB_ERR_INVALID_ARG naming the first invalid frame. */
 ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t n, void* hip_stream);
@@ -277,8 +281,10 @@ ssvb_status ssvb_denoise(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
  * are in host memory are copied into it on a copy stream (results copied back), buffers
  * already in this device's memory are read and written in place.  As soon as one of the
  * server's compute streams is idle, every admitted frame not yet started (at most 64)
- * forms one round on it: the frames' persistent single-frame launches back to back, then
- * one completion event.  Frames that arrive while a round is on the device join the next
+ * forms one round on it: its small frames (at most 8,192 tiles, 1920x1080 at the default
+ * shape) in one launch of the batch kernel with their tiles packed into one list, its
+ * larger frames as persistent single-frame launches back to back, then one completion
+ * event.  Frames that arrive while a round is on the device join the next
  * one, and rounds on different streams overlap.  Every mode of ssvb_compute is served
  * (128 sectors, half resolution; not slice masks).  Each frame's results are those
  * ssvb_compute writes for it with the launch shape of its class.

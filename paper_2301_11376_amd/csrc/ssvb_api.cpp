@@ -374,7 +374,7 @@ hipError_t slot_graph(BatchSlot& s, int kinds, const int grid[2], hipStream_t ca
     if (!s.exec[kinds]) {
         hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        const hipError_t ce = capture_batch(s.d_desc, s.h_desc, s.d_queues, grid, kinds, cap_stream);
+        const hipError_t ce = enqueue_batch(s.d_desc, s.h_desc, s.d_queues, grid, kinds, cap_stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cap_stream, &g);
         if (ce != hipSuccess) e = ce;

@@ -70,7 +70,7 @@ hipError_t launch_inject_bounce(const char* direct, int64_t direct_pitch, int di
 hipError_t launch_upsample(const FrameArgs& A, hipStream_t stream);
 hipError_t launch_debug_lattice(const FrameArgs& A, int32_t* out, hipStream_t stream);
 hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t stream);
-hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, const int grid[2],
+hipError_t enqueue_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, const int grid[2],
                          int kinds, hipStream_t s);
 int batch_blocks_per_cu(int sectors);
 

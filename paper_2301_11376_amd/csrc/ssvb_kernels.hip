@@ -889,7 +889,7 @@ __global__ void reset_queues(uint32_t* q) {
 // ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
-hipError_t capture_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, const int grid[2],
+hipError_t enqueue_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, const int grid[2],
                          int kinds, hipStream_t s) {
     hipError_t e = hipMemcpyAsync((void*)d_desc, h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;

@@ -2,10 +2,12 @@
 // footprint into a device arena owned by the server (FIFO); buffers in host memory are
 // staged through the arena on a copy stream, buffers already in device memory are used
 // in place; admitted frames are run in rounds of up to 64 on two or more compute streams,
-// so that a round can start while another is still on the device.  A round enqueues its
-// frames back to back as persistent single-frame launches (the fastest kernel for each
-// frame's mode, 128 sectors and half resolution included).  Each request is stamped with
-// its completion time once its results are in the caller's buffers.
+// so that a round can start while another is still on the device.  A round runs its small
+// frames (at most kPackTiles tiles) in one launch of the batch kernel, their tiles packed
+// into one list, and enqueues its larger frames back to back as persistent single-frame
+// launches (the fastest kernel for each frame's mode, 128 sectors and half resolution
+// included).  Each request is stamped with its completion time once its results are in
+// the caller's buffers.
 #include <string.h>
 
 #include <algorithm>
@@ -95,6 +97,8 @@ struct ssvb_server {
     hipStream_t streams[kMaxStreams] = {};
     hipEvent_t done[kMaxStreams] = {};      // recorded after each round on its stream
     uint32_t* counters[kMaxStreams] = {};   // queue counters: one set of 16 per frame of a round
+    BatchSlot slot[kMaxStreams];            // the packed small frames of a round, per stream
+    int batch_grid[2] = {0, 0};
     Round rounds[kMaxStreams];
     hipEvent_t staged = nullptr;  // recorded on copy_stream after each admission pass
 
@@ -152,13 +156,34 @@ hipError_t stage(ssvb_server* S, Request& r, uint64_t off) {
 hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs) {
     hipStream_t s = S->streams[k];
     hipError_t e = hipStreamWaitEvent(s, S->staged, 0);
-    // the stream's previous round has retired, so every counter set is back at zero
-    for (size_t j = 0; j < rs.size() && e == hipSuccess; ++j) {
-        const ssvb_frame& F = rs[j]->staged;
+    // the stream's previous round has retired: every counter set is back at zero and the
+    // slot's descriptor upload is done
+    ssvb_frame small[kMaxBatch];
+    int n_small = 0, kinds = 0;
+    std::vector<FrameArgs> large;
+    large.reserve(rs.size());
+    for (const Request* r : rs) {
+        const ssvb_frame& F = r->staged;
+        if ((int64_t)F.camera.width * F.camera.height == 0) continue;
         FrameArgs A;
         fill_frame(A, &S->tab, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
-        e = launch_plain(A, S->counters[k] + 16 * j, S->grid, s);
-        if (e == hipSuccess && A.sub == 2) e = launch_upsample(A, s);
+        if ((uint32_t)A.tiles_x * (uint32_t)A.tiles_y <= kPackTiles) {
+            small[n_small++] = F;
+            kinds |= (F.params.sectors == 128 ? kBatch128 : kBatch32) | (F.params.resolution == 2 ? kBatchHalf : 0);
+        } else {
+            large.push_back(A);
+        }
+    }
+    if (e == hipSuccess && n_small > 0) {
+        // enqueued directly (a graph capture on this thread could collide with a device-wide
+        // synchronisation by the caller's threads)
+        BatchSlot& B = S->slot[k];
+        build_batch(&S->tab, B.h_desc, small, n_small);
+        e = enqueue_batch(B.d_desc, B.h_desc, B.d_queues, S->batch_grid, kinds, s);
+    }
+    for (size_t j = 0; j < large.size() && e == hipSuccess; ++j) {
+        e = launch_plain(large[j], S->counters[k] + 16 * j, S->grid, s);
+        if (e == hipSuccess && large[j].sub == 2) e = launch_upsample(large[j], s);
     }
     for (const Request* r : rs) {
         if (e != hipSuccess) break;
@@ -318,6 +343,7 @@ ssvb_status fatal_status(const ssvb_server* S) {
 
 void destroy_resources(ssvb_server* S) {
     for (int k = 0; k < kMaxStreams; ++k) {
+        free_slot(S->slot[k]);
         if (S->done[k]) (void)hipEventDestroy(S->done[k]);
         if (S->counters[k]) (void)hipFree(S->counters[k]);
         if (S->streams[k]) (void)hipStreamDestroy(S->streams[k]);
@@ -356,6 +382,7 @@ ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t
         e = hipGetDeviceProperties(&prop, S->device);
         S->grid = prop.multiProcessorCount * frame_blocks_per_cu();
     }
+    if (e == hipSuccess) e = batch_grid_size(S->device, S->batch_grid);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->staged, hipEventDisableTiming);
     for (int k = 0; k < streams && e == hipSuccess; ++k) {
@@ -363,6 +390,7 @@ ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t
         if (e == hipSuccess) e = hipEventCreateWithFlags(&S->done[k], hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc((void**)&S->counters[k], kMaxBatch * 16 * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMemset(S->counters[k], 0, kMaxBatch * 16 * sizeof(uint32_t));
+        if (e == hipSuccess) e = init_slot(S->slot[k]);
     }
     // a round waits on `staged` even before anything was staged: record it once
     if (e == hipSuccess) e = hipEventRecord(S->staged, S->copy_stream);
