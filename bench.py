@@ -601,7 +601,8 @@ def main():
                                f"N_b 32, radius {kw['radius']}, thickness {kw['thickness']:.4g}, noise {w['noise']}, "
                                f"procedural scene seed {w['seed']} ({w['n_boxes']} boxes, {w['n_planes']} thin planes)",
                    "samples_per_frame": samples, "pixels": W * H, "parallelism": "single GPU",
-                   "device": torch.cuda.get_device_name(dev), "hip": torch.version.hip},
+                   "device": torch.cuda.get_device_name(dev) or torch.cuda.get_device_properties(dev).gcnArchName,
+                   "hip": torch.version.hip},
         "kernel_ms": {"mean": kernel_ms, "p50": float(np.percentile(per_launch_ms, 50)),
                       "p90": float(np.percentile(per_launch_ms, 90)),
                       "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
