@@ -282,9 +282,10 @@ ssvb_status ssvb_denoise(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
  * already in this device's memory are read and written in place.  As soon as one of the
  * server's compute streams is idle, every admitted frame not yet started (at most 64)
  * forms one round on it: its small frames (at most 8,192 tiles, 1920x1080 at the default
- * shape) in one launch of the batch kernel with their tiles packed into one list, its
- * larger frames as persistent single-frame launches back to back, then one completion
- * event.  Frames that arrive while a round is on the device join the next
+ * shape) in one launch of the batch kernel with their tiles packed into one list, then
+ * its larger frames as persistent single-frame launches back to back.  A request is done
+ * as soon as its own part of the round (the packed frames, or its single-frame launch)
+ * and its result copies have finished.  Frames that arrive while a round is on the device join the next
  * one, and rounds on different streams overlap.  Every mode of ssvb_compute is served
  * (128 sectors, half resolution; not slice masks).  Each frame's results are those
  * ssvb_compute writes for it with the launch shape of its class.

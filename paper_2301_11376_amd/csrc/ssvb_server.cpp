@@ -6,8 +6,9 @@
 // frames (at most kPackTiles tiles) in one launch of the batch kernel, their tiles packed
 // into one list, and enqueues its larger frames back to back as persistent single-frame
 // launches (the fastest kernel for each frame's mode, 128 sectors and half resolution
-// included).  Each request is stamped with its completion time once its results are in
-// the caller's buffers.
+// included).  Each part of a round (the packed frames, each larger frame) ends with an
+// event, so a request is retired, stamped with its completion time and its arena block
+// freed as soon as its own part and result copies are done, not at the end of its round.
 #include <string.h>
 
 #include <algorithm>
@@ -73,9 +74,19 @@ struct Request {
     Clock::time_point t_submit, t_done;
 };
 
+// A round on one stream, in parts that finish in stream order: its packed small frames,
+// then each larger frame.  Each part's requests are done (results in the caller's
+// buffers) when the part's event has fired.
+struct Part {
+    int ev = 0;  // index into the stream's part events
+    std::vector<uint64_t> tickets;
+};
+
 struct Round {
     bool busy = false;
     std::vector<uint64_t> tickets;
+    std::vector<Part> parts;
+    size_t next_part = 0;  // parts before this one have been retired
 };
 
 bool terminal(int state) { return state == DONE || state == FAILED; }
@@ -96,6 +107,7 @@ struct ssvb_server {
     hipStream_t copy_stream = nullptr;
     hipStream_t streams[kMaxStreams] = {};
     hipEvent_t done[kMaxStreams] = {};      // recorded after each round on its stream
+    hipEvent_t part_ev[kMaxStreams][kMaxBatch] = {};  // recorded after each part of a round
     uint32_t* counters[kMaxStreams] = {};   // queue counters: one set of 16 per frame of a round
     BatchSlot slot[kMaxStreams];            // the packed small frames of a round, per stream
     int batch_grid[2] = {0, 0};
@@ -153,54 +165,78 @@ hipError_t stage(ssvb_server* S, Request& r, uint64_t off) {
     return hipSuccess;
 }
 
-hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs) {
+// Copy a request's results from its arena block to the caller's buffers on stream s
+// (nothing to do when the kernel wrote the caller's buffers).
+hipError_t copy_results(const Request& r, hipStream_t s) {
+    if (r.out_in_place) return hipSuccess;
+    const ssvb_frame& F = r.caller;
+    const int W = F.camera.width, H = F.camera.height;
+    struct {
+        void* dst;
+        int64_t pitch;
+        const void* src;
+        size_t row;
+    } c[3] = {{F.out.ao, F.out.ao_pitch_bytes, r.staged.out.ao, (size_t)W * 4},
+              {F.out.gi, F.out.gi_pitch_bytes, r.staged.out.gi, (size_t)W * 12},
+              {F.out.ambient, F.out.ambient_pitch_bytes, r.staged.out.ambient, (size_t)W * 12}};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        e = hipMemcpy2DAsync(c[i].dst, c[i].pitch ? (size_t)c[i].pitch : c[i].row, c[i].src, c[i].row, c[i].row,
+                             (size_t)H, hipMemcpyDefault, s);
+    return e;
+}
+
+// Enqueue a round on stream k: the packed small frames and their result copies, then
+// each larger frame and its copies, each part followed by its event.  `parts` receives
+// the parts in stream order (tickets[i] is the ticket of rs[i]).
+hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs, const std::vector<uint64_t>& tickets,
+                        std::vector<Part>& parts) {
     hipStream_t s = S->streams[k];
     hipError_t e = hipStreamWaitEvent(s, S->staged, 0);
     // the stream's previous round has retired: every counter set is back at zero and the
     // slot's descriptor upload is done
     ssvb_frame small[kMaxBatch];
     int n_small = 0, kinds = 0;
+    std::vector<size_t> small_i, large_i;
     std::vector<FrameArgs> large;
     large.reserve(rs.size());
-    for (const Request* r : rs) {
-        const ssvb_frame& F = r->staged;
-        if ((int64_t)F.camera.width * F.camera.height == 0) continue;
+    for (size_t i = 0; i < rs.size(); ++i) {
+        const ssvb_frame& F = rs[i]->staged;
         FrameArgs A;
         fill_frame(A, &S->tab, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
         if ((uint32_t)A.tiles_x * (uint32_t)A.tiles_y <= kPackTiles) {
             small[n_small++] = F;
+            small_i.push_back(i);
             kinds |= (F.params.sectors == 128 ? kBatch128 : kBatch32) | (F.params.resolution == 2 ? kBatchHalf : 0);
         } else {
             large.push_back(A);
+            large_i.push_back(i);
         }
     }
+    auto finish_part = [&](const std::vector<size_t>& members) {
+        for (size_t i : members) {
+            if (e != hipSuccess) break;
+            e = copy_results(*rs[i], s);
+        }
+        if (e != hipSuccess) return;
+        Part P;
+        P.ev = (int)parts.size();
+        for (size_t i : members) P.tickets.push_back(tickets[i]);
+        e = hipEventRecord(S->part_ev[k][P.ev], s);
+        if (e == hipSuccess) parts.push_back(std::move(P));
+    };
     if (e == hipSuccess && n_small > 0) {
         // enqueued directly (a graph capture on this thread could collide with a device-wide
         // synchronisation by the caller's threads)
         BatchSlot& B = S->slot[k];
         build_batch(&S->tab, B.h_desc, small, n_small);
         e = enqueue_batch(B.d_desc, B.h_desc, B.d_queues, S->batch_grid, kinds, s);
+        finish_part(small_i);
     }
     for (size_t j = 0; j < large.size() && e == hipSuccess; ++j) {
         e = launch_plain(large[j], S->counters[k] + 16 * j, S->grid, s);
         if (e == hipSuccess && large[j].sub == 2) e = launch_upsample(large[j], s);
-    }
-    for (const Request* r : rs) {
-        if (e != hipSuccess) break;
-        if (r->out_in_place) continue;  // the kernel wrote the caller's buffers
-        const ssvb_frame& F = r->caller;
-        const int W = F.camera.width, H = F.camera.height;
-        struct {
-            void* dst;
-            int64_t pitch;
-            const void* src;
-            size_t row;
-        } c[3] = {{F.out.ao, F.out.ao_pitch_bytes, r->staged.out.ao, (size_t)W * 4},
-                  {F.out.gi, F.out.gi_pitch_bytes, r->staged.out.gi, (size_t)W * 12},
-                  {F.out.ambient, F.out.ambient_pitch_bytes, r->staged.out.ambient, (size_t)W * 12}};
-        for (int i = 0; i < 3 && e == hipSuccess; ++i)
-            e = hipMemcpy2DAsync(c[i].dst, c[i].pitch ? (size_t)c[i].pitch : c[i].row, c[i].src, c[i].row, c[i].row,
-                                 (size_t)H, hipMemcpyDefault, s);
+        if (e == hipSuccess) finish_part({large_i[j]});
     }
     if (e == hipSuccess) e = hipEventRecord(S->done[k], s);
     return e;
@@ -222,42 +258,59 @@ void run(ssvb_server* S) {
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         bool progress = false;
-        // 1. retire rounds whose completion event has fired
-        int busy[kMaxStreams], nbusy = 0;
-        for (int k = 0; k < S->nstreams; ++k)
-            if (S->rounds[k].busy) busy[nbusy++] = k;
-        hipError_t q[kMaxStreams];
-        if (nbusy) {
-            lk.unlock();
-            for (int i = 0; i < nbusy; ++i) q[i] = hipEventQuery(S->done[busy[i]]);
-            lk.lock();
-        }
-        const Clock::time_point now = Clock::now();
+        // 1. retire the parts of each round whose events have fired, in stream order; a
+        //    round is over (its stream idle) once its last event has fired.  Only this
+        //    thread touches the rounds, so their events are queried with the lock released.
         int running = 0;
-        for (int i = 0; i < nbusy; ++i) {
-            Round& R = S->rounds[busy[i]];
-            if (q[i] == hipErrorNotReady) {
-                ++running;
-                continue;
+        for (int k = 0; k < S->nstreams; ++k) {
+            Round& R = S->rounds[k];
+            if (!R.busy) continue;
+            hipError_t qs[kMaxBatch];
+            int nq = 0;
+            hipError_t qd = hipErrorNotReady;
+            lk.unlock();
+            size_t p = R.next_part;
+            for (; p < R.parts.size(); ++p) {
+                qs[nq] = hipEventQuery(S->part_ev[k][R.parts[p].ev]);
+                if (qs[nq++] != hipSuccess) break;
             }
-            for (uint64_t t : R.tickets) {
-                Request& r = S->reqs[t];
-                if (q[i] != hipSuccess) {
-                    fail_request(S, t, r, now);
-                    continue;
+            if (p == R.parts.size()) qd = hipEventQuery(S->done[k]);
+            lk.lock();
+            const Clock::time_point now = Clock::now();
+            hipError_t err = hipSuccess;
+            for (int i = 0; i < nq && qs[i] != hipErrorNotReady; ++i) {
+                if (qs[i] != hipSuccess) {
+                    err = qs[i];
+                    break;
                 }
-                r.state = DONE;
-                r.t_done = now;
-                S->adm.finish(t);
-                S->st.completed++;
+                for (uint64_t t : R.parts[R.next_part].tickets) {
+                    Request& r = S->reqs[t];
+                    r.state = DONE;
+                    r.t_done = now;
+                    S->adm.finish(t);
+                    S->st.completed++;
+                }
+                ++R.next_part;
+                progress = true;
             }
-            if (q[i] != hipSuccess && S->fatal == hipSuccess) {
-                S->fatal = q[i];
-                S->fatal_what = "round";
+            if (err == hipSuccess && qd != hipSuccess && qd != hipErrorNotReady) err = qd;
+            if (err != hipSuccess) {
+                for (; R.next_part < R.parts.size(); ++R.next_part)
+                    for (uint64_t t : R.parts[R.next_part].tickets) fail_request(S, t, S->reqs[t], now);
+                if (S->fatal == hipSuccess) {
+                    S->fatal = err;
+                    S->fatal_what = "round";
+                }
             }
-            R.tickets.clear();
-            R.busy = false;
-            progress = true;
+            if (err != hipSuccess || (R.next_part == R.parts.size() && qd == hipSuccess)) {
+                R.busy = false;
+                R.tickets.clear();
+                R.parts.clear();
+                R.next_part = 0;
+                progress = true;
+            } else {
+                ++running;
+            }
         }
         if (progress) S->cv_done.notify_all();
         if (S->stop) {
@@ -306,11 +359,17 @@ void run(ssvb_server* S) {
         for (size_t i = 0; i < admitted.size() && e == hipSuccess; ++i) e = stage(S, *adm_req[i], admitted[i].second);
         if (!admitted.empty() && e == hipSuccess) e = hipEventRecord(S->staged, S->copy_stream);
         const char* what = "staging";
+        std::vector<std::vector<Part>> parts(starts.size());
         for (size_t i = 0; i < starts.size() && e == hipSuccess; ++i) {
-            e = launch_round(S, starts[i].first, round_req[i]);
+            e = launch_round(S, starts[i].first, round_req[i], starts[i].second, parts[i]);
             what = "round launch";
         }
         lk.lock();
+        for (size_t i = 0; i < starts.size() && e == hipSuccess; ++i) {
+            Round& R = S->rounds[starts[i].first];
+            R.parts = std::move(parts[i]);
+            R.next_part = 0;
+        }
         if (e != hipSuccess) {
             // a device error leaves the server unusable: fail everything not yet retired
             if (S->fatal == hipSuccess) {
@@ -320,8 +379,11 @@ void run(ssvb_server* S) {
             const Clock::time_point t_fail = Clock::now();
             for (auto& s : starts) {
                 for (uint64_t t : s.second) fail_request(S, t, S->reqs[t], t_fail);
-                S->rounds[s.first].busy = false;
-                S->rounds[s.first].tickets.clear();
+                Round& R = S->rounds[s.first];
+                R.busy = false;
+                R.tickets.clear();
+                R.parts.clear();
+                R.next_part = 0;
             }
             for (uint64_t t : S->adm.cancel_ready()) fail_request(S, t, S->reqs[t], t_fail);
             for (uint64_t t : S->adm.cancel_queued()) {
@@ -343,6 +405,8 @@ ssvb_status fatal_status(const ssvb_server* S) {
 
 void destroy_resources(ssvb_server* S) {
     for (int k = 0; k < kMaxStreams; ++k) {
+        for (int i = 0; i < kMaxBatch; ++i)
+            if (S->part_ev[k][i]) (void)hipEventDestroy(S->part_ev[k][i]);
         free_slot(S->slot[k]);
         if (S->done[k]) (void)hipEventDestroy(S->done[k]);
         if (S->counters[k]) (void)hipFree(S->counters[k]);
@@ -391,6 +455,8 @@ ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t
         if (e == hipSuccess) e = hipMalloc((void**)&S->counters[k], kMaxBatch * 16 * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMemset(S->counters[k], 0, kMaxBatch * 16 * sizeof(uint32_t));
         if (e == hipSuccess) e = init_slot(S->slot[k]);
+        for (int i = 0; i < kMaxBatch && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&S->part_ev[k][i], hipEventDisableTiming);
     }
     // a round waits on `staged` even before anything was staged: record it once
     if (e == hipSuccess) e = hipEventRecord(S->staged, S->copy_stream);
