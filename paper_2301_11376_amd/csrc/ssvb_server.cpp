@@ -213,6 +213,24 @@ hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs, 
             large_i.push_back(i);
         }
     }
+    // larger frames shortest first (tiles x slices x steps): every request but the longest
+    // finishes earlier than in arrival order, and the round ends at the same time
+    {
+        std::vector<size_t> by_cost(large.size());
+        for (size_t j = 0; j < by_cost.size(); ++j) by_cost[j] = j;
+        auto cost = [&](size_t j) {
+            return (double)large[j].tiles_x * large[j].tiles_y * large[j].nd * large[j].ns;
+        };
+        std::stable_sort(by_cost.begin(), by_cost.end(), [&](size_t a, size_t b) { return cost(a) < cost(b); });
+        std::vector<FrameArgs> l2;
+        std::vector<size_t> i2;
+        for (size_t j : by_cost) {
+            l2.push_back(large[j]);
+            i2.push_back(large_i[j]);
+        }
+        large.swap(l2);
+        large_i.swap(i2);
+    }
     auto finish_part = [&](const std::vector<size_t>& members) {
         for (size_t i : members) {
             if (e != hipSuccess) break;
