@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 SERVE_BUDGET = 64 << 30  # HBM budget of the request loop
+SERVE_STREAMS = 1  # compute streams of the request loop (concurrent rounds measured slower)
 HOST_WORKERS = 16  # CPU share of one GPU on the benchmark hosts
 
 
@@ -417,7 +418,7 @@ def serve_leg(ctx, pool, n_requests, rates):
         free_out[key].append(o)
     plain_fps = n_sat / (t_plain * 1e-3)
 
-    srv = Server(ctx, SERVE_BUDGET, streams=2)
+    srv = Server(ctx, SERVE_BUDGET, streams=SERVE_STREAMS)
     try:
         def run(schedule, count):
             """Submit requests 0..count-1 at host times `schedule` (s, relative); returns
@@ -483,7 +484,7 @@ def serve_leg(ctx, pool, n_requests, rates):
     return {"workload": f"Poisson stream of {len(reqs)} requests (first 200 discarded), resolution uniform over "
                         "960x540 / 1280x720 / 1920x1080 / 2560x1440 / 3840x2160, slices 2..8, steps {8,16,32}, "
                         "FP16 or FP32 normals+radiance (p = 1/2), radius 3, t 0.5, R2 noise, 2 procedural scenes "
-                        "per resolution, draw seed 5; G-buffers device-resident, 64 GB HBM budget, 2 streams",
+                        f"per resolution, draw seed 5; G-buffers device-resident, 64 GB HBM budget, {SERVE_STREAMS} stream(s)",
             "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "frames_per_s": head["frames_per_s"],
             "rate_hz": head["rate_hz"], "saturated_frames_per_s": sat_fps,
             "plain_frames_per_s": plain_fps, "served_vs_plain": sat_fps / plain_fps, "rates": results}

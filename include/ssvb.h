@@ -314,7 +314,11 @@ typedef struct {
 } ssvb_server_counters;
 
 /* Create a server on ctx's device with an arena of hbm_budget_bytes (allocated here;
- * SSVB_ERR_OUT_OF_MEMORY if it cannot be) and `streams` compute streams (1..8, 0 = 2). */
+ * SSVB_ERR_OUT_OF_MEMORY if it cannot be) and `streams` compute streams (1..8, 0 = 1).
+ * With one stream a round starts when the previous one has finished (the gap is the
+ * scheduler's turnaround, tens of microseconds); with more, rounds run concurrently, which
+ * on MI355X measured slower (every round's persistent kernels want all CUs): 0.96 of the
+ * one-stream throughput with two streams, 0.87 with three or four. */
 ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t streams, ssvb_server** out);
 
 /* Queue one frame (validated as by ssvb_compute; masks must be NULL) and return its

@@ -441,7 +441,7 @@ class Server:
     compute streams.  Tensors handed to submit (device, or pinned host) must stay alive
     until the request has finished; this wrapper keeps a reference to them meanwhile."""
 
-    def __init__(self, ctx: Context, hbm_budget_bytes: int, streams: int = 2):
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, streams: int = 1):
         h = ctypes.c_void_p()
         check(lib().ssvb_server_create(ctx.handle, int(hbm_budget_bytes), int(streams), ctypes.byref(h)),
               "ssvb_server_create")

@@ -443,7 +443,7 @@ ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t
     if (!out) return fail(SSVB_ERR_INVALID_ARG, "NULL output handle");
     *out = nullptr;
     if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
-    if (streams == 0) streams = 2;
+    if (streams == 0) streams = 1;
     if (streams < 1 || streams > kMaxStreams)
         return fail(SSVB_ERR_INVALID_ARG, "streams %d outside [1, %d]", streams, kMaxStreams);
     if (hbm_budget_bytes < kAlign) return fail(SSVB_ERR_INVALID_ARG, "HBM budget of %llu bytes is too small",
