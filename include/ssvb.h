@@ -193,17 +193,19 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
                          const ssvb_params* params, const ssvb_outputs* out, void* hip_stream);
 
 /* Many frames of mixed size, slice/step counts, criteria, mask widths, resolutions and
- * element types in one replay of a captured HIP graph (descriptor upload, queue reset, a
- * persistent kernel per mask width present, then the half-resolution fill if any frame
- * asks for it), asynchronous on `hip_stream`.  Small frames (at most 8,192 tiles) are
- * packed into one list of tiles cut into equal-cost runs, one per XCD; larger frames
- * follow in the given order, each with its own per-XCD runs.  Each frame's outputs equal,
- * bit for bit, what ssvb_compute writes for it with the same launch shape.  The first
- * batch with a new set of frame kinds (mask widths, half resolution) captures that set's
- * graph on the calling thread: meanwhile no other thread may synchronise the whole
- * device.  Frames are processed in chunks of 64.  The library keeps two descriptor
- * slots, so a call may block until the batch submitted two chunks earlier has finished.
- * Returns SSVB_ERR_INVALID_ARG naming the first invalid frame. */
+ * element types, asynchronous on `hip_stream`.  Frames of at most 8,192 tiles (1920x1080
+ * at the default launch shape) go into one replay of a captured HIP graph (descriptor
+ * upload, queue reset, a persistent kernel per mask width present, then the
+ * half-resolution fill if any frame asks for it) with their tiles packed into one list
+ * cut into equal-cost runs, one per XCD; larger frames each get the persistent
+ * single-frame launch of ssvb_compute (each fills the GPU by itself).  Each frame's
+ * outputs equal, bit for bit, what ssvb_compute writes for it with the same launch
+ * shape.  The first batch with a new set of frame kinds (mask widths, half resolution)
+ * captures that set's graph on the calling thread: meanwhile no other thread may
+ * synchronise the whole device.  Frames are processed in chunks of 64.  The library keeps
+ * two descriptor slots and the 32 counter sets of ssvb_compute, so a call may block until
+ * the batch submitted two chunks earlier, or the launch 32 large frames earlier, has
+ * finished.  Returns SSVB_ERR_INVALID_ARG naming the first invalid frame. */
 ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t n, void* hip_stream);
 
 /* Force one launch shape for every later frame of this context (NULL: back to the

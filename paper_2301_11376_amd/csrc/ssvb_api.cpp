@@ -580,6 +580,28 @@ ssvb_status ssvb_validate(const ssvb_image* depth, const ssvb_image* normal, con
     return SSVB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One frame as a persistent single-frame launch (and the half-resolution fill) on
+// `stream`.  A counter set of the ring is reused only once its previous launch has
+// completed (blocks the host only with kRing launches of this context still in flight).
+hipError_t launch_single(ssvb_ctx* ctx, const FrameArgs& A, hipStream_t stream) {
+    const int r = (int)(ctx->next_ring++ % kRing);
+    hipError_t e = hipSuccess;
+    if (ctx->ring_pending[r]) e = hipEventSynchronize(ctx->ring_ev[r]);
+    if (e == hipSuccess) e = launch_plain(A, ctx->d_ring + r * kRingStride, ctx->frame_grid, stream);
+    if (e == hipSuccess && A.sub == 2) e = launch_upsample(A, stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ring_ev[r], stream);
+    if (e == hipSuccess) ctx->ring_pending[r] = true;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_image* normal, const ssvb_image* radiance,
                          const ssvb_camera* camera, const ssvb_params* params, const ssvb_outputs* out,
                          void* hip_stream) {
@@ -592,15 +614,7 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     int prev = 0;
     (void)hipGetDevice(&prev);
     if (prev != ctx->device) (void)hipSetDevice(ctx->device);
-    // a counter set is reused only once its previous launch has completed (blocks the
-    // host only with kRing launches of this context still in flight)
-    const int r = (int)(ctx->next_ring++ % kRing);
-    hipError_t e = hipSuccess;
-    if (ctx->ring_pending[r]) e = hipEventSynchronize(ctx->ring_ev[r]);
-    if (e == hipSuccess) e = launch_plain(A, ctx->d_ring + r * kRingStride, ctx->frame_grid, (hipStream_t)hip_stream);
-    if (e == hipSuccess && A.sub == 2) e = launch_upsample(A, (hipStream_t)hip_stream);
-    if (e == hipSuccess) e = hipEventRecord(ctx->ring_ev[r], (hipStream_t)hip_stream);
-    if (e == hipSuccess) ctx->ring_pending[r] = true;
+    const hipError_t e = launch_single(ctx, A, (hipStream_t)hip_stream);
     if (prev != ctx->device) (void)hipSetDevice(prev);
     if (e != hipSuccess) return hip_fail(e, "gather launch");
     return SSVB_OK;
@@ -620,16 +634,29 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
     ssvb_status st = init_batch(ctx);
     hipStream_t stream = (hipStream_t)hip_stream;
     for (int f0 = 0; st == SSVB_OK && f0 < n; f0 += kMaxBatch) {
-        // frames with no pixels launch nothing
+        // frames with no pixels launch nothing; frames of more than kPackTiles tiles are
+        // single-frame launches (each fills the GPU by itself, and a launch of its own
+        // keeps its L2 locality); the others are packed into one replay of the batch graph
         std::vector<ssvb_frame> chunk;
+        std::vector<FrameArgs> large;
         int kinds = 0;
         for (int f = f0; f < std::min(n, f0 + kMaxBatch); ++f) {
             const ssvb_frame& F = frames[f];
             if ((int64_t)F.camera.width * F.camera.height == 0) continue;
+            FrameArgs A;
+            fill_frame(A, &ctx->tab, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
+            if ((uint32_t)A.tiles_x * (uint32_t)A.tiles_y > kPackTiles) {
+                large.push_back(A);
+                continue;
+            }
             chunk.push_back(F);
             kinds |= (F.params.sectors == 128 ? kBatch128 : kBatch32) | (F.params.resolution == 2 ? kBatchHalf : 0);
         }
-        if (chunk.empty()) continue;
+        for (size_t j = 0; j < large.size() && st == SSVB_OK; ++j) {
+            const hipError_t e = launch_single(ctx, large[j], stream);
+            if (e != hipSuccess) st = hip_fail(e, "gather launch");
+        }
+        if (chunk.empty() || st != SSVB_OK) continue;
         BatchSlot& S = ctx->slot[ctx->next_slot++ % kBatchSlots];
         hipGraphExec_t exec = nullptr;
         hipError_t e = slot_graph(S, kinds, ctx->batch_grid, ctx->cap_stream, &exec);
