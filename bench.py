@@ -94,7 +94,7 @@ def _oracle_band(rows):
         return time.perf_counter() - t0
 
 
-def cpu_baseline(gb, cam, kw, rows_per_worker=48):
+def cpu_baseline(gb, cam, kw, rows_per_worker=36):
     """The FP64 oracle on `workers` disjoint row bands of the frame, one forked process
     (one thread) per band, timed end to end."""
     global _CPU_JOB
