@@ -262,3 +262,27 @@ def test_batch_full_sizes(ctx):
         log(f"  frame {i} {cam.width}x{cam.height} {kw.get('sectors', 32)} sectors, resolution "
             f"{kw.get('resolution', 1)}: max |error| at {len(ys)} sampled pixels {err:.2e}")
         assert err <= 1e-3, i
+
+
+def test_batch_packed_edge_cases(ctx):
+    """Packed lists with one-tile frames, split points inside frames and a heavy frame
+    among light ones (costs from 1 x 1 to 16 x 64 samples per pixel), 128-sector and
+    half-resolution frames mixed in: every frame equals its single-frame launch."""
+    rng = np.random.default_rng(17)
+    specs = []
+    for i in range(60):
+        W, H = int(rng.integers(1, 40)), int(rng.integers(1, 24))
+        kw = dict(slices=int(rng.integers(1, 5)), steps=int(rng.integers(1, 9)), radius=float(rng.uniform(0.5, 3)),
+                  thickness=float(rng.uniform(0.1, 1.0)), noise=O.NOISE_HASH, seed=i)
+        if i % 7 == 3:
+            kw["sectors"] = 128
+        if i % 11 == 5 and W > 1 and H > 1:
+            kw["resolution"] = 2
+        specs.append((W, H, 20 + i % 3, bool(i % 2), 3, kw))
+    specs.insert(30, (150, 90, 9, False, 3, dict(slices=16, steps=64, radius=4.0, thickness=0.5,
+                                                  noise=O.NOISE_R2, seed=99)))
+    items = scene_frames(specs)
+    log(f"packed edge cases: {len(items)} frames")
+    got = run_batch(ctx, items)
+    for i, ((gb, cam, kw), g) in enumerate(zip(items, got)):
+        assert_same(g, run_plain(ctx, gb, cam, kw), (i, cam.width, cam.height))

@@ -362,3 +362,39 @@ def test_served_modes(ctx):
         assert srv.stats()["failed"] == 0
     finally:
         srv.close()
+
+
+def test_many_tiny_requests(ctx):
+    """150 tiny requests (1x1 to 39x23, 32 or 128 sectors, full or half resolution) in
+    few large rounds of packed frames: every result equals ssvb_compute's."""
+    import torch
+    from paper_2301_11376_amd import Server
+    rng = np.random.default_rng(23)
+    specs = []
+    for i in range(150):
+        W, H = int(rng.integers(1, 40)), int(rng.integers(1, 24))
+        kw = dict(slices=int(rng.integers(1, 5)), steps=int(rng.integers(1, 9)), radius=float(rng.uniform(0.5, 3)),
+                  thickness=float(rng.uniform(0.1, 1.0)), noise=O.NOISE_R2, seed=i)
+        if i % 5 == 2:
+            kw["sectors"] = 128
+        if i % 9 == 4 and W > 1 and H > 1:
+            kw["resolution"] = 2
+        specs.append((W, H, 30 + i % 2, bool(i % 3 == 0), 3, kw))
+    items = make_items(specs)
+    srv = Server(ctx, 256 << 20)
+    try:
+        reqs = []
+        for gb, cam, kw in items:
+            t, bc, bp, out = device_request(gb, cam, kw)
+            reqs.append((t, out, gb, cam, kw, bc, bp))
+        torch.cuda.synchronize()
+        tks = [srv.submit(t["depth"], t["normal"], t["radiance"], bc, bp, out) for t, out, gb, cam, kw, bc, bp in reqs]
+        for tk, (t, out, gb, cam, kw, bc, bp) in zip(tks, reqs):
+            srv.wait(tk, 60000)
+            same(host(out), plain(ctx, gb, cam, kw), (cam.width, cam.height))
+            srv.release(tk)
+        st = srv.stats()
+        log(f"tiny requests: {st['rounds']} rounds, largest {st['max_round_frames']} frames")
+        assert st["failed"] == 0 and st["completed"] >= len(items)
+    finally:
+        srv.close()
