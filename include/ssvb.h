@@ -48,7 +48,7 @@ typedef enum {
 typedef enum { SSVB_F32 = 0, SSVB_F16 = 1 } ssvb_dtype;
 
 /* Hit criterion (Section 3.1).  ROUND sets a sector iff its centre lies in the sample's
- * angular interval ("at least half covered").  PSEUDOCODE takes the floor of the start
+ * angular interval (a sector counts once half of it is covered).  PSEUDOCODE takes the floor of the start
  * and the ceiling of the width, as Algorithm 1 prints it. */
 typedef enum { SSVB_HIT_ROUND = 0, SSVB_HIT_PSEUDOCODE = 1 } ssvb_hit_criterion;
 
@@ -226,7 +226,7 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
                           float* best_ms);
 
 /* Multi-bounce indirect light (Section 4.3: the indirect light is injected into the light
- * buffer used by the next frame, with its intensity balanced): writes, per pixel and RGB
+ * buffer used by the next frame, its intensity scaled down): writes, per pixel and RGB
  * channel, next = direct + gain * albedo * gi.  direct and albedo: images of width x height
  * (F32 or F16, 3 or 4 channels); gi: FP32 [height][width][3] as ssvb_compute writes it,
  * row pitch gi_pitch_bytes (0 = dense); next: an image of the same channel count as

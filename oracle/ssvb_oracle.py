@@ -15,8 +15,8 @@ division, reproduced here with numpy float32.
 
 Readings of the paper where it is silent, garbled or self-contradictory (each one is
 listed again in the design notes):
-  R1  hit criterion: the prose (Section 3.1, Figure "SliceVS") asks for sectors "at least
-      half covered"; the pseudo-code uses floor/ceil.  Default ROUND sets sector k iff its
+  R1  hit criterion: the prose (Section 3.1 and its slice figure) sets a sector once half of
+      it or more is covered; the pseudo-code uses floor/ceil.  Default ROUND sets sector k iff its
       centre lies in the sample's angular interval; PSEUDOCODE (floor start, ceil width)
       is available as an option.
   R2  the "+pi/2" inside the pseudo-code's sector count is a typo: the count spans
@@ -27,8 +27,8 @@ listed again in the design notes):
   R4  the back sample lies *behind* the front one, t farther from the camera along the
       centre pixel's view ray (s_b = s_f - t v with v pointing to the camera); only this
       makes t -> infinity equal GTAO without falloff (Section 3.1).
-  R5  angles are true angles (atan2 of the slice coordinates), not cosines (Section 3.1:
-      convert from cosine space to angular space).
+  R5  angles are true angles (atan2 of the slice coordinates), not cosines (Section 3.1
+      converts the horizon cosines to angles).
   R6  sectors are uniform in angle (Eq. 4 and the AO update of Algorithm 1).
   R7  the AO output is visibility (1 = unoccluded), as Algorithm 1 accumulates it.
   R8  loop bounds are exclusive: N_d slices, N_s steps on *each* side (Section 4.1).
@@ -47,22 +47,22 @@ listed again in the design notes):
       ambient += (unoccluded sectors of the subregion) / N_b * L(direction) with L an L2
       real-SH probe in world space (Section 3.2; probes are named in Section 5).
   R18 GI is Algorithm 1's quantity divided by N_d, with no further normalisation.
-  R19 "view-space position at step j" is the depth read from the texel containing the
+  R19 the view-space position of step j (Algorithm 1) is the depth read from the texel containing the
       step's exact screen position, placed on that exact position's view ray (the depth
       buffer is point sampled; the sample stays in the slice plane).
-  R21 the optional "exponential" step distribution (Section 4.3: samples denser near the
+  R21 the optional exponential step distribution (Section 4.3: samples denser near the
       pixel; the curve is not given) is quadratic: step j sits at ((j + 1 + xi) /
       (N_s + 1))^2 of the reach q (N_s + 1), with the same jitter xi; in integers,
       o_j = (((q a_j^2) >> 16) * floor(2^32 / (N_s + 1))) >> 32, a_j = 256 (j + 1) + xi8.
   R22 half resolution (Section 4.3: the gather runs on a quarter of the pixels, then a
-      "classic bilateral upsampler" fills the image; neither is specified further): the
+      bilateral upsampler fills the image; neither is specified further): the
       gather runs on the pixels whose x and y are both even, reading the full-resolution
       G-buffer; every other pixel takes the average of its 1, 2 or 4 nearest computed
       pixels with weights bilinear x (1e-3 + exp(-((z - z_n) / (0.05 z))^2)), background
       neighbours excluded; a background pixel, or one with no computed foreground
       neighbour, outputs AO = 1, GI = 0, ambient = 0.
   R23 multi-bounce (Section 4.3: the indirect light is injected into the light buffer of
-      the next frame, its intensity "balanced"): next light = direct + g albedo * GI per
+      the next frame, its intensity scaled down): next light = direct + g albedo * GI per
       pixel and channel, with a gain g in [0, 1] as the balance.
   R24 denoising (Section 4.1 and Table 2 time a denoising pass after the gather, 0.33 ms
       at full and 0.1 ms at half resolution, but do not describe it): an edge-aware
@@ -133,8 +133,8 @@ class Params:
 
 
 # ----------------------------------------------------------------------------------------
-# counter-based noise (random numbers the method draws; Algorithm 1: "directions with
-# random offset"; Section 4.3: jitter along the sampling direction)
+# counter-based noise (random numbers the method draws; Algorithm 1: slice directions
+# turned by a random offset; Section 4.3: jitter along the sampling direction)
 # ----------------------------------------------------------------------------------------
 
 def pcg_hash(v):
@@ -441,7 +441,7 @@ def compute(depth, normal, radiance, cam: Camera, prm: Params, pixels=None,
     q = step_q4(np.where(valid, z_p, 1.0), cam, prm)
     t_p = t0 + tk * np.where(valid, z_p, 0.0) if tk != 0.0 else np.full(n, t0)
 
-    # Algorithm 1: directions with random offset; per-slice jitter (Section 4.3)
+    # Algorithm 1: slice directions turned by a random offset; per-slice jitter (Section 4.3)
     rho16, xi8 = slice_noise(xs, ys, nd, prm.noise, prm.seed)
     lut_dx, lut_dy = direction_lut()
 
