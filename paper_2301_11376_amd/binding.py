@@ -381,8 +381,9 @@ class Context:
             tmp = like(src)
         P = ssvb_denoise_params(int(passes), int(normal_power), float(plane_sigma), int(resolution))
         d, n, c = image_of(depth), image_of(normal), camera.to_c()
-        i, o = self.outputs_of(src), self.outputs_of(out)
-        t = self.outputs_of(tmp) if tmp is not None else None
+        three = ("ao", "gi", "ambient")  # slice masks (if `src` holds them) are not filtered
+        i, o = self.outputs_of({k: src[k] for k in three}), self.outputs_of({k: out[k] for k in three})
+        t = self.outputs_of({k: tmp[k] for k in three}) if tmp is not None else None
         check(lib().ssvb_denoise(self.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(c), ctypes.byref(i),
                                  ctypes.byref(t) if t is not None else None, ctypes.byref(o), ctypes.byref(P),
                                  _stream_ptr(stream)), "ssvb_denoise")

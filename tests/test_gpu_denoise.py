@@ -189,3 +189,20 @@ def test_denoise_rejects(ctx):
         ctx.denoise(t["depth"], t["normal"], bc, src, out=other, tmp=other)
     ctx.denoise(t["depth"], t["normal"], bc, src, passes=1, out=other)   # one pass needs no tmp
     torch.cuda.synchronize()
+
+
+def test_denoise_takes_compute_output_with_masks(ctx):
+    """The dict ssvb_compute's binding returns (slice masks included) can be denoised as
+    it is; the masks play no part."""
+    import torch
+    gb, cam = scene(40, 30, 15)
+    bc, _ = PY.cams(cam)
+    bp, _ = PY.params(slices=2, steps=6, radius=1.5, thickness=0.4, noise=O.NOISE_HASH, seed=4)
+    t = PY.to_device(gb)
+    with_masks = ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp, masks=True)
+    plain_out = {k: v.clone() for k, v in with_masks.items() if k != "masks"}
+    a = ctx.denoise(t["depth"], t["normal"], bc, with_masks)
+    b = ctx.denoise(t["depth"], t["normal"], bc, plain_out)
+    torch.cuda.synchronize()
+    for k in ("ao", "gi", "ambient"):
+        assert torch.equal(a[k], b[k]), k
