@@ -309,21 +309,17 @@ void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames,
     for (int f = 0; f < n; ++f) {
         const ssvb_frame& F = frames[f];
         fill_frame(D->frames[f], tab, &F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
-        D->order[f] = f;
     }
-    // packed lists of the small frames per mask width: tile-count prefix sums, and runs of
+    // per mask width: the frames in the given order, tile-count prefix sums, and runs of
     // equal sample cost (a tile costs tile pixels x slices x steps)
     for (int w = 0; w < 2; ++w) {
         int m = 0;
         uint32_t tiles = 0;
         double total = 0.0;
         D->prefix[w][0] = 0;
-        for (int oi = 0; oi < n; ++oi) {
-            const int f = D->order[oi];
+        for (int f = 0; f < n; ++f) {
             const FrameArgs& A = D->frames[f];
             if ((A.nb == 128) != (w == 1)) continue;
-            D->packed[f] = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y <= kPackTiles;
-            if (!D->packed[f]) continue;
             D->plist[w][m] = f;
             tiles += (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
             D->prefix[w][++m] = tiles;

@@ -52,8 +52,8 @@ void free_slot(BatchSlot& s);
 // `tab` (forced, tuned for the frame's class, else the default).
 void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, const ssvb_image* normal,
                 const ssvb_image* radiance, const ssvb_camera* cam, const ssvb_params* p, const ssvb_outputs* out);
-// Descriptor table of up to kMaxBatch non-empty frames: constants and the order in which
-// the persistent kernel works through them.
+// Descriptor table of up to kMaxBatch non-empty frames (callers keep it to frames of at
+// most kPackTiles tiles): constants, the per-width tile lists and their equal-cost runs.
 void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames, int n);
 
 // One frame with the persistent kernel: `queues` is a set of 9 counters that must be

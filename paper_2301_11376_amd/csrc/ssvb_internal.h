@@ -94,24 +94,20 @@ __device__ __forceinline__ void walk_tile(const FrameArgs& A, uint32_t ord, int&
 // batched persistent path
 // ---------------------------------------------------------------------------------------
 constexpr int kMaxBatch = 64;  // frames per descriptor table (larger batches are chunked)
-// queue heads: one per frame and XCD, then one per mask width and XCD for the packed list
-constexpr int kBatchQueues = kMaxBatch * kXcds + 2 * kXcds;
-// frames of at most this many tiles are packed (a 1920x1080 frame in 32x8 tiles has 8,100)
+// queue heads: one per mask width and XCD
+constexpr int kBatchQueues = 2 * kXcds;
+// frames of at most this many tiles go into batches; larger ones get single-frame launches
+// (a 1920x1080 frame in 32x8 tiles has 8,100)
 constexpr uint32_t kPackTiles = 8192;
 // kinds of frame in a batch; each set of kinds has its own captured graph
 constexpr int kBatch32 = 1, kBatch128 = 2, kBatchHalf = 4, kBatchKinds = 8;
 
-// Frames of one persistent launch and the order they are worked through.
-// Small frames (at most kPackTiles tiles) are packed: for each mask width w (0: 32
-// sectors, 1: 128) their tile walks are laid end to end (frame plist[w][j] holds tiles
+// Frames of one persistent launch.  For each mask width w (0: 32 sectors, 1: 128) the tile
+// walks of that width's frames are laid end to end (frame plist[w][j] holds tiles
 // prefix[w][j] .. prefix[w][j + 1] - 1) and the list is cut into kXcds runs of equal
-// sample cost, run k (tiles split[w][k] .. split[w][k + 1] - 1) in queue
-// kMaxBatch * kXcds + w * kXcds + k.  Each larger frame f has its own queues: queue
-// f * kXcds + k holds run k of its tile walk (the walk cut into kXcds equal runs).
+// sample cost, run k (tiles split[w][k] .. split[w][k + 1] - 1) in queue w * kXcds + k.
 struct BatchDesc {
     int32_t n_frames;
-    int32_t packed[kMaxBatch];  // 1 if the frame is in a packed list
-    int32_t order[kMaxBatch];
     int32_t pn[2];
     int32_t plist[2][kMaxBatch];
     uint32_t prefix[2][kMaxBatch + 1];

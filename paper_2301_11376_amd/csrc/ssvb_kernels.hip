@@ -709,16 +709,11 @@ __global__ __launch_bounds__(kBlock) void debug_endpoints(FrameArgs A, float* ou
 // Persistent kernel over a batch of frames; workgroup b runs on XCD b mod 8.  Criterion,
 // element types and thickness are taken per frame at run time.  One instance per mask
 // width: an instance skips the frames of the other width, so the 32-sector instance keeps
-// its register budget.
-//  - Small frames first: their tile walks form one list cut into 8 runs of equal sample
-//    cost, one per XCD; a workgroup drains its own run, then steals from the others.
-//    Every claim returns a tile until the list is exhausted, so frames of a few hundred
-//    tiles cost no more than their work (with per-frame queues every workgroup would pass
-//    over every queue of every frame).
-//  - Then the larger frames, in the descriptor's order: each frame's strip walk is cut
-//    into 8 contiguous runs, one per XCD (compact regions per L2); a workgroup drains its
-//    own run, then what is left of the others, and moves on to the next frame without
-//    waiting for the rest (back-to-back single-frame launches with their tails overlapped).
+// its register budget.  The frames' tile walks form one list cut into 8 runs of equal
+// sample cost, one per XCD; a workgroup drains its own run, then steals from the others.
+// Every claim returns a tile until the list is exhausted, so frames of a few hundred tiles
+// cost no more than their work (with queues per frame every workgroup would pass over
+// every queue of every frame).
 template <int NB>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void gather_batch(
     const BatchDesc* __restrict__ D, uint32_t* __restrict__ queues) {
@@ -726,51 +721,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     __shared__ uint32_t s_item;
     const int home = hw_xcd();
     const int w = NB == 128 ? 1 : 0;
-    if (D->pn[w] > 0) {
-        // the small frames: one list of tiles, one run per XCD
-        int j = 0;  // frame of the last tile taken: runs are walked in increasing order
-        for (int qi = 0; qi < kXcds; ++qi) {
-            const int k = (home + qi) & (kXcds - 1);
-            const uint32_t first = D->split[w][k];
-            const uint32_t count = D->split[w][k + 1] - first;
-            for (;;) {
-                const uint32_t item = grab(&queues[kMaxBatch * kXcds + w * kXcds + k], &s_item);
-                if (item >= count) break;
-                const uint32_t g = first + item;
-                if (g < D->prefix[w][j]) j = 0;
-                while (D->prefix[w][j + 1] <= g) ++j;
-                const FrameArgs& A = D->frames[D->plist[w][j]];
-                const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
-                int tx, ty;
-                walk_tile(A, g - D->prefix[w][j], tx, ty);
-                const int x = (tx * A.tile_w + px % A.tile_w) * A.sub;
-                const int y = (ty * A.tile_h + px / A.tile_w) * A.sub;
-                if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1, NB>(A, L, x, y, li, lp, nullptr, nullptr);
-            }
-        }
-    }
-    // the larger frames, each with its own queues
-    const int n = D->n_frames;
-    for (int oi = 0; oi < n; ++oi) {
-        const int f = D->order[oi];
-        const FrameArgs& A = D->frames[f];
-        if (A.nb != NB || D->packed[f]) continue;
-        const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
-        const uint32_t per = (nt + kXcds - 1) / kXcds;
-        const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
-        for (int qi = 0; qi < kXcds; ++qi) {
-            const int k = (home + qi) & (kXcds - 1);
-            const uint32_t first = (uint32_t)k * per;
-            const uint32_t count = first < nt ? min(per, nt - first) : 0u;
-            for (;;) {
-                const uint32_t item = grab(&queues[f * kXcds + k], &s_item);
-                if (item >= count) break;
-                int tx, ty;
-                walk_tile(A, first + item, tx, ty);
-                const int x = (tx * A.tile_w + px % A.tile_w) * A.sub;
-                const int y = (ty * A.tile_h + px / A.tile_w) * A.sub;
-                if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1, NB>(A, L, x, y, li, lp, nullptr, nullptr);
-            }
+    if (D->pn[w] == 0) return;
+    int j = 0;  // frame of the last tile taken: runs are walked in increasing order
+    for (int qi = 0; qi < kXcds; ++qi) {
+        const int k = (home + qi) & (kXcds - 1);
+        const uint32_t first = D->split[w][k];
+        const uint32_t count = D->split[w][k + 1] - first;
+        for (;;) {
+            const uint32_t item = grab(&queues[w * kXcds + k], &s_item);
+            if (item >= count) break;
+            const uint32_t g = first + item;
+            if (g < D->prefix[w][j]) j = 0;
+            while (D->prefix[w][j + 1] <= g) ++j;
+            const FrameArgs& A = D->frames[D->plist[w][j]];
+            const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
+            int tx, ty;
+            walk_tile(A, g - D->prefix[w][j], tx, ty);
+            const int x = (tx * A.tile_w + px % A.tile_w) * A.sub;
+            const int y = (ty * A.tile_h + px / A.tile_w) * A.sub;
+            if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1, NB>(A, L, x, y, li, lp, nullptr, nullptr);
         }
     }
 }
