@@ -496,6 +496,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2_1080p")
+    ap.add_argument("--noise", choices=["hash", "r2", "fixed"], default=None,
+                    help="replace the workload's noise (fixed: every pixel the same slice directions and "
+                         "offsets, which shows what the per-pixel decorrelation costs in cache misses)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -525,6 +528,9 @@ def main():
     # ---- host work first (forked workers), before anything touches the GPU ----
     from gbuffer_scene import workload, mixed_batch, request_stream, render_pool
     gb, cam, w, scene = workload(args.workload)
+    own_noise = w["noise"]
+    if args.noise:
+        w["noise"] = args.noise
     kw = dict(slices=w["slices"], steps=w["steps"], radius=w["radius"], thickness=w["thickness"],
               seed=w["seed"], ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
     keys = []
@@ -608,7 +614,7 @@ def main():
                       "p90": float(np.percentile(per_launch_ms, 90)),
                       "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, shape),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, shape) if w["noise"] == own_noise else None,
                      "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": abytes,
                      "launch_shape": list(shape),
                      "stream_copy_gbs": copy_gbs, "frac_of_stream_copy": achieved / copy_gbs,
