@@ -1,14 +1,15 @@
 // Request loop of the visibility-bitmask gather: frames are admitted by their HBM
 // footprint into a device arena owned by the server (FIFO); buffers in host memory are
 // staged through the arena on a copy stream, buffers already in device memory are used
-// in place; admitted frames are run in rounds of up to 64 on two or more compute streams,
-// so that a round can start while another is still on the device.  A round runs its small
-// frames (at most kPackTiles tiles) in one launch of the batch kernel, their tiles packed
-// into one list, and enqueues its larger frames back to back as persistent single-frame
-// launches (the fastest kernel for each frame's mode, 128 sectors and half resolution
-// included).  Each part of a round (the packed frames, each larger frame) ends with an
-// event, so a request is retired, stamped with its completion time and its arena block
-// freed as soon as its own part and result copies are done, not at the end of its round.
+// in place; admitted frames are run in rounds of up to 64 on one or more compute streams
+// (one by default; with more, a round can start while another is still on the device).
+// A round runs its small frames (at most kPackTiles tiles) in one launch of the batch
+// kernel, their tiles packed into one list, and enqueues its larger frames back to back as
+// persistent single-frame launches (the fastest kernel for each frame's mode, 128 sectors
+// and half resolution included).  Each part of a round (the packed frames, each larger
+// frame) ends with an event, so a request is retired, stamped with its completion time and
+// its arena block freed as soon as its own part and result copies are done, not at the end
+// of its round.
 #include <string.h>
 
 #include <algorithm>
@@ -293,6 +294,11 @@ void run(ssvb_server* S) {
                 if (qs[nq++] != hipSuccess) break;
             }
             if (p == R.parts.size()) qd = hipEventQuery(S->done[k]);
+            bool bad = qd != hipSuccess && qd != hipErrorNotReady;
+            for (int i = 0; i < nq; ++i) bad = bad || (qs[i] != hipSuccess && qs[i] != hipErrorNotReady);
+            // before the round's requests are failed (and their buffers possibly freed by
+            // the caller), let whatever of it is still in flight drain
+            if (bad) (void)hipStreamSynchronize(S->streams[k]);
             lk.lock();
             const Clock::time_point now = Clock::now();
             hipError_t err = hipSuccess;
@@ -381,6 +387,13 @@ void run(ssvb_server* S) {
         for (size_t i = 0; i < starts.size() && e == hipSuccess; ++i) {
             e = launch_round(S, starts[i].first, round_req[i], starts[i].second, parts[i]);
             what = "round launch";
+        }
+        if (e != hipSuccess) {
+            // the requests below are about to be failed: first let the copies and rounds
+            // already enqueued for them finish, so nothing on the device still reads or
+            // writes their buffers once the caller sees them failed
+            (void)hipStreamSynchronize(S->copy_stream);
+            for (auto& s : starts) (void)hipStreamSynchronize(S->streams[s.first]);
         }
         lk.lock();
         for (size_t i = 0; i < starts.size() && e == hipSuccess; ++i) {
