@@ -248,6 +248,48 @@ def image_of(t, channels_expected=None) -> ssvb_image:
     return ssvb_image(t.data_ptr(), t.stride(0) * es, dt, ch)
 
 
+def check_tensor(t, name, H, W, channels=None, kind="image", device=None, allow_host=False):
+    """Check that tensor ``t`` can hold what the library reads or writes through its
+    pointer for an H x W frame: the C ABI takes bare pointers and pitches, so a tensor
+    smaller than the camera says (or with overlapping rows) would be read or written out
+    of bounds on the device.  ``channels``: None for [H, W], else the allowed C of
+    [H, W, C].  ``kind``: "image" (FP32 or FP16), "f32" or "i32"."""
+    import torch
+    if t is None:
+        raise ValueError(f"{name}: missing")
+    if channels is None:
+        if t.dim() != 2:
+            raise ValueError(f"{name}: expected [H, W], got shape {tuple(t.shape)}")
+        C = 1
+    else:
+        if t.dim() != 3 or t.shape[2] not in channels:
+            raise ValueError(f"{name}: expected [H, W, C] with C in {tuple(channels)}, got shape {tuple(t.shape)}")
+        C = t.shape[2]
+    if tuple(t.shape[:2]) != (H, W):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} does not match the {W}x{H} camera")
+    allowed = {"image": (torch.float32, torch.float16), "f32": (torch.float32,), "i32": (torch.int32,)}[kind]
+    if t.dtype not in allowed:
+        raise ValueError(f"{name}: dtype {t.dtype} (need one of {allowed})")
+    if t.is_cuda:
+        if device is not None and t.device.index != device:
+            raise ValueError(f"{name}: on {t.device}, the context is on cuda:{device}")
+    elif not allow_host:
+        raise ValueError(f"{name}: must be a device tensor")
+    if H * W > 0:
+        if (C > 1 and (t.stride(2) != 1 or t.stride(1) != C)) or (C == 1 and t.stride(1) != 1):
+            raise ValueError(f"{name}: pixels must be contiguous")
+        if H > 1 and t.stride(0) < W * C:
+            raise ValueError(f"{name}: rows overlap (row stride {t.stride(0)} < {W * C})")
+
+
+def check_outputs(out, H, W, device=None, allow_host=False, masks_words=None):
+    check_tensor(out.get("ao"), "ao", H, W, None, "f32", device, allow_host)
+    check_tensor(out.get("gi"), "gi", H, W, (3,), "f32", device, allow_host)
+    check_tensor(out.get("ambient"), "ambient", H, W, (3,), "f32", device, allow_host)
+    if out.get("masks") is not None:
+        check_tensor(out["masks"], "masks", H, W, (masks_words,), "i32", device, allow_host)
+
+
 def _stream_ptr(stream):
     import torch
     if stream is None:
@@ -286,7 +328,8 @@ class Context:
     def compute(self, depth, normal, radiance, camera: Camera, params: Params, out=None, masks=False, stream=None):
         """Run ssvb_compute on torch device tensors; returns dict(ao, gi, ambient[, masks])."""
         import torch
-        H, W = depth.shape[:2]
+        H, W = camera.height, camera.width
+        self._check_inputs(depth, normal, radiance, H, W)
         dev = depth.device
         if out is None:
             out = {"ao": torch.empty((H, W), dtype=torch.float32, device=dev),
@@ -295,6 +338,7 @@ class Context:
             if masks:
                 out["masks"] = torch.empty((H, W, params.slices * (params.sectors // 32)), dtype=torch.int32,
                                            device=dev)
+        check_outputs(out, H, W, self.device, masks_words=params.slices * (params.sectors // 32))
         o = ssvb_outputs(out["ao"].data_ptr(), out["gi"].data_ptr(), out["ambient"].data_ptr(),
                          out["masks"].data_ptr() if out.get("masks") is not None else None,
                          out["ao"].stride(0) * 4, out["gi"].stride(0) * 4, out["ambient"].stride(0) * 4,
@@ -304,6 +348,11 @@ class Context:
         check(lib().ssvb_compute(self.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(r), ctypes.byref(c),
                                  ctypes.byref(p), ctypes.byref(o), _stream_ptr(stream)), "ssvb_compute")
         return out
+
+    def _check_inputs(self, depth, normal, radiance, H, W, allow_host=False):
+        check_tensor(depth, "depth", H, W, None, "f32", self.device, allow_host)
+        check_tensor(normal, "normal", H, W, (3, 4), "image", self.device, allow_host)
+        check_tensor(radiance, "radiance", H, W, (3, 4), "image", self.device, allow_host)
 
     @staticmethod
     def alloc_outputs(H, W, slices, device, masks=False, sectors=32):
@@ -324,7 +373,10 @@ class Context:
                             out["gi"].stride(0) * 4, out["ambient"].stride(0) * 4,
                             m.stride(0) * 4 if m is not None else 0)
 
-    def frame(self, depth, normal, radiance, camera: Camera, params: Params, out) -> ssvb_frame:
+    def frame(self, depth, normal, radiance, camera: Camera, params: Params, out, allow_host=False) -> ssvb_frame:
+        H, W = camera.height, camera.width
+        self._check_inputs(depth, normal, radiance, H, W, allow_host)
+        check_outputs(out, H, W, self.device, allow_host, masks_words=params.slices * (params.sectors // 32))
         return ssvb_frame(image_of(depth), image_of(normal), image_of(radiance), camera.to_c(), params.to_c(),
                           self.outputs_of(out))
 
@@ -359,6 +411,10 @@ class Context:
         H, W = direct.shape[:2]
         if out is None:
             out = torch.empty_like(direct)
+        check_tensor(direct, "direct", H, W, (3, 4), "image", self.device)
+        check_tensor(albedo, "albedo", H, W, (3, 4), "image", self.device)
+        check_tensor(gi, "gi", H, W, (3,), "f32", self.device)
+        check_tensor(out, "out", H, W, (3, 4), "image", self.device)  # the library checks C against direct
         d, a, o = image_of(direct), image_of(albedo), image_of(out)
         check(lib().ssvb_inject_bounce(self.handle, W, H, ctypes.byref(d), ctypes.byref(a), gi.data_ptr(),
                                        gi.stride(0) * 4, float(gain), ctypes.byref(o), _stream_ptr(stream)),
@@ -375,10 +431,17 @@ class Context:
         def like(s):
             return {k: torch.empty_like(s[k]) for k in ("ao", "gi", "ambient")}
 
+        H, W = camera.height, camera.width
+        check_tensor(depth, "depth", H, W, None, "f32", self.device)
+        check_tensor(normal, "normal", H, W, (3, 4), "image", self.device)
+        check_outputs({k: src.get(k) for k in ("ao", "gi", "ambient")}, H, W, self.device)
         if out is None:
             out = like(src)
         if tmp is None and passes > 1:
             tmp = like(src)
+        check_outputs(out, H, W, self.device)
+        if tmp is not None:
+            check_outputs(tmp, H, W, self.device)
         P = ssvb_denoise_params(int(passes), int(normal_power), float(plane_sigma), int(resolution))
         d, n, c = image_of(depth), image_of(normal), camera.to_c()
         three = ("ao", "gi", "ambient")  # slice masks (if `src` holds them) are not filtered
@@ -414,7 +477,8 @@ class Context:
 
     def debug_lattice(self, depth, camera: Camera, params: Params, stream=None):
         import torch
-        H, W = depth.shape[:2]
+        H, W = camera.height, camera.width
+        check_tensor(depth, "depth", H, W, None, "f32", self.device)
         xy = torch.empty((H, W, params.slices, 2, params.steps, 2), dtype=torch.int32, device=depth.device)
         d, c, p = image_of(depth), camera.to_c(), params.to_c()
         check(lib().ssvb_debug_lattice(self.handle, ctypes.byref(d), ctypes.byref(c), ctypes.byref(p),
@@ -423,7 +487,9 @@ class Context:
 
     def debug_endpoints(self, depth, normal, camera: Camera, params: Params, stream=None):
         import torch
-        H, W = depth.shape[:2]
+        H, W = camera.height, camera.width
+        check_tensor(depth, "depth", H, W, None, "f32", self.device)
+        check_tensor(normal, "normal", H, W, (3, 4), "image", self.device)
         ep = torch.empty((H, W, params.slices, 2, params.steps, 2), dtype=torch.float32, device=depth.device)
         d, n, c, p = image_of(depth), image_of(normal), camera.to_c(), params.to_c()
         check(lib().ssvb_debug_endpoints(self.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(c),
@@ -451,7 +517,7 @@ class Server:
         self._held = {}
 
     def submit(self, depth, normal, radiance, camera: Camera, params: Params, out) -> int:
-        F = self.ctx.frame(depth, normal, radiance, camera, params, out)
+        F = self.ctx.frame(depth, normal, radiance, camera, params, out, allow_host=True)
         t = ctypes.c_uint64()
         check(lib().ssvb_server_submit(self.handle, ctypes.byref(F), ctypes.byref(t)), "ssvb_server_submit")
         self._held[t.value] = (depth, normal, radiance, out)

@@ -580,6 +580,20 @@ ssvb_status ssvb_validate(const ssvb_image* depth, const ssvb_image* normal, con
 
 namespace {
 
+// Makes the context's device current for the lifetime of the guard (the test hooks below
+// run on whatever device the caller left current otherwise).
+struct DeviceGuard {
+    int prev = 0;
+    bool switched = false;
+    explicit DeviceGuard(int device) {
+        (void)hipGetDevice(&prev);
+        if (prev != device) switched = hipSetDevice(device) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (switched) (void)hipSetDevice(prev);
+    }
+};
+
 // One frame as a persistent single-frame launch (and the half-resolution fill) on
 // `stream`.  A counter set of the ring is reused only once its previous launch has
 // completed (blocks the host only with kRing launches of this context still in flight).
@@ -897,6 +911,7 @@ ssvb_status ssvb_debug_lattice(ssvb_ctx* ctx, const ssvb_image* depth, const ssv
     if (!xy_out) return fail(SSVB_ERR_INVALID_ARG, "NULL lattice output");
     FrameArgs A;
     fill_frame(A, &ctx->tab, depth, nullptr, nullptr, camera, params, nullptr);
+    DeviceGuard g(ctx->device);
     hipError_t e = launch_debug_lattice(A, xy_out, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "lattice launch");
     return SSVB_OK;
@@ -917,6 +932,7 @@ ssvb_status ssvb_debug_endpoints(ssvb_ctx* ctx, const ssvb_image* depth, const s
     FrameArgs A;
     fill_frame(A, &ctx->tab, depth, normal, nullptr, camera, params, nullptr);
     hipStream_t st = (hipStream_t)hip_stream;
+    DeviceGuard g(ctx->device);
     const size_t bytes = (size_t)W * H * params->slices * 2 * params->steps * 2 * sizeof(float);
     hipError_t e = hipMemsetAsync(ep_out, 0xFF, bytes, st);  // all-ones = NaN for skipped samples
     if (e == hipSuccess) e = launch_debug_endpoints(A, ep_out, st);
@@ -927,6 +943,7 @@ ssvb_status ssvb_debug_endpoints(ssvb_ctx* ctx, const ssvb_image* depth, const s
 ssvb_status ssvb_debug_direction_table(ssvb_ctx* ctx, int32_t* host_out) {
     if (!ctx || !host_out) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
     int2 tmp[kLutSize];
+    DeviceGuard g(ctx->device);
     hipError_t e = hipMemcpy(tmp, ctx->tab.d_lut, sizeof tmp, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "direction table copy");
     for (int k = 0; k < kLutSize; ++k) {

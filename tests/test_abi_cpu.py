@@ -182,3 +182,38 @@ def test_validate_depth_span_limit(B):
     assert status(B, frame(B, W=16384, H=16384, n=setter("channels", 4),
                            d=setter("pitch_bytes", 0))) == 0
     assert status(B, frame(B, W=16384, H=16384, n=setter("pitch_bytes", 16384 * 16 + 16))) == 1
+
+
+def test_binding_checks_tensors_against_the_camera(B):
+    """The C ABI takes bare pointers and pitches: the binding refuses tensors that the
+    library would read or write out of bounds (host tensors here, as the server takes)."""
+    import torch
+    chk = B.check_tensor
+    H, W = 6, 10
+    ok3 = torch.zeros((H, W, 3))
+    chk(ok3, "n", H, W, (3, 4), "image", allow_host=True)
+    chk(torch.zeros((H, W + 7, 4))[:, :W], "n", H, W, (3, 4), "image", allow_host=True)   # pitched view
+    chk(torch.zeros((H, W), dtype=torch.float16)[:, :W], "d", H, W, None, "image", allow_host=True)
+    chk(torch.zeros((0, 0)), "d", 0, 0, None, "f32", allow_host=True)
+    bad = [
+        (torch.zeros((H - 1, W, 3)), (3, 4), "image"),                 # fewer rows than the camera
+        (torch.zeros((H, W + 1, 3)), (3, 4), "image"),                 # wider than the camera
+        (torch.zeros((H, W, 2)), (3, 4), "image"),                     # channel count
+        (torch.zeros((H, W, 3), dtype=torch.float64), (3, 4), "image"),
+        (torch.zeros((1, W, 3)).expand(H, W, 3), (3, 4), "image"),     # every row the same memory
+        (torch.zeros((H, 2 * W, 3))[:, ::2], (3, 4), "image"),         # pixels not contiguous
+        (torch.zeros((H, W, 3)).permute(1, 0, 2).contiguous().permute(1, 0, 2), (3, 4), "image"),
+        (torch.zeros((H, W)), None, "i32"),                            # masks are int32
+    ]
+    for t, ch, kind in bad:
+        with pytest.raises(ValueError):
+            chk(t, "x", H, W, ch, kind, allow_host=True)
+    with pytest.raises(ValueError):                                    # device tensors only
+        chk(ok3, "n", H, W, (3, 4), "image")
+    out = {"ao": torch.zeros((H, W)), "gi": torch.zeros((H, W, 3)), "ambient": torch.zeros((H, W, 3))}
+    B.check_outputs(out, H, W, allow_host=True)
+    B.check_outputs(dict(out, masks=torch.zeros((H, W, 4), dtype=torch.int32)), H, W, allow_host=True, masks_words=4)
+    for k, t in (("ao", torch.zeros((H, W, 1))), ("gi", torch.zeros((H, W, 4))), ("ambient", torch.zeros((H, W - 1, 3))),
+                 ("masks", torch.zeros((H, W, 3), dtype=torch.int32))):
+        with pytest.raises(ValueError):
+            B.check_outputs(dict(out, **{k: t}), H, W, allow_host=True, masks_words=4)
