@@ -715,7 +715,7 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
     if ((int64_t)F.camera.width * F.camera.height == 0) return fail(SSVB_ERR_INVALID_ARG, "empty frame");
     static const int kTiles[][3] = {{32, 8, 1}, {16, 16, 1}, {64, 4, 1}, {8, 32, 1}, {16, 8, 2}, {8, 16, 2},
                                     {32, 4, 2}, {8, 8, 4},   {16, 4, 4}, {8, 4, 8},  {4, 8, 8}};
-    static const int kStrips[] = {2, 4, 8};
+    static const int kStrips[] = {1, 2, 4, 8};
     hipStream_t stream = (hipStream_t)hip_stream;
     int prev = 0;
     (void)hipGetDevice(&prev);
