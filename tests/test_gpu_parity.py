@@ -251,6 +251,44 @@ def test_pitched_buffers(ctx):
     PY.compare(gpu, ref, gb, oc, op)
 
 
+def test_binding_refuses_mismatched_tensors(ctx):
+    """Tensors that do not match the camera are refused by the binding before anything is
+    launched (the library itself only sees pointers and pitches); the outputs stay as they were."""
+    import torch
+    gb, cam, _ = tiny()
+    bc, _ = PY.cams(cam)
+    bp, _ = PY.params(slices=2, steps=4)
+    t = PY.to_device(gb)
+    H, W = gb["depth"].shape
+    out = filled_outputs(H, W)
+    bad_inputs = [
+        (t["depth"][: H - 1], t["normal"], t["radiance"]),               # fewer rows than the camera
+        (t["depth"], t["normal"][:, : W - 3], t["radiance"]),            # narrower
+        (t["depth"], t["normal"], t["radiance"][..., :2]),               # two channels
+        (t["depth"].double(), t["normal"], t["radiance"]),               # FP64 depth
+        (t["depth"][:1].expand(H, W), t["normal"], t["radiance"]),       # one row for all
+        (t["depth"].cpu(), t["normal"], t["radiance"]),                  # host memory
+    ]
+    for d, n, r in bad_inputs:
+        with pytest.raises(ValueError):
+            ctx.compute(d, n, r, bc, bp, out=out)
+    for k, v in (("ao", torch.zeros((H, W - 1), device="cuda")), ("gi", torch.zeros((H, W, 4), device="cuda")),
+                 ("ambient", torch.zeros((H - 2, W, 3), device="cuda"))):
+        with pytest.raises(ValueError):
+            ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp, out=dict(out, **{k: v}))
+    with pytest.raises(ValueError):   # masks narrower than N_d words per pixel
+        ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp,
+                    out=dict(out, masks=torch.zeros((H, W, 1), dtype=torch.int32, device="cuda")))
+    torch.cuda.synchronize()
+    assert all(bool((v == -7.0).all()) for v in out.values())
+
+
+def filled_outputs(H, W):
+    import torch
+    return {"ao": torch.full((H, W), -7.0, device="cuda"), "gi": torch.full((H, W, 3), -7.0, device="cuda"),
+            "ambient": torch.full((H, W, 3), -7.0, device="cuda")}
+
+
 def test_deterministic(ctx):
     gb, cam, sc = tiny()
     log("determinism")
