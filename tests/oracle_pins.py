@@ -131,6 +131,112 @@ def pin_plane_ambient_linear(O):
         assert np.allclose(r["ambient"][0], want, atol=1e-12), (na, r["ambient"][0], want)
 
 
+def _real_sh_scipy(l, m, dirs):
+    """Real spherical harmonic (l, m) from scipy's complex ones (which carry the
+    Condon-Shortley phase): sqrt(2) (-1)^m Im Y_l^|m| for m < 0, Y_l^0, sqrt(2) (-1)^m Re
+    Y_l^m for m > 0.  ``dirs`` [n, 3] unit vectors."""
+    from scipy.special import sph_harm_y
+    theta = np.arccos(np.clip(dirs[:, 2], -1.0, 1.0))
+    phi = np.arctan2(dirs[:, 1], dirs[:, 0])
+    if m < 0:
+        return math.sqrt(2.0) * (-1) ** m * np.imag(sph_harm_y(l, -m, theta, phi))
+    if m == 0:
+        return np.real(sph_harm_y(l, 0, theta, phi))
+    return math.sqrt(2.0) * (-1) ** m * np.real(sph_harm_y(l, m, theta, phi))
+
+
+SH_LM = [(0, 0), (1, -1), (1, 0), (1, 1), (2, -2), (2, -1), (2, 0), (2, 1), (2, 2)]  # index l^2 + l + m
+
+
+def _fibonacci_sphere(n):
+    k = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * k / n
+    r = np.sqrt(1.0 - z * z)
+    ph = math.pi * (3.0 - math.sqrt(5.0)) * k
+    return np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1)
+
+
+def pin_sh_basis(O):
+    """The ambient probe's nine basis functions are scipy's real spherical harmonics of
+    degree 0-2 in the order l^2 + l + m (values at random directions), and they are
+    orthonormal over the sphere (FP64 quadrature on a 20,000-point Fibonacci grid)."""
+    rng = np.random.default_rng(17)
+    d = rng.normal(size=(64, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    for i, (l, m) in enumerate(SH_LM):
+        c = np.zeros((9, 3))
+        c[i] = (1.0, -2.0, 0.5)
+        got = O.sh_eval(c, d)
+        want = _real_sh_scipy(l, m, d)
+        for ch, s in enumerate((1.0, -2.0, 0.5)):
+            assert np.allclose(got[:, ch], s * want, atol=1e-12), (i, l, m, ch)
+    g = _fibonacci_sphere(20000)
+    Y = np.stack([O.sh_eval(np.eye(9)[i][:, None] * np.ones((1, 3)), g)[:, 0] for i in range(9)])
+    gram = Y @ Y.T * (4.0 * math.pi / g.shape[0])
+    assert np.allclose(gram, np.eye(9), atol=1e-4), np.abs(gram - np.eye(9)).max()
+
+
+def _sh_quadratic_form(l, m):
+    """Constant c and symmetric Q with Y_lm(a) = c + a^T Q a on the unit sphere (least squares
+    on scipy's values; for l <= 2 the fit is exact)."""
+    rng = np.random.default_rng(3)
+    d = rng.normal(size=(40, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    A = np.stack([np.ones_like(x), x, y, z, x * x, y * y, z * z, 2 * x * y, 2 * y * z, 2 * x * z], axis=1)
+    sol = np.linalg.lstsq(A, _real_sh_scipy(l, m, d), rcond=None)[0]
+    assert np.allclose(A @ sol, _real_sh_scipy(l, m, d), atol=1e-12)
+    c, lin = sol[0], sol[1:4]
+    Q = np.array([[sol[4], sol[7], sol[9]], [sol[7], sol[5], sol[8]], [sol[9], sol[8], sol[6]]])
+    return c, lin, Q
+
+
+def pin_plane_ambient_quadratic(O):
+    """Centre pixel of a fronto-parallel plane (nothing occluded, projected normal = v),
+    FIXED noise so the N_d slices lie at i pi / N_d, under probes with quadratic terms.  The
+    subregion directions are a_k = cos(b_k) v + sin(b_k) e_i with b_k = -pi/2 + (k + 1/2)
+    pi / N_a, so the mean over them of any function c + l.a + a^T Q a is c + mean(cos b)
+    l.v + tr(Q M) with M = mean(cos^2 b) v v^T + mean(sin^2 b) mean_i(e_i e_i^T); for
+    N_d >= 2 the slice tangents average to half the identity of the image plane.  The
+    probe is evaluated in world space (a rotated to R a).  Tolerance: the direction table
+    rounds each e_i by at most 2^-13 rad."""
+    cam = make_camera(31, 31, fov_y_deg=90, pitch_deg=0)
+    gb = plane_gbuffer(cam, (0, 0, 1), (0, 0, -3.0))
+    rng = np.random.default_rng(23)
+    R = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    if np.linalg.det(R) < 0:
+        R[:, 0] = -R[:, 0]
+    Rf = np.array([float(np.float32(v)) for v in R.reshape(-1)]).reshape(3, 3)
+    cam = cam.__class__(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(Rf.reshape(-1)))
+    forms = [_sh_quadratic_form(l, m) for (l, m) in SH_LM]
+    v = np.array([0.0, 0.0, 1.0])
+    probes = []
+    for i in range(4, 9):  # one quadratic coefficient at a time
+        sh = np.zeros((9, 3))
+        sh[i] = rng.uniform(-1.0, 1.0, 3)
+        probes.append(sh)
+    probes.append(rng.uniform(-0.6, 0.6, (9, 3)))  # every band at once
+    for nd in (2, 4):
+        for na in (1, 2, 4):
+            kk = np.arange(na)
+            b = -0.5 * math.pi + (kk + 0.5) * math.pi / na
+            mc, mc2, ms2 = np.cos(b).mean(), (np.cos(b) ** 2).mean(), (np.sin(b) ** 2).mean()
+            M = mc2 * np.outer(v, v) + ms2 * 0.5 * np.diag([1.0, 1.0, 0.0])
+            for sh in probes:
+                shf = np.array([float(np.float32(x)) for x in sh.reshape(-1)]).reshape(9, 3)
+                prm = O.Params(slices=nd, steps=4, radius=1.0, thickness=0.5, noise=O.NOISE_FIXED,
+                               ambient_samples=na, ambient_sh=tuple(sh.reshape(-1)))
+                r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, pixels=([15], [15]))
+                want = np.zeros(3)
+                for i, (c, lin, Q) in enumerate(forms):
+                    Qv = Rf.T @ Q @ Rf  # world direction = R a
+                    val = c + mc * (lin @ (Rf @ v)) + np.trace(Qv @ M)
+                    want += val * shf[i]
+                scale = np.abs(shf).sum(axis=0)
+                assert np.all(np.abs(r["ambient"][0] - want) <= 1e-3 * scale + 1e-12), \
+                    (nd, na, r["ambient"][0], want)
+
+
 # ----------------------------------------------------------------------------------------
 # P2: infinite thickness reproduces the horizon (GTAO) integral
 # ----------------------------------------------------------------------------------------
@@ -936,6 +1042,8 @@ ALL_PINS = [
     pin_plane_fronto,
     pin_plane_tilted,
     pin_plane_ambient_linear,
+    pin_sh_basis,
+    pin_plane_ambient_quadratic,
     pin_horizon_infinite_thickness,
     pin_horizon_uniform_integral,
     pin_gtao_cosine_closed_form,

@@ -77,6 +77,16 @@ MUTATIONS = {
                                                   "np.arange(gh), np.arange(gw)"),
     "denoise tap taken from the pixel": ("acc[py0:py1, px0:px1] += w[..., None] * sig[Q]",
                                          "acc[py0:py1, px0:px1] += w[..., None] * sig[py0:py1, px0:px1]"),
+    "SH xy constant halved": ("0.5 * math.sqrt(15.0 / pi) * x * y", "0.25 * math.sqrt(15.0 / pi) * x * y"),
+    "SH yz and xz swapped": ("0.5 * math.sqrt(15.0 / pi) * y * z,\n        0.25 * math.sqrt(5.0 / pi) * (3.0 * z * z - 1.0),\n"
+                             "        0.5 * math.sqrt(15.0 / pi) * x * z,",
+                             "0.5 * math.sqrt(15.0 / pi) * x * z,\n        0.25 * math.sqrt(5.0 / pi) * (3.0 * z * z - 1.0),\n"
+                             "        0.5 * math.sqrt(15.0 / pi) * y * z,"),
+    "SH x^2 - y^2 read as x^2 - z^2": ("(x * x - y * y)", "(x * x - z * z)"),
+    "SH zonal constant doubled": ("0.25 * math.sqrt(5.0 / pi) * (3.0 * z * z - 1.0)",
+                                  "0.5 * math.sqrt(5.0 / pi) * (3.0 * z * z - 1.0)"),
+    "SH zonal without the constant": ("(3.0 * z * z - 1.0)", "(3.0 * z * z)"),
+    "SH x^2 - y^2 constant": ("0.25 * math.sqrt(15.0 / pi) * (x * x - y * y)", "0.5 * math.sqrt(15.0 / pi) * (x * x - y * y)"),
     "denoise background overwritten": ("sig = np.where(fg[..., None], acc / wsum[..., None], sig)",
                                        "sig = acc / wsum[..., None]"),
 }
