@@ -324,11 +324,18 @@ typedef struct {
 ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t streams, ssvb_server** out);
 
 /* Queue one frame (validated as by ssvb_compute; masks must be NULL) and return its
- * ticket.  Never blocks on the device.  SSVB_ERR_OUT_OF_MEMORY if its footprint exceeds
- * the whole arena; SSVB_ERR_BUSY if 2^20 tickets are unreleased or the server is being
- * destroyed; SSVB_ERR_DEVICE after a device error stopped the server.  A frame with no
- * pixels finishes at once. */
-ssvb_status ssvb_server_submit(ssvb_server* server, const ssvb_frame* frame, uint64_t* ticket);
+ * ticket.  Never blocks on the device.  hip_stream is the stream on which the caller last
+ * wrote or read the frame's buffers (inputs and outputs; NULL is the null stream): an
+ * event is recorded on it here, and every copy and kernel of the server that touches this
+ * request's buffers waits for that event, so the request sees all work the caller
+ * enqueued on that stream before this call, with no host synchronisation.  Work on other
+ * streams must be ordered before this call by the caller.  The buffers must stay alive
+ * and must not be written by the caller until the request has finished.
+ * SSVB_ERR_OUT_OF_MEMORY if its footprint exceeds the whole arena; SSVB_ERR_BUSY if 2^20
+ * tickets are unreleased or the server is being destroyed; SSVB_ERR_DEVICE after a device
+ * error stopped the server, or if the event cannot be recorded on hip_stream.  A frame
+ * with no pixels finishes at once. */
+ssvb_status ssvb_server_submit(ssvb_server* server, const ssvb_frame* frame, void* hip_stream, uint64_t* ticket);
 
 /* *done = 1 once the request's outputs are in the caller's buffers; *latency_ms (may be
  * NULL) is then the time from submission to completion.  SSVB_ERR_NOT_FOUND for an

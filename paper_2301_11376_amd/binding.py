@@ -149,7 +149,7 @@ def lib() -> ctypes.CDLL:
     L.ssvb_server_create.restype = I
     L.ssvb_server_create.argtypes = [V, U64, I, P(V)]
     L.ssvb_server_submit.restype = I
-    L.ssvb_server_submit.argtypes = [V, P(ssvb_frame), P(U64)]
+    L.ssvb_server_submit.argtypes = [V, P(ssvb_frame), V, P(U64)]
     L.ssvb_server_poll.restype = I
     L.ssvb_server_poll.argtypes = [V, U64, P(I), P(D)]
     L.ssvb_server_wait.restype = I
@@ -516,10 +516,13 @@ class Server:
         self.ctx = ctx
         self._held = {}
 
-    def submit(self, depth, normal, radiance, camera: Camera, params: Params, out) -> int:
+    def submit(self, depth, normal, radiance, camera: Camera, params: Params, out, stream=None) -> int:
+        """Queue a frame; the server orders its work after everything enqueued on `stream`
+        (default: the current torch stream of the context's device) before this call."""
         F = self.ctx.frame(depth, normal, radiance, camera, params, out, allow_host=True)
         t = ctypes.c_uint64()
-        check(lib().ssvb_server_submit(self.handle, ctypes.byref(F), ctypes.byref(t)), "ssvb_server_submit")
+        check(lib().ssvb_server_submit(self.handle, ctypes.byref(F), _stream_ptr(stream), ctypes.byref(t)),
+              "ssvb_server_submit")
         self._held[t.value] = (depth, normal, radiance, out)
         return t.value
 

@@ -73,6 +73,9 @@ struct Request {
     int state = QUEUED;
     ssvb_status err = SSVB_OK;
     Clock::time_point t_submit, t_done;
+    // recorded at submission on the caller's stream: the server's copies and kernels for
+    // this request wait on it, so they run after everything the caller enqueued before
+    hipEvent_t ready = nullptr;
 };
 
 // A round on one stream, in parts that finish in stream order: its packed small frames,
@@ -122,6 +125,7 @@ struct ssvb_server {
     hipError_t fatal = hipSuccess;  // first device error; every later request fails with it
     std::string fatal_what;
     std::unordered_map<uint64_t, Request> reqs;
+    std::vector<hipEvent_t> ev_pool;  // ready events of finished requests, for reuse
     uint64_t next_ticket = 1;
     ssvb_server_counters st{};
 };
@@ -155,6 +159,10 @@ hipError_t stage(ssvb_server* S, Request& r, uint64_t off) {
     if (!r.out_in_place)
         r.staged.out = ssvb_outputs{(float*)(base + r.lay.ao), (float*)(base + r.lay.gi), (float*)(base + r.lay.amb),
                                     nullptr, 0, 0, 0, 0};
+    if (!(r.in_place[0] && r.in_place[1] && r.in_place[2])) {
+        const hipError_t e = hipStreamWaitEvent(S->copy_stream, r.ready, 0);
+        if (e != hipSuccess) return e;
+    }
     const ssvb_image* src[3] = {&F.depth, &F.normal, &F.radiance};
     for (int i = 0; i < 3; ++i) {
         if (r.in_place[i]) continue;
@@ -194,6 +202,8 @@ hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs, 
                         std::vector<Part>& parts) {
     hipStream_t s = S->streams[k];
     hipError_t e = hipStreamWaitEvent(s, S->staged, 0);
+    // buffers read or written in place (inputs, outputs) are ordered after the caller's work
+    for (size_t i = 0; i < rs.size() && e == hipSuccess; ++i) e = hipStreamWaitEvent(s, rs[i]->ready, 0);
     // the stream's previous round has retired: every counter set is back at zero and the
     // slot's descriptor upload is done
     ssvb_frame small[kMaxBatch];
@@ -261,7 +271,15 @@ hipError_t launch_round(ssvb_server* S, int k, const std::vector<Request*>& rs, 
     return e;
 }
 
+// A request reached a terminal state: its ready event goes back to the pool (every wait on
+// it was enqueued when the request was staged or launched).
+void recycle_event(ssvb_server* S, Request& r) {
+    if (r.ready) S->ev_pool.push_back(r.ready);
+    r.ready = nullptr;
+}
+
 void fail_request(ssvb_server* S, uint64_t t, Request& r, Clock::time_point now) {
+    recycle_event(S, r);
     r.state = FAILED;
     r.err = SSVB_ERR_DEVICE;
     r.t_done = now;
@@ -309,6 +327,7 @@ void run(ssvb_server* S) {
                 }
                 for (uint64_t t : R.parts[R.next_part].tickets) {
                     Request& r = S->reqs[t];
+                    recycle_event(S, r);
                     r.state = DONE;
                     r.t_done = now;
                     S->adm.finish(t);
@@ -419,6 +438,7 @@ void run(ssvb_server* S) {
             for (uint64_t t : S->adm.cancel_ready()) fail_request(S, t, S->reqs[t], t_fail);
             for (uint64_t t : S->adm.cancel_queued()) {
                 Request& r = S->reqs[t];
+                recycle_event(S, r);
                 r.state = FAILED;
                 r.err = SSVB_ERR_DEVICE;
                 r.t_done = t_fail;
@@ -435,6 +455,10 @@ ssvb_status fatal_status(const ssvb_server* S) {
 }
 
 void destroy_resources(ssvb_server* S) {
+    for (auto& kv : S->reqs)
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+    for (hipEvent_t ev : S->ev_pool) (void)hipEventDestroy(ev);
+    S->ev_pool.clear();
     for (int k = 0; k < kMaxStreams; ++k) {
         for (int i = 0; i < kMaxBatch; ++i)
             if (S->part_ev[k][i]) (void)hipEventDestroy(S->part_ev[k][i]);
@@ -512,7 +536,7 @@ ssvb_status ssvb_server_create(ssvb_ctx* ctx, uint64_t hbm_budget_bytes, int32_t
     return SSVB_OK;
 }
 
-ssvb_status ssvb_server_submit(ssvb_server* S, const ssvb_frame* frame, uint64_t* ticket) {
+ssvb_status ssvb_server_submit(ssvb_server* S, const ssvb_frame* frame, void* hip_stream, uint64_t* ticket) {
     if (!S || !frame || !ticket) return fail(SSVB_ERR_INVALID_ARG, "NULL argument");
     const ssvb_frame& F = *frame;
     ssvb_status s = ssvb_validate(&F.depth, &F.normal, &F.radiance, &F.camera, &F.params, &F.out);
@@ -532,11 +556,39 @@ ssvb_status ssvb_server_submit(ssvb_server* S, const ssvb_frame* frame, uint64_t
         return fail(SSVB_ERR_OUT_OF_MEMORY, "request footprint %llu bytes exceeds the %llu-byte arena",
                     (unsigned long long)r.lay.total, (unsigned long long)S->adm.arena().size());
     const bool empty = (int64_t)F.camera.width * F.camera.height == 0;
+    if (!empty) {
+        // order the request after the caller's work on `hip_stream`
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            if (!S->ev_pool.empty()) {
+                r.ready = S->ev_pool.back();
+                S->ev_pool.pop_back();
+            }
+        }
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        if (prev != S->device) (void)hipSetDevice(S->device);
+        hipError_t e = r.ready ? hipSuccess : hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(r.ready, (hipStream_t)hip_stream);
+        if (prev != S->device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) {
+            if (r.ready) {
+                std::lock_guard<std::mutex> g(S->mu);
+                S->ev_pool.push_back(r.ready);
+            }
+            return hip_fail(e, "recording the request's ready event");
+        }
+    }
     {
         std::lock_guard<std::mutex> g(S->mu);
-        if (S->fatal != hipSuccess) return fatal_status(S);
-        if (S->stop) return fail(SSVB_ERR_BUSY, "server is shutting down");
-        if (S->reqs.size() >= kMaxLive) return fail(SSVB_ERR_BUSY, "%zu requests not yet released", S->reqs.size());
+        auto refuse = [&](ssvb_status st) {
+            recycle_event(S, r);
+            return st;
+        };
+        if (S->fatal != hipSuccess) return refuse(fatal_status(S));
+        if (S->stop) return refuse(fail(SSVB_ERR_BUSY, "server is shutting down"));
+        if (S->reqs.size() >= kMaxLive)
+            return refuse(fail(SSVB_ERR_BUSY, "%zu requests not yet released", S->reqs.size()));
         const uint64_t t = S->next_ticket++;
         r.t_submit = Clock::now();
         if (empty) {
@@ -614,7 +666,10 @@ ssvb_status ssvb_server_destroy(ssvb_server* S) {
         S->stop = true;
         // requests not yet in a round are dropped; rounds on the device are waited for
         for (uint64_t t : S->adm.cancel_ready()) S->reqs[t].state = FAILED;
-        for (uint64_t t : S->adm.cancel_queued()) S->reqs[t].state = FAILED;
+        for (uint64_t t : S->adm.cancel_queued()) {
+            recycle_event(S, S->reqs[t]);
+            S->reqs[t].state = FAILED;
+        }
     }
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();

@@ -222,6 +222,43 @@ def test_rounds_overlap_and_alone_equals_mix(ctx):
         srv.close()
 
 
+def test_submit_orders_after_caller_stream(ctx):
+    """Inputs written and outputs cleared by work still queued on the caller's stream,
+    submitted with no host synchronisation: the server waits for that work (an event
+    recorded on the caller's stream at submission), so the results equal plain launches
+    on the final inputs (device buffers, read and written in place)."""
+    import torch
+    from paper_2301_11376_amd import Server
+    items = make_items(SPECS[:2])
+    refs = [host(plain(ctx, gb, cam, kw)) for gb, cam, kw in items]
+    srv = Server(ctx, 256 << 20)
+    try:
+        for rep in range(2):
+            reqs = []
+            for (gb, cam, kw), ref in zip(items, refs):
+                t, bc, bp, out = device_request(gb, cam, kw, pinned=False)
+                src = {k: v.clone() for k, v in t.items()}
+                for v in t.values():
+                    v.zero_()  # depth 0: every pixel background until the copy below lands
+                torch.cuda.synchronize()
+                # tens of milliseconds of queued work, then the real inputs
+                a = torch.randn(4096, 4096, device="cuda")
+                for _ in range(12):
+                    a = torch.mm(a, a) * 1e-2
+                for k in t:
+                    t[k].copy_(src[k])
+                for v in out.values():
+                    v.fill_(float("nan"))
+                reqs.append((srv.submit(t["depth"], t["normal"], t["radiance"], bc, bp, out), out, ref, t, src))
+            for tk, out, ref, _, _ in reqs:
+                srv.wait(tk, 60000)
+                same(host(out), ref, (rep, tk))
+                srv.release(tk)
+            log(f"rep {rep}: {len(reqs)} requests ordered after the caller's stream")
+    finally:
+        srv.close()
+
+
 def test_pinned_host_buffers(ctx):
     from paper_2301_11376_amd import Server
     items = make_items(SPECS[3:5])
