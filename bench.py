@@ -75,49 +75,89 @@ def measured_traffic(workload_name, shape):
 
 
 # ---------------------------------------------------------------------------------------
-# CPU baseline: the oracle as it stands, on row bands, one process per band
+# cpu_baseline leg: the FP64 oracle as it stands, on row bands, one process per band.  Its
+# runs give the timed baseline (a bounded band of each workload, median of 3) and the
+# reference outputs the GPU's per-output error is reported against.
 # ---------------------------------------------------------------------------------------
 
-_CPU_JOB = None
+# rows per band of the timed baseline (HOST_WORKERS bands, centred in the frame): about
+# 63 M samples each at 1080p and 4K, the whole frame at 128x128
+TIMED_ROWS = {"c1_128": None, "c2_1080p": 16, "c3_4k_fp16": 2}
+# rows of the 4K frame whose outputs are compared with the oracle (centred)
+C3_PARITY_ROWS = 135
 
 
-def _oracle_band(rows):
-    from threadpoolctl import threadpool_limits
+def oracle_params(O, w, scene):
+    return O.Params(slices=w["slices"], steps=w["steps"], radius=w["radius"], thickness=w["thickness"],
+                    noise=O.NOISE_NAMES[w["noise"]], seed=w["seed"],
+                    ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
+
+
+def oracle_camera(O, cam):
+    return O.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(cam.view_to_world))
+
+
+def cpu_baseline_leg(loaded, workers, names):
+    """Timed oracle bands (median of 3 per workload) and the oracle's outputs for the error
+    report: the whole 128x128 and 1080p frames (with slice masks) and a centred band of the
+    4K frame on its FP16 inputs (with masks) and on the FP32 originals."""
     import oracle as O
-    gb, oc, kw = _CPU_JOB
-    W = gb["depth"].shape[1]
-    ys = np.repeat(np.arange(rows[0], rows[1]), W)
-    xs = np.tile(np.arange(W), rows[1] - rows[0])
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, O.Params(**kw), pixels=(ys, xs))
-        return time.perf_counter() - t0
-
-
-def cpu_baseline(gb, cam, kw, rows_per_worker=36):
-    """The FP64 oracle on `workers` disjoint row bands of the frame, one forked process
-    (one thread) per band, timed end to end."""
-    global _CPU_JOB
-    import multiprocessing as mp
-    import oracle as O
-    H, W = gb["depth"].shape
-    workers = max(1, min(HOST_WORKERS, os.cpu_count() or 1, H // rows_per_worker))
-    y0 = (H - workers * rows_per_worker) // 2
-    bands = [(y0 + i * rows_per_worker, y0 + (i + 1) * rows_per_worker) for i in range(workers)]
-    oc = O.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(cam.view_to_world))
-    _CPU_JOB = (gb, oc, kw)
+    from oracle.bands import compute_rows
+    base, refs = {}, {}
+    for name in names:
+        gb, cam, w, scene = loaded[name][:4]
+        H, W = gb["depth"].shape
+        oc, prm = oracle_camera(O, cam), oracle_params(O, w, scene)
+        rows = TIMED_ROWS[name]
+        r0, r1 = (0, H) if rows is None else ((H - workers * rows) // 2, (H - workers * rows) // 2 + workers * rows)
+        runs = []
+        for _ in range(3):
+            res, wall, cpu = compute_rows(gb, oc, prm, r0, r1, workers, return_masks=rows is None)
+            runs.append((wall, cpu))
+        if rows is None:
+            refs[name] = {"rows": (0, H), "fp": res}
+        samples = (r1 - r0) * W * w["slices"] * 2 * w["steps"]
+        walls = sorted(r[0] for r in runs)
+        med = walls[1]
+        base[name] = {"value": samples / med / 1e9, "unit": "Gsamples/s", "cores": min(workers, r1 - r0),
+                      "kind": "oracle",
+                      "sample": f"rows {r0}..{r1 - 1} of the {W}x{H} frame ({(r1 - r0) * W} px, {samples} samples) in "
+                                f"{min(workers, r1 - r0)} bands, one single-threaded NumPy FP64 process per band; "
+                                f"median of 3 runs ({', '.join(f'{x:.2f}' for x in walls)} s wall)",
+                      "single_process_value": samples / float(np.median([r[1] for r in runs])) / 1e9}
+        print(f"cpu baseline {name}: {base[name]['value']:.4f} Gsamples/s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(workers) as p:
-        per = p.map(_oracle_band, bands)
-    wall = time.perf_counter() - t0
-    px = workers * rows_per_worker * W
-    samples = px * kw["slices"] * 2 * kw["steps"]
-    return {"value": samples / wall / 1e9, "unit": "Gsamples/s", "cores": workers, "kind": "oracle",
-            "sample": f"rows {bands[0][0]}..{bands[-1][1] - 1} of the same frame ({px} px, {samples} samples) "
-                      f"in {workers} bands of {rows_per_worker} rows, one single-threaded NumPy FP64 process "
-                      f"per band; {wall:.1f} s wall, {sum(per):.1f} s CPU",
-            "single_process_value": samples / sum(per) / 1e9, "cpu_model": cpu_model(),
-            "host_cpus": os.cpu_count()}
+    if "c2_1080p" in names:
+        gb, cam, w, scene = loaded["c2_1080p"][:4]
+        H = gb["depth"].shape[0]
+        res, _, _ = compute_rows(gb, oracle_camera(O, cam), oracle_params(O, w, scene), 0, H, workers,
+                                 return_masks=True, bands=4 * workers)
+        refs["c2_1080p"] = {"rows": (0, H), "fp": res}
+    if "c3_4k_fp16" in names:
+        gb, cam, w, scene, gb32 = loaded["c3_4k_fp16"]
+        H = gb["depth"].shape[0]
+        r0 = (H - C3_PARITY_ROWS) // 2
+        oc, prm = oracle_camera(O, cam), oracle_params(O, w, scene)
+        res16, _, _ = compute_rows(gb, oc, prm, r0, r0 + C3_PARITY_ROWS, workers, return_masks=True,
+                                   bands=2 * workers)
+        res32, _, _ = compute_rows(gb32, oc, prm, r0, r0 + C3_PARITY_ROWS, workers, bands=2 * workers)
+        refs["c3_4k_fp16"] = {"rows": (r0, r0 + C3_PARITY_ROWS), "fp": res16, "fp32_originals": res32}
+    print(f"oracle reference outputs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return base, refs
+
+
+def error_report(gpu, ref, masks=True):
+    """Per output: mean, p99 and max of |GPU - FP64 oracle| over every element (AO per
+    pixel, GI and ambient per pixel and channel); with masks, the fraction of pixels whose
+    slice masks all equal the oracle's."""
+    rep = {}
+    for k in ("ao", "gi", "ambient"):
+        d = np.abs(gpu[k].astype(np.float64) - ref[k]).reshape(-1)
+        rep[k] = {"mean": float(d.mean()), "p99": float(np.percentile(d, 99)), "max": float(d.max())}
+    if masks:
+        g = gpu["masks"].reshape(ref["masks"].shape).view(np.uint32)
+        rep["mask_agreement"] = float((g == ref["masks"]).all(axis=-1).mean())
+    return rep
 
 
 def cpu_model():
@@ -490,6 +530,84 @@ def serve_leg(ctx, pool, n_requests, rates):
             "plain_frames_per_s": plain_fps, "served_vs_plain": sat_fps / plain_fps, "rates": results}
 
 
+def frame_leg(ctx, name, gb, cam, w, scene, steps, warmup, own_noise=True):
+    """One workload's frame, inputs resident in HBM: `warmup` untimed launches, then `steps`
+    launches timed by the host clock around the loop (ms/frame, Gsamples/s) and by HIP
+    events on the stream the kernels run on (the gather kernel's duration, the roofline)."""
+    import torch
+    from paper_2301_11376_amd import Camera, Params, NOISE_NAMES
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in gb.items()}
+    H, W = gb["depth"].shape
+    out = {"ao": torch.empty((H, W), device=dev), "gi": torch.empty((H, W, 3), device=dev),
+           "ambient": torch.empty((H, W, 3), device=dev)}
+    c = Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(cam.view_to_world))
+    p = Params(slices=w["slices"], steps=w["steps"], radius=w["radius"], thickness=w["thickness"],
+               noise=NOISE_NAMES[w["noise"]], seed=w["seed"],
+               ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
+    stream = torch.cuda.current_stream()
+    shape = ctx.get_launch(c, p, 3 if w["fp16"] else 0)
+    for _ in range(warmup):
+        ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    ms = wall * 1e3 / steps
+    samples, abytes = algorithmic_bytes(W, H, w["slices"], w["steps"], w["fp16"])
+    kernel_ms = float(per_launch_ms.mean())
+    achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    floor_bytes = W * H * ((4 + 6 + 6 if w["fp16"] else 4 + 12 + 12) + 28)
+    print(f"{name}: timed {steps} steps: {ms:.3f} ms/frame wall, kernel mean {kernel_ms:.3f} ms "
+          f"(p50 {np.percentile(per_launch_ms, 50):.3f}, p99 {np.percentile(per_launch_ms, 99):.3f})",
+          file=sys.stderr, flush=True)
+    res = {
+        "workload": f"{name}: {W}x{H}, {w['slices']} slices x {w['steps']} steps per side, N_b 32, radius "
+                    f"{w['radius']}, thickness {w['thickness']:.4g}, noise {w['noise']}, "
+                    f"{'FP16' if w['fp16'] else 'FP32'} normals and radiance, procedural scene seed {w['seed']} "
+                    f"({w['n_boxes']} boxes, {w['n_planes']} thin planes)",
+        "samples_per_frame": samples, "pixels": W * H, "ms_per_frame": ms,
+        "gsamples_s": samples / (ms * 1e-3) / 1e9, "steps": steps, "warmup": warmup,
+        "kernel_ms": {"mean": kernel_ms, "p50": float(np.percentile(per_launch_ms, 50)),
+                      "p90": float(np.percentile(per_launch_ms, 90)),
+                      "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(name, shape) if own_noise else None,
+                     "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": abytes,
+                     "bytes_per_sample": 16 if w["fp16"] else 28, "bytes_per_pixel": 38 if w["fp16"] else 44,
+                     "launch_shape": list(shape), "compulsory_floor_bytes": floor_bytes,
+                     "compulsory_floor_ms": floor_bytes / (HBM_PEAK_GBS * 1e9) * 1e3},
+    }
+    return res, (t, c, p, out)
+
+
+def parity_leg(ctx, name, tensors, ref):
+    """The workload's frame once more with slice masks, compared with the oracle's outputs
+    from the cpu_baseline leg (the rows it computed)."""
+    import torch
+    t, c, p, _ = tensors
+    o = ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, masks=True)
+    torch.cuda.synchronize()
+    r0, r1 = ref["rows"]
+    gpu = {k: v[r0:r1].cpu().numpy() for k, v in o.items()}
+    del o
+    rep = {"rows": [r0, r1], "vs_oracle_same_inputs": error_report(gpu, ref["fp"])}
+    if "fp32_originals" in ref:
+        rep["vs_oracle_fp32_originals"] = error_report(gpu, ref["fp32_originals"], masks=False)
+    e = rep["vs_oracle_same_inputs"]
+    print(f"parity {name}: masks {e['mask_agreement']:.6f}, max |err| AO {e['ao']['max']:.2e} "
+          f"GI {e['gi']['max']:.2e} ambient {e['ambient']['max']:.2e}", file=sys.stderr, flush=True)
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -499,13 +617,17 @@ def main():
     ap.add_argument("--noise", choices=["hash", "r2", "fixed"], default=None,
                     help="replace the workload's noise (fixed: every pixel the same slice directions and "
                          "offsets, which shows what the per-pixel decorrelation costs in cache misses)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle: no cpu_baseline and no per-output error report")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 4K FP16 leg")
+    ap.add_argument("--c3-steps", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-table2", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-sweep", action="store_true", help="also serve at 0.5 and 0.9 of saturation")
+    ap.add_argument("--serve-rates", default="0.5,0.7,0.9",
+                    help="request rates as fractions of the saturated rate (p50 / p99 at each)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the gather, run a plain device copy of MIB MiB (scales HBM counters)")
     args = ap.parse_args()
@@ -526,13 +648,21 @@ def main():
         return
 
     # ---- host work first (forked workers), before anything touches the GPU ----
-    from gbuffer_scene import workload, mixed_batch, request_stream, render_pool
-    gb, cam, w, scene = workload(args.workload)
-    own_noise = w["noise"]
-    if args.noise:
-        w["noise"] = args.noise
-    kw = dict(slices=w["slices"], steps=w["steps"], radius=w["radius"], thickness=w["thickness"],
-              seed=w["seed"], ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
+    from gbuffer_scene import workload, request_stream, render_pool, render_gbuffer
+    names = [args.workload]
+    if args.workload == "c2_1080p" and not args.no_c3:
+        names.append("c3_4k_fp16")
+    if not args.no_cpu_baseline and "c1_128" not in names:
+        names.insert(0, "c1_128")
+    loaded = {}
+    for n in names:
+        gb_n, cam_n, w_n, sc_n = workload(n)
+        own = w_n["noise"]
+        if args.noise:
+            w_n["noise"] = args.noise
+        w_n["own_noise"] = own == w_n["noise"]
+        extra = (render_gbuffer(sc_n, cam_n),) if w_n["fp16"] else ()  # FP32 originals
+        loaded[n] = (gb_n, cam_n, w_n, sc_n) + extra
     keys = []
     if not args.no_batch:
         keys += [(f["scene_seed"], f["width"], f["height"]) for kind in BATCH_WORKLOADS for f in batch_frames(kind)]
@@ -543,87 +673,53 @@ def main():
         t0 = time.perf_counter()
         pool = render_pool(keys, workers=min(HOST_WORKERS, os.cpu_count() or 1))
         print(f"rendered {len(pool)} pool frames in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    cpu = None
+    base, refs = None, {}
     if not args.no_cpu_baseline:
-        import oracle as O
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        onoise = {"hash": O.NOISE_HASH, "r2": O.NOISE_R2, "fixed": O.NOISE_FIXED}[w["noise"]]
-        cpu = cpu_baseline(gb, cam, dict(kw, noise=onoise))
-        print(f"cpu baseline {cpu['value']:.4f} Gsamples/s on {cpu['cores']} processes", file=sys.stderr, flush=True)
+        base, refs = cpu_baseline_leg(loaded, max(1, min(HOST_WORKERS, os.cpu_count() or 1)), names)
 
     # ---- GPU ----
     import torch
-    from paper_2301_11376_amd import Camera, Context, Params, NOISE_NAMES
+    from paper_2301_11376_amd import Context
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    t = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in gb.items()}
-    H, W = gb["depth"].shape
-    out = {"ao": torch.empty((H, W), device=dev), "gi": torch.empty((H, W, 3), device=dev),
-           "ambient": torch.empty((H, W, 3), device=dev)}
     ctx = Context(0)
-    c = Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, tuple(cam.view_to_world))
-    p = Params(**dict(kw, noise=NOISE_NAMES[w["noise"]]))
-    stream = torch.cuda.current_stream()
-
-    shape = ctx.get_launch(c, p, 1 * (w["fp16"]) | 2 * (w["fp16"]))
-    for _ in range(args.warmup):
-        ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
-    torch.cuda.synchronize()
-    print(f"warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per_launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    ms = wall * 1e3 / args.steps
-    samples, abytes = algorithmic_bytes(W, H, kw["slices"], kw["steps"], w["fp16"])
-    kernel_ms = float(per_launch_ms.mean())
-    achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    gb, cam, w, scene = loaded[args.workload][:4]
+    head, tensors = frame_leg(ctx, args.workload, gb, cam, w, scene, args.steps, args.warmup, w["own_noise"])
+    t, c, p, out = tensors
     copy_gbs = stream_copy_gbs()
-    floor_bytes = W * H * ((4 + 6 + 6 if w["fp16"] else 4 + 12 + 12) + 28)
-    print(f"timed {args.steps} steps: {ms:.3f} ms/frame wall, kernel mean {kernel_ms:.3f} ms "
-          f"(p50 {np.percentile(per_launch_ms, 50):.3f}, p99 {np.percentile(per_launch_ms, 99):.3f})",
-          file=sys.stderr, flush=True)
-
+    head["roofline"]["stream_copy_gbs"] = copy_gbs
+    head["roofline"]["frac_of_stream_copy"] = head["roofline"]["achieved"] / copy_gbs
     result = {
         "metric": "Gsamples/s & ms/frame at 1080p vs HBM roofline; p50/p99 latency, mixed frames",
-        "value": samples / (ms * 1e-3) / 1e9,
+        "value": head["gsamples_s"],
         "unit": "Gsamples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_frame"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" + ("+f16 normal/radiance" if w["fp16"] else ""),
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {W}x{H}, {kw['slices']} slices x {kw['steps']} steps per side, "
-                               f"N_b 32, radius {kw['radius']}, thickness {kw['thickness']:.4g}, noise {w['noise']}, "
-                               f"procedural scene seed {w['seed']} ({w['n_boxes']} boxes, {w['n_planes']} thin planes)",
-                   "samples_per_frame": samples, "pixels": W * H, "parallelism": "single GPU",
+        "config": {"workload": head["workload"], "samples_per_frame": head["samples_per_frame"],
+                   "pixels": head["pixels"], "parallelism": "single GPU",
                    "device": torch.cuda.get_device_name(dev) or torch.cuda.get_device_properties(dev).gcnArchName,
                    "hip": torch.version.hip},
-        "kernel_ms": {"mean": kernel_ms, "p50": float(np.percentile(per_launch_ms, 50)),
-                      "p90": float(np.percentile(per_launch_ms, 90)),
-                      "p99": float(np.percentile(per_launch_ms, 99)), "min": float(per_launch_ms.min())},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, shape) if w["noise"] == own_noise else None,
-                     "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": abytes,
-                     "launch_shape": list(shape),
-                     "stream_copy_gbs": copy_gbs, "frac_of_stream_copy": achieved / copy_gbs,
-                     "compulsory_floor_bytes": floor_bytes,
-                     "compulsory_floor_ms": floor_bytes / (HBM_PEAK_GBS * 1e9) * 1e3},
+        "kernel_ms": head["kernel_ms"],
+        "roofline": head["roofline"],
     }
-    if cpu is not None:
+    if base is not None:
+        cpu = dict(base[args.workload])
         cpu["gpu_speedup"] = result["value"] / cpu["value"]
+        cpu["cpu_model"] = cpu_model()
+        cpu["host_cpus"] = os.cpu_count()
+        cpu["workloads"] = base
         result["cpu_baseline"] = cpu
+    parity = {}
+    if args.workload in refs:
+        parity[args.workload] = parity_leg(ctx, args.workload, tensors, refs[args.workload])
     if not args.no_table2 and args.workload == "c2_1080p":
         result["table2"] = table2_leg(ctx, t, c, scene, slices=1)
         print("table2: " + ", ".join(f"{r['row']} {r['ms']:.3f} ms" for r in result["table2"]["rows"]),
@@ -636,11 +732,34 @@ def main():
         result["sectors128"] = sectors_leg(ctx, t, c, p)
         print(f"sectors: 32 {result['sectors128']['ms_32']:.3f} ms, 128 {result['sectors128']['ms_128']:.3f} ms",
               file=sys.stderr, flush=True)
+    del t, out, tensors
+    for n in names:
+        if n == args.workload:
+            continue
+        gb_n, cam_n, w_n, sc_n = loaded[n][:4]
+        if n == "c3_4k_fp16":
+            res, tens = frame_leg(ctx, n, gb_n, cam_n, w_n, sc_n, args.c3_steps, 2, w_n["own_noise"])
+            result["c3_4k_fp16"] = res
+        else:
+            from paper_2301_11376_amd import Camera, Params, NOISE_NAMES
+            tt = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in gb_n.items()}
+            cc = Camera(cam_n.width, cam_n.height, cam_n.fx, cam_n.fy, cam_n.cx, cam_n.cy,
+                        tuple(cam_n.view_to_world))
+            pp = Params(slices=w_n["slices"], steps=w_n["steps"], radius=w_n["radius"],
+                        thickness=w_n["thickness"], noise=NOISE_NAMES[w_n["noise"]], seed=w_n["seed"],
+                        ambient_sh=tuple(float(v) for v in sc_n.ambient_sh.reshape(-1)))
+            tens = (tt, cc, pp, None)
+        if n in refs:
+            parity[n] = parity_leg(ctx, n, tens, refs[n])
+        del tens
+        torch.cuda.empty_cache()
+    if parity:
+        result["parity"] = parity
     if not args.no_batch:
         result["batch"] = batch_leg(ctx, pool, autotune=not args.no_autotune)
         result["batch_small"] = batch_leg(ctx, pool, autotune=not args.no_autotune, kind="small")
     if not args.no_serve:
-        rates = [0.5, 0.7, 0.9] if args.serve_sweep else [0.7]
+        rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
         result["serving"] = serve_leg(ctx, pool, args.serve_requests, rates)
     ctx.close()
     print(json.dumps(result), flush=True)
