@@ -75,8 +75,23 @@ struct LaunchShape {
 };
 void set_launch(FrameArgs& A, LaunchShape L);
 
+// ---------------------------------------------------------------------------------------
+// index path of the gather kernels, from a work item to every byte offset they access.
+// Host and device: the kernels call these, and a host build of them checks on the CPU
+// that every access stays inside the frame's buffers.
+// ---------------------------------------------------------------------------------------
+#define SSVB_HD __host__ __device__ __forceinline__
+
+// Run of walk positions [first, first + count) queued for XCD k: the walk over nt tiles cut
+// into kXcds runs of ceil(nt / kXcds) (the last ones shorter or empty).
+SSVB_HD void xcd_run(uint32_t nt, int k, uint32_t& first, uint32_t& count) {
+    const uint32_t per = (nt + kXcds - 1) / kXcds;
+    first = (uint32_t)k * per;
+    count = first < nt ? min(per, nt - first) : 0u;
+}
+
 // Position `ord` of the strip walk over the frame's tiles -> tile (tx, ty).
-__device__ __forceinline__ void walk_tile(const FrameArgs& A, uint32_t ord, int& tx, int& ty) {
+SSVB_HD void walk_tile(const FrameArgs& A, uint32_t ord, int& tx, int& ty) {
     const uint32_t S = (uint32_t)A.strip, TY = (uint32_t)A.tiles_y;
     const uint32_t full = (uint32_t)A.tiles_x / S;
     if (ord < full * S * TY) {
@@ -90,6 +105,42 @@ __device__ __forceinline__ void walk_tile(const FrameArgs& A, uint32_t ord, int&
     }
 }
 
+// Pixel (x, y) of thread `thread` of a workgroup working on tile (tx, ty), and the thread's
+// lane `li` among the lp lanes that share the pixel.  The caller skips pixels with
+// x >= W or y >= H (the frame's last tile row and column may be partial).
+SSVB_HD void tile_pixel(const FrameArgs& A, int tx, int ty, int thread, int& x, int& y, int& li) {
+    const int lp = A.lp, px = thread / lp;
+    li = thread & (lp - 1);
+    x = (tx * A.tile_w + px % A.tile_w) * A.sub;
+    y = (ty * A.tile_h + px / A.tile_w) * A.sub;
+}
+
+// Offset of step j (0-based) from the pixel centre along the slice, in 1/16 pixel.
+// Uniform steps (Algorithm 1): (j + 1 + xi) steps of q, jit = (q xi8) >> 8.  Quadratic
+// steps (Section 4.3: denser near the pixel): the reach q (N_s + 1) times
+// ((j + 1 + xi) / (N_s + 1))^2, in integers: ((q a^2) >> 16) * floor(2^32 / (N_s + 1))
+// >> 32 with a = 256 (j + 1) + xi8 (q a^2 < 2^44, the second product < 2^50).
+template <bool QUAD>
+SSVB_HD int step_offset(const FrameArgs& A, int q, int jit, int xi8, int j) {
+    if (!QUAD) return q * (j + 1) + jit;
+    const uint64_t a = (uint64_t)(uint32_t)((j + 1) * 256 + xi8);
+    const uint64_t t = ((uint64_t)(uint32_t)q * (a * a)) >> 16;
+    return (int)((t * (uint64_t)A.ns_recip) >> 32);
+}
+
+// Lattice coordinate of a sample: c16 = (pixel << 16) + 2^15 (the pixel centre in 1/65536
+// px), so = the signed step offset in 1/16 px, d = the direction component in 1/4096;
+// arithmetic shift = floor.  |c16 + so d| < 2^31 for frames of at most kMaxDim pixels and
+// offsets below kLatticeCapPx pixels.
+SSVB_HD int lattice_coord(int c16, int so, int d) { return (c16 + so * d) >> 16; }
+
+// Byte offsets in the images (every image spans less than 4 GiB: 32-bit offsets).
+SSVB_HD uint32_t depth_off(const FrameArgs& A, int X, int Y) {
+    return (uint32_t)Y * (uint32_t)A.depth_pitch + (uint32_t)X * 4u;
+}
+SSVB_HD uint32_t image_off(int64_t pitch, int ch, bool f16, int x, int y) {
+    return (uint32_t)y * (uint32_t)pitch + (uint32_t)(x * ch) * (f16 ? 2u : 4u);
+}
 // ---------------------------------------------------------------------------------------
 // batched persistent path
 // ---------------------------------------------------------------------------------------
@@ -114,5 +165,14 @@ struct BatchDesc {
     uint32_t split[2][kXcds + 1];
     FrameArgs frames[kMaxBatch];
 };
+
+// Frame (index into plist[w]) of tile g of width w's list.  `j` is the caller's cursor: the
+// frame of its previous tile (0 at first); runs are claimed in increasing order, so the
+// search usually moves forward by a few frames.  Requires g < prefix[w][pn[w]].
+SSVB_HD int batch_frame(const BatchDesc& D, int w, uint32_t g, int j) {
+    if (g < D.prefix[w][j]) j = 0;
+    while (D.prefix[w][j + 1] <= g) ++j;
+    return j;
+}
 
 }  // namespace ssvb

@@ -66,23 +66,6 @@ __device__ __forceinline__ uint32_t jitter8(const FrameArgs& A, int x, int y, in
 // address space lets it use global (rather than flat) loads and stores.
 #define GMEM __attribute__((address_space(1)))
 
-// Offset of step j (0-based) from the pixel centre along the slice, in 1/16 pixel.
-// Uniform steps (Algorithm 1): (j + 1 + xi) steps of q, jit = (q xi8) >> 8.  Quadratic
-// steps (Section 4.3: denser near the pixel): the reach q (N_s + 1) times
-// ((j + 1 + xi) / (N_s + 1))^2, in integers: ((q a^2) >> 16) * floor(2^32 / (N_s + 1))
-// >> 32 with a = 256 (j + 1) + xi8 (q a^2 < 2^44, the second product < 2^50).
-template <bool QUAD>
-__device__ __forceinline__ int step_offset(const FrameArgs& A, int q, int jit, int xi8, int j) {
-    if (!QUAD) return q * (j + 1) + jit;
-    const uint64_t a = (uint64_t)(uint32_t)((j + 1) * 256 + xi8);
-    const uint64_t t = ((uint64_t)(uint32_t)q * (a * a)) >> 16;
-    return (int)((t * (uint64_t)A.ns_recip) >> 32);
-}
-
-__device__ __forceinline__ uint32_t depth_off(const FrameArgs& A, int X, int Y) {
-    return (uint32_t)Y * (uint32_t)A.depth_pitch + (uint32_t)X * 4u;
-}
-
 __device__ __forceinline__ float depth_load(const FrameArgs& A, uint32_t off) {
     return *(const GMEM float*)((const GMEM char*)A.depth + off);
 }
@@ -91,8 +74,7 @@ __device__ __forceinline__ float depth_load(const FrameArgs& A, uint32_t off) {
 template <int F>
 __device__ __forceinline__ float3 load3(const char* base, int64_t pitch, int ch, int f16, int x, int y) {
     const bool h = F < 0 ? f16 != 0 : F == 1;
-    const uint32_t off = (uint32_t)y * (uint32_t)pitch + (uint32_t)(x * ch) * (h ? 2u : 4u);
-    const GMEM char* b = (const GMEM char*)base + off;
+    const GMEM char* b = (const GMEM char*)base + image_off(pitch, ch, h, x, y);
     if (h) {
         const GMEM _Float16* p = (const GMEM _Float16*)b;
         return make_float3((float)p[0], (float)p[1], (float)p[2]);
@@ -490,8 +472,8 @@ __device__ __forceinline__ void gather_pixel_steps(const FrameArgs& A, ExactLds&
                 for (int j = 0; j < A.ns; ++j) {
                     const int o = step_offset<QUAD>(A, q, jit, xi8, j);
                     int32_t* d = dbg_i + ((((int64_t)i * 2 + side) * A.ns + j) * 2);
-                    d[0] = (x16 + s * o * D.x) >> 16;
-                    d[1] = (y16 + s * o * D.y) >> 16;
+                    d[0] = lattice_coord(x16, s * o, D.x);
+                    d[1] = lattice_coord(y16, s * o, D.y);
                 }
             }
             continue;
@@ -509,7 +491,7 @@ __device__ __forceinline__ void gather_pixel_steps(const FrameArgs& A, ExactLds&
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
                     const int so = side ? -o : o;
-                    const int X = (x16 + so * D.x) >> 16, Y = (y16 + so * D.y) >> 16;
+                    const int X = lattice_coord(x16, so, D.x), Y = lattice_coord(y16, so, D.y);
                     const bool ok = j0 + u < A.ns && (unsigned)X < (unsigned)A.W && (unsigned)Y < (unsigned)A.H &&
                                     (FAR || !(X == x && Y == y)) && geom;
                     zs[u][side] = depth_load(A, ok ? depth_off(A, X, Y) : own);
@@ -524,7 +506,7 @@ __device__ __forceinline__ void gather_pixel_steps(const FrameArgs& A, ExactLds&
                 for (int side = 0; side < 2; ++side) {
                     const int s = side ? -1 : 1;
                     const int so = side ? -o : o;
-                    const int X = (x16 + so * D.x) >> 16, Y = (y16 + so * D.y) >> 16;
+                    const int X = lattice_coord(x16, so, D.x), Y = lattice_coord(y16, so, D.y);
                     const bool ok = (unsigned)X < (unsigned)A.W && (unsigned)Y < (unsigned)A.H &&
                                     (FAR || !(X == x && Y == y)) && geom;
                     if (MODE == MODE_ENDPOINTS) {
@@ -659,24 +641,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     typedef const __attribute__((address_space(4))) FrameArgs* ConstArgs;  // scalar-loadable
     const ConstArgs args = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
     const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
-    const uint32_t per = (nt + kXcds - 1) / kXcds;
     const int home = hw_xcd();
     for (int qi = 0; qi < kXcds; ++qi) {
         const int k = (home + qi) & (kXcds - 1);
-        const uint32_t first = (uint32_t)k * per;
-        const uint32_t count = first < nt ? min(per, nt - first) : 0u;
+        uint32_t first, count;
+        xcd_run(nt, k, first, count);
         for (;;) {
             const uint32_t item = grab(&q[k], &s_item);
             if (item >= count) break;
             ConstArgs ap = args;
             asm volatile("" : "+s"(ap));
             const FrameArgs& F = *(const FrameArgs*)ap;
-            int tx, ty;
+            int tx, ty, x, y, li;
             walk_tile(F, first + item, tx, ty);
-            const int lp = F.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
-            const int x = (tx * F.tile_w + px % F.tile_w) * F.sub;
-            const int y = (ty * F.tile_h + px / F.tile_w) * F.sub;
-            if (x < F.W && y < F.H) gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT, NB>(F, L, x, y, li, lp, nullptr, nullptr);
+            tile_pixel(F, tx, ty, (int)threadIdx.x, x, y, li);
+            if ((unsigned)x < (unsigned)F.W && (unsigned)y < (unsigned)F.H) gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT, NB>(F, L, x, y, li, F.lp, nullptr, nullptr);
         }
     }
     if (threadIdx.x == 0) {
@@ -731,15 +710,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             const uint32_t item = grab(&queues[w * kXcds + k], &s_item);
             if (item >= count) break;
             const uint32_t g = first + item;
-            if (g < D->prefix[w][j]) j = 0;
-            while (D->prefix[w][j + 1] <= g) ++j;
+            j = batch_frame(*D, w, g, j);
             const FrameArgs& A = D->frames[D->plist[w][j]];
-            const int lp = A.lp, li = (int)threadIdx.x & (lp - 1), px = (int)threadIdx.x / lp;
-            int tx, ty;
+            int tx, ty, x, y, li;
             walk_tile(A, g - D->prefix[w][j], tx, ty);
-            const int x = (tx * A.tile_w + px % A.tile_w) * A.sub;
-            const int y = (ty * A.tile_h + px / A.tile_w) * A.sub;
-            if (x < A.W && y < A.H) gather_pixel<-1, MODE_COMPUTE, false, -1, NB>(A, L, x, y, li, lp, nullptr, nullptr);
+            tile_pixel(A, tx, ty, (int)threadIdx.x, x, y, li);
+            if ((unsigned)x < (unsigned)A.W && (unsigned)y < (unsigned)A.H) gather_pixel<-1, MODE_COMPUTE, false, -1, NB>(A, L, x, y, li, A.lp, nullptr, nullptr);
         }
     }
 }

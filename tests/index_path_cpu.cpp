@@ -1,0 +1,413 @@
+// Host emulation of the gather kernels' index path, for the CPU test suite.
+//
+// The kernels' index functions (XCD runs, tile walk, tile -> pixel, batch cursor, step
+// offsets, lattice, image offsets) are __host__ __device__ and are called here as written;
+// the frame constants come from the library's own fill_frame / build_batch (libssvb.so,
+// no GPU needed).  For every frame and launch shape below the emulation claims every work
+// item the way the persistent kernels do and checks, with bounds assertions (and ASan /
+// UBSan in the test build), that
+//   - every tile of every frame is claimed exactly once, and every computed pixel is
+//     reached by exactly lp lanes (each lane once) and lies inside the frame;
+//   - every byte the pixel's code reads (own depth, normal, radiance) or writes (AO, GI,
+//     ambient, slice masks) lies inside its buffer;
+//   - the integer lattice never overflows int32 at the frame's extreme pixels, longest
+//     offsets and every direction of the slice-direction table;
+//   - sampled texels pass the kernels' on-screen test only inside the frame.
+// It runs the library's strip walk and, with --interleaved, a reconstruction of the
+// interleaved strip walk (strips 0, 8, 16, ... then 1, 9, 17, ...) that was timed and then
+// withdrawn.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "ssvb_host.h"
+
+using namespace ssvb;
+
+static long g_checks = 0, g_fail = 0;
+
+#define CHECK(cond, ...)                                                     \
+    do {                                                                     \
+        ++g_checks;                                                          \
+        if (!(cond)) {                                                       \
+            if (++g_fail <= 20) {                                            \
+                printf("FAIL %s:%d: %s: ", __FILE__, __LINE__, #cond);       \
+                printf(__VA_ARGS__);                                         \
+                printf("\n");                                                \
+            }                                                                \
+        }                                                                    \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------
+// the withdrawn interleaved walk, reconstructed: strips (S tiles wide, the last one
+// possibly narrower) are visited in the order 0, 8, 16, ..., 1, 9, 17, ..., 7, 15, ...
+// ---------------------------------------------------------------------------------------
+static void walk_interleaved(const FrameArgs& A, uint32_t ord, int& tx, int& ty) {
+    const uint32_t S = (uint32_t)A.strip, TY = (uint32_t)A.tiles_y, TX = (uint32_t)A.tiles_x;
+    const uint32_t nstrips = (TX + S - 1) / S, full = TX / S, wl = TX - full * S;
+    uint32_t base = 0;
+    for (uint32_t g = 0; g < (uint32_t)kXcds && g < nstrips; ++g) {
+        const uint32_t in_group = (nstrips - g + kXcds - 1) / kXcds;  // strips g, g + 8, ...
+        uint32_t tiles = in_group * S * TY;
+        const bool has_partial = wl != 0 && (nstrips - 1) % kXcds == g;
+        if (has_partial) tiles -= (S - wl) * TY;
+        if (ord < base + tiles) {
+            const uint32_t r = ord - base, st_local = r / (S * TY), rr = r % (S * TY);
+            const uint32_t strip = g + (uint32_t)kXcds * st_local;
+            const uint32_t width = (wl != 0 && strip == nstrips - 1) ? wl : S;
+            ty = (int)(rr / width);
+            tx = (int)(strip * S + rr % width);
+            return;
+        }
+        base += tiles;
+    }
+    tx = ty = -1;  // past the end: reported by the caller
+}
+
+static bool g_interleaved = false;
+
+static void walk(const FrameArgs& A, uint32_t ord, int& tx, int& ty) {
+    if (g_interleaved) walk_interleaved(A, ord, tx, ty);
+    else walk_tile(A, ord, tx, ty);
+}
+
+// ---------------------------------------------------------------------------------------
+// buffers of one frame (byte sizes only: nothing is allocated)
+// ---------------------------------------------------------------------------------------
+struct Frame {
+    int W, H, nd, ns, nb, sub, dist, min_q4;
+    bool n16, r16;
+    int nch, rch;
+    int pad;  // extra bytes per row in every pitch
+    bool masks;
+    float radius;
+};
+
+struct Sizes {
+    int64_t depth, normal, radiance, ao, gi, amb, masks;
+};
+
+static int64_t span(int64_t pitch, int H, int64_t row) { return pitch * (H - 1) + row; }
+
+static Sizes sizes_of(const FrameArgs& A) {
+    Sizes s;
+    const int W = A.W, H = A.H;
+    s.depth = span(A.depth_pitch, H, (int64_t)W * 4);
+    s.normal = span(A.normal_pitch, H, (int64_t)W * A.normal_ch * (A.normal_f16 ? 2 : 4));
+    s.radiance = span(A.radiance_pitch, H, (int64_t)W * A.radiance_ch * (A.radiance_f16 ? 2 : 4));
+    s.ao = span(A.ao_pitch, H, (int64_t)W * 4);
+    s.gi = span(A.gi_pitch, H, (int64_t)W * 12);
+    s.amb = span(A.amb_pitch, H, (int64_t)W * 12);
+    s.masks = A.masks ? span(A.masks_pitch, H, (int64_t)W * A.nd * (A.nb / 32) * 4) : 0;
+    return s;
+}
+
+// The library's frame constants for a frame description (fake, distinct base addresses:
+// only offsets are checked).
+static void make_frame(const Frame& f, LaunchShape shape, bool forced, FrameArgs& A, ssvb_frame* out_frame = nullptr) {
+    static FrameTables tab;
+    tab.forced = forced;
+    tab.force = shape;
+    ssvb_camera cam{f.W, f.H, 0.5f * f.H, 0.5f * f.H, 0.5f * f.W, 0.5f * f.H, {1, 0, 0, 0, 1, 0, 0, 0, 1}};
+    ssvb_params p;
+    ssvb_default_params(&p);
+    p.slices = f.nd;
+    p.steps = f.ns;
+    p.sectors = f.nb;
+    p.radius = f.radius;
+    p.resolution = f.sub;
+    p.step_distribution = f.dist;
+    p.min_step_q4 = f.min_q4;
+    const int ne = f.n16 ? 2 : 4, re = f.r16 ? 2 : 4;
+    ssvb_image depth{(const void*)0x10000000, f.pad ? (int64_t)f.W * 4 + f.pad * 4 : 0, SSVB_F32, 1};
+    ssvb_image normal{(const void*)0x20000000, f.pad ? (int64_t)f.W * f.nch * ne + f.pad * ne : 0,
+                      f.n16 ? SSVB_F16 : SSVB_F32, f.nch};
+    ssvb_image radiance{(const void*)0x30000000, f.pad ? (int64_t)f.W * f.rch * re + f.pad * re : 0,
+                        f.r16 ? SSVB_F16 : SSVB_F32, f.rch};
+    ssvb_outputs o{(float*)0x40000000, (float*)0x50000000, (float*)0x60000000,
+                   f.masks ? (uint32_t*)0x70000000 : nullptr,
+                   f.pad ? (int64_t)f.W * 4 + f.pad * 4 : 0, f.pad ? (int64_t)f.W * 12 + f.pad * 4 : 0,
+                   f.pad ? (int64_t)f.W * 12 + f.pad * 4 : 0,
+                   f.pad ? (int64_t)f.W * f.nd * (f.nb / 32) * 4 + f.pad * 4 : 0};
+    CHECK(ssvb_validate(&depth, &normal, &radiance, &cam, &p, &o) == SSVB_OK, "frame %dx%d rejected: %s", f.W, f.H,
+          ssvb_last_error());
+    fill_frame(A, &tab, &depth, &normal, &radiance, &cam, &p, &o);
+    if (out_frame) *out_frame = ssvb_frame{depth, normal, radiance, cam, p, o};
+}
+
+// Everything one pixel's code touches, as the kernels compute it.
+static void check_pixel(const FrameArgs& A, const Sizes& S, int x, int y, int li) {
+    CHECK(x >= 0 && x < A.W && y >= 0 && y < A.H, "pixel (%d, %d) outside %dx%d", x, y, A.W, A.H);
+    CHECK(x % A.sub == 0 && y % A.sub == 0, "pixel (%d, %d) not on the computed grid (sub %d)", x, y, A.sub);
+    CHECK(li >= 0 && li < A.lp, "lane %d of %d", li, A.lp);
+    const int64_t d = depth_off(A, x, y);
+    CHECK(d >= 0 && d + 4 <= S.depth, "depth offset %lld of %lld", (long long)d, (long long)S.depth);
+    const int64_t n = image_off(A.normal_pitch, A.normal_ch, A.normal_f16, x, y);
+    CHECK(n + 3 * (A.normal_f16 ? 2 : 4) <= S.normal, "normal offset %lld of %lld", (long long)n, (long long)S.normal);
+    const int64_t r = image_off(A.radiance_pitch, A.radiance_ch, A.radiance_f16, x, y);
+    CHECK(r + 3 * (A.radiance_f16 ? 2 : 4) <= S.radiance, "radiance offset %lld", (long long)r);
+    // outputs, as the kernels address them (row pointer + element)
+    CHECK((int64_t)y * A.ao_pitch + (int64_t)x * 4 + 4 <= S.ao, "ao (%d, %d)", x, y);
+    CHECK((int64_t)y * A.gi_pitch + 12 * (int64_t)x + 12 <= S.gi, "gi (%d, %d)", x, y);
+    CHECK((int64_t)y * A.amb_pitch + 12 * (int64_t)x + 12 <= S.amb, "ambient (%d, %d)", x, y);
+    if (A.masks) {
+        const int words = A.nb / 32;
+        for (int i = li; i < A.nd; i += A.lp) {
+            const int64_t m = (int64_t)y * A.masks_pitch + 4 * ((int64_t)x * A.nd * words + (int64_t)i * words);
+            CHECK(m >= 0 && m + 4 * words <= S.masks, "masks (%d, %d) slice %d", x, y, i);
+        }
+    }
+}
+
+// One frame as gather_frame runs it: 8 XCD runs of the walk, 256 threads per tile.
+static void emulate_frame(const FrameArgs& A) {
+    const Sizes S = sizes_of(A);
+    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+    std::vector<uint8_t> tile_seen(nt, 0);
+    std::vector<uint8_t> lanes((size_t)A.W * A.H, 0);
+    uint32_t claimed = 0;
+    for (int k = 0; k < kXcds; ++k) {
+        uint32_t first, count;
+        xcd_run(nt, k, first, count);
+        CHECK(count == 0 || first + count <= nt, "run %d: [%u, %u) of %u", k, first, first + count, nt);
+        for (uint32_t item = 0; item < count; ++item) {
+            int tx = -1, ty = -1;
+            walk(A, first + item, tx, ty);
+            ++claimed;
+            CHECK(tx >= 0 && tx < A.tiles_x && ty >= 0 && ty < A.tiles_y, "walk %u -> tile (%d, %d) of %dx%d",
+                  first + item, tx, ty, A.tiles_x, A.tiles_y);
+            if (!(tx >= 0 && tx < A.tiles_x && ty >= 0 && ty < A.tiles_y)) continue;
+            CHECK(tile_seen[(size_t)ty * A.tiles_x + tx]++ == 0, "tile (%d, %d) claimed twice", tx, ty);
+            for (int t = 0; t < 256; ++t) {
+                int x, y, li;
+                tile_pixel(A, tx, ty, t, x, y, li);
+                if (x < A.W && y < A.H) {  // the kernels' guard
+                    check_pixel(A, S, x, y, li);
+                    if (x >= 0 && y >= 0) lanes[(size_t)y * A.W + x]++;
+                }
+            }
+        }
+    }
+    CHECK(claimed == nt, "%u of %u tiles claimed", claimed, nt);
+    long wrong = 0;
+    for (int y = 0; y < A.H; ++y)
+        for (int x = 0; x < A.W; ++x) {
+            const int want = (x % A.sub == 0 && y % A.sub == 0) ? A.lp : 0;
+            wrong += lanes[(size_t)y * A.W + x] != want;
+        }
+    CHECK(wrong == 0, "%ld pixels not reached by exactly lp lanes (%dx%d, tile %dx%d, strip %d, lp %d, sub %d)", wrong,
+          A.W, A.H, A.tile_w, A.tile_h, A.strip, A.lp, A.sub);
+}
+
+// The lattice at the frame's extreme pixels, for the longest offsets and every direction
+// of the table (computed as the library builds it): no int32 overflow, and a texel that
+// passes the on-screen test lies inside the frame.
+static void check_lattice(const FrameArgs& A) {
+    const int xs[2] = {0, ((A.W - 1) / A.sub) * A.sub}, ys[2] = {0, ((A.H - 1) / A.sub) * A.sub};
+    const int qs[2] = {A.q_min, A.q_max};
+    const int xis[2] = {0, 255};
+    for (int k = 0; k < kLutSize; k += 1) {
+        const double phi = M_PI * k / kLutSize;
+        const int dx = (int)floor(kLutOne * cos(phi) + 0.5), dy = (int)floor(kLutOne * sin(phi) + 0.5);
+        for (int q : qs)
+            for (int xi8 : xis)
+                for (int j : {0, A.ns - 1})
+                    for (int s : {1, -1}) {
+                        const int jit = (q * xi8) >> 8;
+                        const int o = A.step_dist == SSVB_STEPS_QUADRATIC ? step_offset<true>(A, q, jit, xi8, j)
+                                                                          : step_offset<false>(A, q, jit, xi8, j);
+                        CHECK(o >= 0 && o < 16 * (kLatticeCapPx + 1), "offset %d (q %d, j %d)", o, q, j);
+                        for (int x : xs)
+                            for (int y : ys) {
+                                const int64_t X64 = (((int64_t)x << 16) + 32768 + (int64_t)s * o * dx) >> 16;
+                                const int64_t Y64 = (((int64_t)y << 16) + 32768 + (int64_t)s * o * dy) >> 16;
+                                const int64_t sx = ((int64_t)x << 16) + 32768 + (int64_t)s * o * dx;
+                                const int64_t sy = ((int64_t)y << 16) + 32768 + (int64_t)s * o * dy;
+                                CHECK(sx >= INT32_MIN && sx <= INT32_MAX && sy >= INT32_MIN && sy <= INT32_MAX,
+                                      "lattice overflow at (%d, %d), offset %d, direction %d", x, y, o, k);
+                                const int X = lattice_coord((x << 16) + 32768, s * o, dx);
+                                const int Y = lattice_coord((y << 16) + 32768, s * o, dy);
+                                CHECK(X == X64 && Y == Y64, "lattice (%d, %d) != (%lld, %lld)", X, Y, (long long)X64,
+                                      (long long)Y64);
+                                if ((unsigned)X < (unsigned)A.W && (unsigned)Y < (unsigned)A.H) {
+                                    const int64_t d = depth_off(A, X, Y);
+                                    CHECK(d + 4 <= sizes_of(A).depth, "texel (%d, %d)", X, Y);
+                                }
+                            }
+                    }
+    }
+}
+
+// A batch as gather_batch runs it: per mask width, 8 runs of the packed tile list, claimed
+// by `wgs` workgroups in turn (each starting at its own XCD's run and keeping its frame
+// cursor across claims, as the kernel does).
+static void emulate_batch(const std::vector<Frame>& frames, LaunchShape shape, int wgs) {
+    std::vector<ssvb_frame> F(frames.size());
+    std::vector<FrameArgs> A(frames.size());
+    for (size_t i = 0; i < frames.size(); ++i) make_frame(frames[i], shape, true, A[i], &F[i]);
+    static BatchDesc D;
+    memset(&D, 0, sizeof D);
+    // the descriptor as the library builds it for a context with this (forced) launch shape
+    static FrameTables tab;
+    tab.forced = true;
+    tab.force = shape;
+    build_batch(&tab, &D, F.data(), (int)F.size());
+    for (int w = 0; w < 2; ++w) {
+        const int pn = D.pn[w];
+        const uint32_t total = pn ? D.prefix[w][pn] : 0;
+        CHECK(D.split[w][0] == 0 && D.split[w][kXcds] == total, "width %d: runs [%u, %u) of %u tiles", w,
+              D.split[w][0], D.split[w][kXcds], total);
+        for (int k = 0; k < kXcds; ++k) CHECK(D.split[w][k] <= D.split[w][k + 1], "width %d run %d reversed", w, k);
+        std::vector<std::vector<uint8_t>> seen(pn);
+        std::vector<Sizes> sz(pn);
+        for (int j = 0; j < pn; ++j) {
+            const FrameArgs& f = D.frames[D.plist[w][j]];
+            seen[j].assign((size_t)f.tiles_x * f.tiles_y, 0);
+            sz[j] = sizes_of(f);
+            CHECK(D.prefix[w][j + 1] - D.prefix[w][j] == (uint32_t)f.tiles_x * f.tiles_y, "frame %d tiles", j);
+        }
+        uint32_t head[kXcds] = {};
+        std::vector<int> qi(wgs, 0), cursor(wgs, 0);
+        std::vector<bool> done(wgs, false);
+        int active = wgs;
+        while (active > 0) {
+            for (int g = 0; g < wgs; ++g) {
+                if (done[g]) continue;
+                const int home = g % kXcds;
+                // the next claim of workgroup g: its current run, else the following ones
+                for (;;) {
+                    if (qi[g] == kXcds) {
+                        done[g] = true;
+                        --active;
+                        break;
+                    }
+                    const int k = (home + qi[g]) & (kXcds - 1);
+                    const uint32_t first = D.split[w][k], count = D.split[w][k + 1] - first;
+                    const uint32_t item = head[k]++;
+                    if (item >= count) {
+                        ++qi[g];
+                        continue;
+                    }
+                    const uint32_t gt = first + item;
+                    CHECK(gt < total, "tile %u of %u", gt, total);
+                    const int j = batch_frame(D, w, gt, cursor[g]);
+                    cursor[g] = j;
+                    CHECK(j >= 0 && j < pn && D.prefix[w][j] <= gt && gt < D.prefix[w][j + 1],
+                          "cursor: tile %u -> frame %d", gt, j);
+                    const FrameArgs& f = D.frames[D.plist[w][j]];
+                    int tx, ty;
+                    walk(f, gt - D.prefix[w][j], tx, ty);
+                    CHECK(tx >= 0 && tx < f.tiles_x && ty >= 0 && ty < f.tiles_y, "batch walk -> (%d, %d)", tx, ty);
+                    if (tx >= 0 && tx < f.tiles_x && ty >= 0 && ty < f.tiles_y) {
+                        CHECK(seen[j][(size_t)ty * f.tiles_x + tx]++ == 0, "batch tile claimed twice");
+                        for (int t = 0; t < 256; ++t) {
+                            int x, y, li;
+                            tile_pixel(f, tx, ty, t, x, y, li);
+                            if (x < f.W && y < f.H) check_pixel(f, sz[j], x, y, li);
+                        }
+                    }
+                    break;  // one claim per turn
+                }
+            }
+        }
+        for (int j = 0; j < pn; ++j) {
+            long miss = 0;
+            for (uint8_t c : seen[j]) miss += c != 1;
+            CHECK(miss == 0, "width %d frame %d: %ld tiles not claimed exactly once", w, j, miss);
+        }
+    }
+}
+
+int main(int argc, char** argv) {
+    bool quick = false;
+    for (int i = 1; i < argc; ++i) {
+        if (!strcmp(argv[i], "--interleaved")) g_interleaved = true;
+        if (!strcmp(argv[i], "--quick")) quick = true;
+    }
+    // the launch shapes of the autotuner (tile w, h, lanes) x strips, and the default
+    static const int kTiles[][3] = {{32, 8, 1}, {16, 16, 1}, {64, 4, 1}, {8, 32, 1}, {16, 8, 2}, {8, 16, 2},
+                                    {32, 4, 2}, {8, 8, 4},   {16, 4, 4}, {8, 4, 8},  {4, 8, 8}};
+    static const int kStrips[] = {1, 2, 3, 4, 8};
+    // frames of the GPU suite: workloads, tests, batch and serving mixes, ragged and extreme
+    // sizes (W, H, slices, steps, sectors, resolution, distribution, fp16, channels, pad, masks)
+    struct Spec {
+        int W, H, nd, ns, nb, sub, dist, f16, ch, pad, masks;
+    };
+    std::vector<Spec> specs = {
+        {128, 128, 2, 8, 32, 1, 0, 0, 3, 0, 1},   {64, 48, 4, 8, 32, 1, 0, 0, 3, 0, 1},
+        {67, 45, 3, 5, 32, 1, 0, 0, 3, 0, 1},     {1, 1, 3, 5, 32, 1, 0, 0, 3, 0, 1},
+        {1, 37, 3, 5, 32, 1, 0, 1, 4, 0, 1},      {37, 1, 3, 5, 32, 1, 0, 0, 4, 0, 1},
+        {129, 3, 3, 5, 128, 1, 0, 0, 3, 0, 1},    {200, 113, 4, 16, 32, 1, 0, 1, 3, 3, 0},
+        {33, 91, 8, 3, 32, 1, 0, 0, 4, 0, 1},     {96, 64, 5, 7, 32, 1, 0, 0, 3, 5, 1},
+        {160, 90, 7, 9, 32, 1, 1, 1, 3, 0, 0},    {39, 23, 64, 2, 128, 1, 0, 0, 3, 0, 1},
+        {41, 31, 3, 1024, 32, 1, 1, 0, 3, 0, 1},  {65, 33, 4, 16, 32, 2, 0, 0, 3, 0, 0},
+        {255, 143, 4, 16, 128, 2, 1, 1, 4, 7, 0}, {256, 144, 2, 8, 32, 1, 0, 0, 3, 0, 0},
+        {320, 180, 4, 16, 32, 1, 0, 0, 3, 0, 0},  {480, 270, 2, 16, 32, 1, 0, 0, 3, 0, 0},
+        {640, 360, 4, 8, 32, 1, 0, 0, 3, 0, 0},   {960, 540, 8, 32, 32, 1, 0, 1, 3, 0, 0},
+        {1280, 720, 2, 8, 32, 1, 0, 0, 3, 0, 0},  {1920, 1080, 4, 16, 32, 1, 0, 0, 3, 0, 1},
+        {1920, 1080, 4, 16, 128, 2, 1, 0, 3, 0, 0}, {2560, 1440, 8, 32, 32, 1, 0, 0, 3, 0, 0},
+        {3840, 2160, 8, 32, 32, 1, 0, 1, 3, 0, 1}, {16384, 1, 3, 2, 32, 1, 0, 0, 3, 0, 1},
+        {1, 16384, 3, 2, 32, 1, 0, 0, 3, 0, 1},   {3, 4099, 3, 2, 32, 1, 0, 0, 3, 0, 1},
+    };
+    auto frame_of = [](const Spec& s, bool masks) {
+        Frame f;
+        f.W = s.W, f.H = s.H, f.nd = s.nd, f.ns = s.ns, f.nb = s.nb, f.sub = s.sub, f.dist = s.dist;
+        f.min_q4 = s.ns >= 1024 ? 1 : 16;
+        f.n16 = f.r16 = s.f16 != 0;
+        f.nch = f.rch = s.ch;
+        f.pad = s.pad;
+        f.masks = masks && s.sub == 1;
+        f.radius = (s.W == 1 || s.H == 1 || s.W == 3) ? 1e9f : 3.0f;  // the extreme-size tests' reach
+        return f;
+    };
+    long frames_done = 0;
+    for (const Spec& s : specs) {
+        const Frame f = frame_of(s, s.masks != 0);
+        const bool big = (int64_t)s.W * s.H > 2000000;
+        for (const auto& tl : kTiles) {
+            for (int st : kStrips) {
+                if ((big || quick) && !(st == 1 || st == 2 || st == 4)) continue;
+                if ((big || quick) && !(tl[2] == 1 || (tl[0] == 16 && tl[1] == 8))) continue;
+                FrameArgs A;
+                make_frame(f, LaunchShape{tl[0], tl[1], st, tl[2]}, true, A);
+                emulate_frame(A);
+                ++frames_done;
+            }
+        }
+        // the library's default shape (no forced shape)
+        FrameArgs A;
+        make_frame(f, LaunchShape{32, 8, 4, 1}, false, A);
+        emulate_frame(A);
+        check_lattice(A);
+        ++frames_done;
+    }
+    // batches: the mixed small frames of the GPU batch tests, with every launch shape
+    std::vector<Frame> batch;
+    for (const Spec& s : specs) {
+        if ((int64_t)s.W * s.H > 400000) continue;
+        batch.push_back(frame_of(s, false));
+    }
+    for (int i = 0; i < 40; ++i) {  // one-tile frames up to a few tiles, as the packed-batch tests draw
+        const Spec s{1 + (i * 7) % 39, 1 + (i * 5) % 23, 2 + i % 3, 8, (i % 4 == 3) ? 128 : 32, 1 + (i % 5 == 4), 0,
+                     i % 2, 3, 0, 0};
+        batch.push_back(frame_of(s, false));
+    }
+    if (batch.size() > (size_t)kMaxBatch) batch.resize(kMaxBatch);
+    long batches = 0;
+    for (const auto& tl : kTiles) {
+        for (int st : kStrips) {
+            if (quick && st != 4) continue;
+            for (int wgs : {1, 7, 1024}) {
+                emulate_batch(batch, LaunchShape{tl[0], tl[1], st, tl[2]}, wgs);
+                ++batches;
+            }
+        }
+    }
+    printf("%s walk: %ld frame launches, %ld batches, %ld checks, %ld failed\n",
+           g_interleaved ? "interleaved" : "strip", frames_done, batches, g_checks, g_fail);
+    return g_fail != 0;
+}

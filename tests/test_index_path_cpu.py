@@ -1,0 +1,59 @@
+"""CPU test of the gather kernels' complete index path (index_path_cpu.cpp): the kernels'
+own __host__ __device__ index functions and the library's own frame constants (fill_frame,
+build_batch from libssvb.so), built with hipcc for the host under ASan and UBSan, over
+every frame shape and launch shape the GPU suite uses (autotuner tiles, lanes per pixel
+1-8, strips 1-8, full and half resolution, both mask widths, pitched buffers, 16384-pixel
+frames): every tile is claimed once, every computed pixel reached by each of its lanes
+once, every byte read or written inside its buffer, no int32 overflow in the lattice.
+The same checks run on a reconstruction of the withdrawn interleaved strip walk."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "tests", "index_path_cpu.cpp")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.fixture(scope="module")
+def emulator():
+    if not os.path.exists(HIPCC) or shutil.which("ld") is None:
+        pytest.skip("needs hipcc")
+    from paper_2301_11376_amd import binding, build_lib
+    if not os.path.exists(binding.LIB_PATH):
+        build_lib.build()
+    libdir = os.path.dirname(binding.LIB_PATH)
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "index_path")
+        # host-only build; the sanitizers apply to the host code
+        cmd = [HIPCC, "-x", "hip", "--cuda-host-only", "-O1", "-g", "-std=c++17",
+               "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2301_11376_amd", "csrc"),
+               "-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=all",
+               SRC, "-L", libdir, "-lssvb", f"-Wl,-rpath,{libdir}", "-o", exe]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        assert res.returncode == 0, res.stdout + res.stderr
+        yield exe
+
+
+def run(exe, *args):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    res = subprocess.run([exe, *args], capture_output=True, text=True, timeout=900, env=env)
+    print(res.stdout)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert " 0 failed" in res.stdout
+    return res.stdout
+
+
+def test_strip_walk_index_path(emulator):
+    """The library's walk, every launch shape of the autotuner on every frame up to 1080p
+    (four shapes on the 4K frame)."""
+    run(emulator)
+
+
+def test_interleaved_walk_reconstruction_index_path(emulator):
+    """The reconstructed interleaved walk (strips 0, 8, 16, ... then 1, 9, ...) with the
+    strip widths 1, 2 and 4 and the lp = 1 tiles: in bounds and a bijection as well."""
+    run(emulator, "--interleaved", "--quick")
