@@ -230,13 +230,59 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
  * channel, next = direct + gain * albedo * gi.  direct and albedo: images of width x height
  * (F32 or F16, 3 or 4 channels); gi: FP32 [height][width][3] as ssvb_compute writes it,
  * row pitch gi_pitch_bytes (0 = dense); next: an image of the same channel count as
- * direct (F32 or F16; F16 rounds to nearest even), its fourth channel, if any, copied
- * from direct.  next may be direct itself (each element is read before it is written).
+ * direct, or of 3 channels (F32 or F16; F16 rounds to nearest even); a fourth channel of
+ * next is copied from direct.  next may be direct itself (each element is read before it is written).
  * gain finite and >= 0 (>= 1 lets repeated bounces grow without bound).  Asynchronous
  * on hip_stream; validated before anything is launched. */
 ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, const ssvb_image* direct,
                                const ssvb_image* albedo, const float* gi, int64_t gi_pitch_bytes, float gain,
                                const ssvb_image* next, void* hip_stream);
+
+/* A sequence of frames of one size with multi-bounce feedback and temporal jitter.
+ * Section 4.3 injects a frame's indirect light into the light buffer the next frame uses;
+ * Section 3.1 distributes the integral over time as well as space, and Section 4.1 times
+ * one slice per pixel turned from frame to frame.  The sequence owns, in device memory
+ * allocated here (the only allocation; steps allocate nothing), its light buffer
+ * (width x height x 3 of light_dtype, F32 or F16), the FP32 GI of the last frame and a
+ * zeroed FP32 GI image that stands for the frame before frame 0 (width x height x 3 each):
+ * 36 (F32 light) or 30 (F16) bytes per pixel.  The frame counter starts at 0.  Errors:
+ * SSVB_ERR_INVALID_ARG (size outside [1, 16384], dtype), SSVB_ERR_OUT_OF_MEMORY,
+ * SSVB_ERR_DEVICE. */
+typedef struct ssvb_sequence ssvb_sequence;
+ssvb_status ssvb_sequence_create(ssvb_ctx* ctx, int32_t width, int32_t height, ssvb_dtype light_dtype,
+                                 ssvb_sequence** out);
+
+/* Frame n of the sequence (n = the frame counter), asynchronous on hip_stream:
+ *   1. light = direct + gain * albedo * GI of frame n - 1 (nothing before frame 0), written
+ *      to the sequence's light buffer as ssvb_inject_bounce writes it (FP32 arithmetic);
+ *   2. the gather of ssvb_compute on (depth, normal, light) with params->seed + n (mod
+ *      2^32), so the slice rotations and step jitters change from frame to frame;
+ *   3. out receives AO, GI, ambient (and the slice masks if out->masks is set) as
+ *      ssvb_compute writes them, and the GI is copied to the sequence for frame n + 1.
+ * direct and albedo: images of the sequence's size (F32 or F16, 3 or 4 channels); depth,
+ * normal, camera, params and out as for ssvb_compute, the camera of the sequence's size.
+ * gain finite and >= 0.  Everything is validated before anything is launched; the frame
+ * counter advances only when the step was enqueued.  Steps of one sequence must be
+ * ordered on the device (one stream, or the caller orders them); steps of different
+ * sequences are independent. */
+ssvb_status ssvb_sequence_step(ssvb_sequence* seq, const ssvb_image* depth, const ssvb_image* normal,
+                               const ssvb_image* direct, const ssvb_image* albedo, const ssvb_camera* camera,
+                               const ssvb_params* params, float gain, const ssvb_outputs* out, void* hip_stream);
+
+/* Set the frame counter to 0: the next step has no feedback and uses params->seed. */
+ssvb_status ssvb_sequence_reset(ssvb_sequence* seq);
+
+/* The frame counter (frames stepped since creation or the last reset). */
+ssvb_status ssvb_sequence_frame(ssvb_sequence* seq, int64_t* frame);
+
+/* Copy the light buffer of the last step (width x height x 3 of the light type, dense
+ * rows) to `dst` (device or host memory, rows of dst_pitch_bytes, 0 = dense), ordered on
+ * hip_stream after that step. */
+ssvb_status ssvb_sequence_copy_light(ssvb_sequence* seq, void* dst, int64_t dst_pitch_bytes, void* hip_stream);
+
+/* Free the sequence's buffers (after its work on the device has finished).  NULL is
+ * ignored. */
+ssvb_status ssvb_sequence_destroy(ssvb_sequence* seq);
 
 /* Parameters of ssvb_denoise.
  *  passes        1..3: pass i averages over 5 x 5 taps 2^i cells apart

@@ -26,6 +26,7 @@ from .ssvb_oracle import (  # noqa: F401
     compute,
     bilateral_upsample,
     inject_bounce,
+    bounce_sequence,
     denoise,
     DENOISE_KERNEL,
     UPSAMPLE_SIGMA,

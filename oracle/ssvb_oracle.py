@@ -74,6 +74,13 @@ listed again in the design notes):
       centre's own weight is h_0^2; taps off the image or on background are left out and
       the weights renormalised; a background pixel keeps its input.  At half resolution
       the R22 upsampler then refills the pixels with an odd coordinate.
+  R25 frame sequences (Section 4.3: multi-bounce through the light buffer of the next
+      frame; Section 3.1: the integral is distributed over time as well as space; Section
+      4.1: one slice per pixel jittered over frames): frame n's light = direct_n + g
+      albedo_n * GI_{n-1} (no feedback before frame 0), stored in the light buffer's
+      precision (FP32 or FP16), and frame n draws its noise with seed s0 + n (mod 2^32).
+      Temporal accumulation of the outputs (which needs reprojection for a moving camera)
+      is left to the caller.
 """
 from __future__ import annotations
 
@@ -278,6 +285,31 @@ def inject_bounce(direct, albedo, gi, gain):
     d = np.asarray(direct)[..., :3].astype(np.float64)
     a = np.asarray(albedo)[..., :3].astype(np.float64)
     return d + float(np.float32(gain)) * a * np.asarray(gi, dtype=np.float64)
+
+
+def bounce_sequence(frames, cam, prm, gain, light_dtype=np.float32, **compute_kw):
+    """A sequence of frames with multi-bounce feedback and temporal jitter (reading R25).
+
+    Frame n's light buffer is its direct light plus gain x albedo x the GI of frame n - 1
+    (Section 4.3: the indirect light is injected into the light buffer the next frame
+    uses; nothing before frame 0), stored as ``light_dtype``; frame n is gathered on that
+    light with the noise of seed prm.seed + n, so the slices turn from frame to frame
+    (Section 3.1 distributes the integral over time; the timings of Section 4.1 take one
+    slice per pixel, jittered over frames).  ``frames``: a sequence of dicts with
+    ``depth``, ``normal``, ``direct`` and ``albedo`` (one camera for all).  Returns one
+    ``compute`` result per frame (``compute_kw`` passed on, e.g. return_masks), each with
+    the frame's ``light`` added."""
+    from dataclasses import replace
+    out, gi = [], None
+    for n, f in enumerate(frames):
+        H, W = np.asarray(f["depth"]).shape
+        prev = gi if gi is not None else np.zeros((H, W, 3))
+        light = inject_bounce(f["direct"], f["albedo"], prev, gain).astype(light_dtype)
+        r = compute(f["depth"], f["normal"], light, cam, replace(prm, seed=(prm.seed + n) % (1 << 32)), **compute_kw)
+        r["light"] = light
+        gi = r["gi"]
+        out.append(r)
+    return out
 
 
 UPSAMPLE_SIGMA = 0.05    # relative depth scale of the upsampling weights (R22)

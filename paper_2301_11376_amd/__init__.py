@@ -10,6 +10,7 @@ from .binding import (  # noqa: F401
     FrameArray,
     Params,
     SSVBError,
+    Sequence,
     Server,
     HIT_ROUND,
     HIT_PSEUDOCODE,

@@ -31,7 +31,8 @@ EXPORTED = [
     "ssvb_autotune", "ssvb_debug_lattice", "ssvb_debug_endpoints", "ssvb_debug_direction_table",
     "ssvb_debug_noise_constants", "ssvb_server_create", "ssvb_server_submit", "ssvb_server_poll",
     "ssvb_server_wait", "ssvb_server_release", "ssvb_server_stats", "ssvb_server_destroy", "ssvb_inject_bounce",
-    "ssvb_default_denoise_params", "ssvb_denoise",
+    "ssvb_default_denoise_params", "ssvb_denoise", "ssvb_sequence_create", "ssvb_sequence_step",
+    "ssvb_sequence_reset", "ssvb_sequence_frame", "ssvb_sequence_copy_light", "ssvb_sequence_destroy",
 ]
 
 
@@ -145,6 +146,19 @@ def lib() -> ctypes.CDLL:
     L.ssvb_denoise.restype = I
     L.ssvb_denoise.argtypes = [V, P(ssvb_image), P(ssvb_image), P(ssvb_camera), P(ssvb_outputs), P(ssvb_outputs),
                                P(ssvb_outputs), P(ssvb_denoise_params), V]
+    L.ssvb_sequence_create.restype = I
+    L.ssvb_sequence_create.argtypes = [V, I, I, I, P(V)]
+    L.ssvb_sequence_step.restype = I
+    L.ssvb_sequence_step.argtypes = [V, P(ssvb_image), P(ssvb_image), P(ssvb_image), P(ssvb_image), P(ssvb_camera),
+                                     P(ssvb_params), ctypes.c_float, P(ssvb_outputs), V]
+    L.ssvb_sequence_reset.restype = I
+    L.ssvb_sequence_reset.argtypes = [V]
+    L.ssvb_sequence_frame.restype = I
+    L.ssvb_sequence_frame.argtypes = [V, P(ctypes.c_int64)]
+    L.ssvb_sequence_copy_light.restype = I
+    L.ssvb_sequence_copy_light.argtypes = [V, V, ctypes.c_int64, V]
+    L.ssvb_sequence_destroy.restype = I
+    L.ssvb_sequence_destroy.argtypes = [V]
     U64, D = ctypes.c_uint64, ctypes.c_double
     L.ssvb_server_create.restype = I
     L.ssvb_server_create.argtypes = [V, U64, I, P(V)]
@@ -501,6 +515,72 @@ class Context:
         buf = (ctypes.c_int32 * 8192)()
         check(lib().ssvb_debug_direction_table(self.handle, buf), "ssvb_debug_direction_table")
         return [(buf[2 * k], buf[2 * k + 1]) for k in range(4096)]
+
+
+class Sequence:
+    """An ssvb_sequence: frames of one size with multi-bounce feedback through a light
+    buffer the sequence owns, and the noise seed advanced per frame (temporal jitter)."""
+
+    def __init__(self, ctx: Context, width: int, height: int, light_dtype: str = "f32"):
+        h = ctypes.c_void_p()
+        dt = {"f32": F32, "f16": F16}[light_dtype]
+        check(lib().ssvb_sequence_create(ctx.handle, int(width), int(height), dt, ctypes.byref(h)),
+              "ssvb_sequence_create")
+        self.handle = h
+        self.ctx = ctx
+        self.width, self.height, self.light_dtype = int(width), int(height), light_dtype
+
+    def step(self, depth, normal, direct, albedo, camera: Camera, params: Params, gain: float, out=None,
+             masks=False, stream=None):
+        """Frame n of the sequence: light = direct + gain * albedo * GI of frame n - 1, then
+        the gather on that light with seed params.seed + n; returns the outputs dict."""
+        H, W = camera.height, camera.width
+        ctx = self.ctx
+        check_tensor(depth, "depth", H, W, None, "f32", ctx.device)
+        check_tensor(normal, "normal", H, W, (3, 4), "image", ctx.device)
+        check_tensor(direct, "direct", H, W, (3, 4), "image", ctx.device)
+        check_tensor(albedo, "albedo", H, W, (3, 4), "image", ctx.device)
+        if out is None:
+            out = Context.alloc_outputs(H, W, params.slices, depth.device, masks=masks, sectors=params.sectors)
+        check_outputs(out, H, W, ctx.device, masks_words=params.slices * (params.sectors // 32))
+        o = Context.outputs_of(out)
+        d, n, dl, al = image_of(depth), image_of(normal), image_of(direct), image_of(albedo)
+        c, p = camera.to_c(), params.to_c()
+        check(lib().ssvb_sequence_step(self.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(dl),
+                                       ctypes.byref(al), ctypes.byref(c), ctypes.byref(p), float(gain),
+                                       ctypes.byref(o), _stream_ptr(stream)), "ssvb_sequence_step")
+        return out
+
+    def reset(self):
+        check(lib().ssvb_sequence_reset(self.handle), "ssvb_sequence_reset")
+
+    @property
+    def frame(self) -> int:
+        v = ctypes.c_int64()
+        check(lib().ssvb_sequence_frame(self.handle, ctypes.byref(v)), "ssvb_sequence_frame")
+        return v.value
+
+    def light(self, stream=None):
+        """A copy of the light buffer of the last step ([H, W, 3] tensor of the light type)."""
+        import torch
+        t = torch.empty((self.height, self.width, 3),
+                        dtype=torch.float16 if self.light_dtype == "f16" else torch.float32,
+                        device=f"cuda:{self.ctx.device}")
+        check(lib().ssvb_sequence_copy_light(self.handle, ctypes.c_void_p(t.data_ptr()), 0, _stream_ptr(stream)),
+              "ssvb_sequence_copy_light")
+        return t
+
+    def close(self):
+        if getattr(self, "handle", None):
+            st = lib().ssvb_sequence_destroy(self.handle)
+            self.handle = None
+            check(st, "ssvb_sequence_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libssvb.so")
 
-SOURCES = ["ssvb_kernels.hip", "ssvb_denoise.hip", "ssvb_api.cpp", "ssvb_server.cpp"]
+SOURCES = ["ssvb_kernels.hip", "ssvb_denoise.hip", "ssvb_api.cpp", "ssvb_server.cpp", "ssvb_sequence.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions (v_pk_*_f32) anywhere in device code

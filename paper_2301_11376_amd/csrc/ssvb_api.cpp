@@ -770,10 +770,12 @@ ssvb_status ssvb_autotune(ssvb_ctx* ctx, const ssvb_frame* frame, void* hip_stre
     return SSVB_OK;
 }
 
-ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, const ssvb_image* direct,
-                               const ssvb_image* albedo, const float* gi, int64_t gi_pitch_bytes, float gain,
-                               const ssvb_image* next, void* hip_stream) {
-    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+}  // extern "C"
+
+namespace ssvb {
+// The checks of ssvb_inject_bounce, before anything is launched.
+ssvb_status validate_bounce(int32_t width, int32_t height, const ssvb_image* direct, const ssvb_image* albedo,
+                            const float* gi, int64_t gi_pitch_bytes, float gain, const ssvb_image* next) {
     if (width < 0 || height < 0 || width > kMaxDim || height > kMaxDim)
         return fail(SSVB_ERR_INVALID_ARG, "image %dx%d outside [0, %d]", width, height, kMaxDim);
     if (!(finite(gain) && gain >= 0.0f)) return fail(SSVB_ERR_INVALID_ARG, "gain must be finite and >= 0");
@@ -781,11 +783,24 @@ ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, con
     if ((s = check_image(direct, "direct", width, height, false))) return s;
     if ((s = check_image(albedo, "albedo", width, height, false))) return s;
     if ((s = check_image(next, "next", width, height, false))) return s;
-    if (next->channels != direct->channels)
+    if (next->channels != direct->channels && !(next->channels == 3 && direct->channels == 4))
         return fail(SSVB_ERR_INVALID_ARG, "next has %d channels, direct %d", next->channels, direct->channels);
     if ((int64_t)width * height == 0) return SSVB_OK;
     if (!gi || (uintptr_t)gi % 4) return fail(SSVB_ERR_INVALID_ARG, "gi: NULL or misaligned");
     if ((s = check_out_pitch(gi_pitch_bytes, (int64_t)width * 12, "gi"))) return s;
+    return SSVB_OK;
+}
+}  // namespace ssvb
+
+extern "C" {
+
+ssvb_status ssvb_inject_bounce(ssvb_ctx* ctx, int32_t width, int32_t height, const ssvb_image* direct,
+                               const ssvb_image* albedo, const float* gi, int64_t gi_pitch_bytes, float gain,
+                               const ssvb_image* next, void* hip_stream) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    ssvb_status s = validate_bounce(width, height, direct, albedo, gi, gi_pitch_bytes, gain, next);
+    if (s) return s;
+    if ((int64_t)width * height == 0) return SSVB_OK;
     auto pitch = [&](const ssvb_image* im) {
         return im->pitch_bytes ? im->pitch_bytes : (int64_t)width * im->channels * elem_size(im->dtype);
     };

@@ -74,6 +74,10 @@ hipError_t enqueue_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint3
                          int kinds, hipStream_t s);
 int batch_blocks_per_cu(int sectors);
 
+// The argument checks of ssvb_inject_bounce (nothing launched).
+ssvb_status validate_bounce(int32_t width, int32_t height, const ssvb_image* direct, const ssvb_image* albedo,
+                            const float* gi, int64_t gi_pitch_bytes, float gain, const ssvb_image* next);
+
 // The device and the frame tables of a context.
 int ctx_device(const ssvb_ctx* ctx);
 const FrameTables* ctx_tables(const ssvb_ctx* ctx);

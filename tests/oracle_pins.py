@@ -997,6 +997,63 @@ def pin_multi_bounce(O):
     assert inc[-1] < 1e-6 * sums[-1]
 
 
+def pin_bounce_sequence(O):
+    """Frame sequences (Section 4.3 multi-bounce, temporal jitter; reading R25).
+    (1) Gain 0: frame n is the single-frame gather of the direct light with seed s0 + n,
+    and the frames differ.  (2) The integral distributed over time: one randomly turned
+    slice per frame at the hinge of a 45-degree wall, averaged over 256 frames, reaches the
+    wall's analytic occluded fraction, like 64 slices in one frame.  (3) Feedback: frame
+    n's light is direct + gain x albedo x GI of frame n - 1 (then rounded to the light
+    buffer's FP16 when asked), and on the lit crease with FIXED noise the GI grows frame
+    after frame to a fixed point (in FP16 storage once the increments fall below its
+    resolution)."""
+    gb, cam, sc = tiny_scene()
+    oc = ocam(O, cam)
+    H, W = gb["depth"].shape
+    albedo = np.full((H, W, 3), 0.6, np.float32)
+    frames = [dict(depth=gb["depth"], normal=gb["normal"], direct=gb["radiance"], albedo=albedo)] * 3
+    prm = O.Params(slices=2, steps=6, radius=1.5, thickness=0.4, noise=O.NOISE_HASH, seed=7,
+                   ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    seq = O.bounce_sequence(frames, oc, prm, 0.0)
+    for n, r in enumerate(seq):
+        from dataclasses import replace
+        one = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, replace(prm, seed=7 + n))
+        for k in ("ao", "gi", "ambient"):
+            assert np.array_equal(r[k], one[k]), (n, k)
+    assert not np.array_equal(seq[0]["ao"], seq[1]["ao"]), "the slices must turn from frame to frame"
+    # (2) temporal distribution of the integral
+    alpha = math.radians(45.0)
+    cgb, ccam = _crease(alpha, 41, 4.0)
+    c = 20
+    ref = wall_ao_analytic(alpha)
+    cframes = [dict(depth=cgb["depth"], normal=cgb["normal"], direct=cgb["radiance"],
+                    albedo=np.full(cgb["radiance"].shape, 0.5, np.float32))] * 256
+    for seed in (5, 1000):
+        cprm = O.Params(slices=1, steps=4, radius=4.0, thickness=INF, noise=O.NOISE_HASH, seed=seed)
+        ao = np.array([r["ao"][c, c] for r in O.bounce_sequence(cframes, ocam(O, ccam), cprm, 0.0)])
+        assert abs(ao.mean() - ref) < 0.012, (seed, ao.mean(), ref)
+        assert ao.std() > 0.01  # single frames really differ
+    # (3) feedback through the light buffer
+    wcam = make_camera(48, 32, fov_y_deg=70, pitch_deg=-30)
+    wgb = crease_gbuffer(wcam, D=3.0, alpha=math.radians(60))
+    walb = np.full(wgb["radiance"].shape, 0.7, np.float32)
+    wframes = [dict(depth=wgb["depth"], normal=wgb["normal"], direct=wgb["radiance"], albedo=walb)] * 6
+    wprm = O.Params(slices=4, steps=8, radius=2.0, thickness=INF, noise=O.NOISE_FIXED)
+    for dt in (np.float32, np.float16):
+        wseq = O.bounce_sequence(wframes, ocam(O, wcam), wprm, 0.9, light_dtype=dt)
+        d = wgb["radiance"].astype(np.float64)
+        assert np.array_equal(wseq[0]["light"], d.astype(dt))
+        for n in range(1, 6):
+            want = (d + np.float64(np.float32(0.9)) * walb.astype(np.float64) * wseq[n - 1]["gi"]).astype(dt)
+            assert np.array_equal(wseq[n]["light"], want), (dt, n)
+        sums = [r["gi"].sum() for r in wseq]
+        inc = np.diff(sums)
+        if dt == np.float32:
+            assert sums[0] > 0 and np.all(inc > 0) and np.all(inc[1:] < inc[:-1]), (dt, sums)
+        else:  # FP16 storage rounds the small late increments away: the fixed point comes sooner
+            assert sums[0] > 0 and inc[0] > 0 and np.all(inc >= 0) and inc[-1] == 0, (dt, sums)
+
+
 def pin_noise_statistics(O):
     """Rotations and jitters are uniform (chi-square) and the slices of one pixel are
     spread evenly over pi; the R2 rotation is a low-discrepancy dither."""
@@ -1060,5 +1117,6 @@ ALL_PINS = [
     pin_quadratic_steps,
     pin_half_resolution,
     pin_multi_bounce,
+    pin_bounce_sequence,
     pin_denoise,
 ]

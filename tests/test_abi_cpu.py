@@ -172,6 +172,20 @@ def test_create_without_gpu_fails_cleanly(B):
     assert not h.value
 
 
+def test_sequence_null_handles(B):
+    """The frame-sequence entry points refuse missing handles before touching a device."""
+    L = B.lib()
+    h = ctypes.c_void_p()
+    assert L.ssvb_sequence_create(None, 16, 16, 0, ctypes.byref(h)) == 1 and not h.value
+    assert L.ssvb_sequence_create(None, 16, 16, 0, None) == 1
+    assert L.ssvb_sequence_step(None, None, None, None, None, None, None, 0.5, None, None) == 1
+    assert L.ssvb_sequence_reset(None) == 1
+    v = ctypes.c_int64(-1)
+    assert L.ssvb_sequence_frame(None, ctypes.byref(v)) == 1 and v.value == -1
+    assert L.ssvb_sequence_copy_light(None, None, 0, None) == 1
+    assert L.ssvb_sequence_destroy(None) == 0
+
+
 def test_validate_depth_span_limit(B):
     # images are addressed with 32-bit byte offsets
     assert status(B, frame(B, W=16384, H=16384, d=setter("pitch_bytes", 65536))) == 0

@@ -87,6 +87,11 @@ MUTATIONS = {
                                   "0.5 * math.sqrt(5.0 / pi) * (3.0 * z * z - 1.0)"),
     "SH zonal without the constant": ("(3.0 * z * z - 1.0)", "(3.0 * z * z)"),
     "SH x^2 - y^2 constant": ("0.25 * math.sqrt(15.0 / pi) * (x * x - y * y)", "0.5 * math.sqrt(15.0 / pi) * (x * x - y * y)"),
+    "sequence seed not advanced": ("seed=(prm.seed + n) % (1 << 32)", "seed=prm.seed"),
+    "sequence feeds back the light": ("        gi = r[\"gi\"]\n        out.append(r)", "        gi = light\n        out.append(r)"),
+    "sequence ignores the gain": ("light = inject_bounce(f[\"direct\"], f[\"albedo\"], prev, gain)",
+                                  "light = inject_bounce(f[\"direct\"], f[\"albedo\"], prev, 1.0)"),
+    "sequence light kept in FP64": (".astype(light_dtype)", ""),
     "denoise background overwritten": ("sig = np.where(fg[..., None], acc / wsum[..., None], sig)",
                                        "sig = acc / wsum[..., None]"),
 }
@@ -102,11 +107,24 @@ def _mutant(name, old, new):
     return mod
 
 
+# the pin most likely to catch a mutant of this kind runs first (only the run time
+# depends on the order: a mutant passes this test if any pin fails on it)
+FIRST = [("denoise", "pin_denoise"), ("a-trous", "pin_denoise"), ("plane distance", "pin_denoise"),
+         ("plane falloff", "pin_denoise"), ("normal weight", "pin_denoise"), ("sequence", "pin_bounce_sequence"),
+         ("SH ", "pin_sh_basis"), ("bounce", "pin_multi_bounce"), ("upsampling", "pin_half_resolution"),
+         ("half resolution", "pin_half_resolution"), ("quadratic", "pin_quadratic_steps")]
+
+
+def pin_order(name):
+    first = [pin for key, pin in FIRST if key in name]
+    return sorted(P.ALL_PINS, key=lambda f: 0 if f.__name__ in first else 1)
+
+
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_pins_catch_mutation(name):
     old, new = MUTATIONS[name]
     O = _mutant(name, old, new)
-    for pin in P.ALL_PINS:
+    for pin in pin_order(name):
         try:
             pin(O)
         except Exception:

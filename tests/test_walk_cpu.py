@@ -44,9 +44,9 @@ int main() {
 
 def walk_source():
     text = open(HEADER).read()
-    i = text.index("__device__ __forceinline__ void walk_tile(")
+    i = text.index("SSVB_HD void walk_tile(")
     j = text.index("\n}\n", i) + 3
-    return text[i:j].replace("__device__ __forceinline__", "static inline")
+    return text[i:j].replace("SSVB_HD", "static inline")
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
