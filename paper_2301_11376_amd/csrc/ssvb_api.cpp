@@ -197,6 +197,18 @@ void r2_constants(uint32_t out[3]) {
 }  // namespace
 
 namespace ssvb {
+// The context's tables, in FP64 on the host: the slice directions (Dx, Dy) =
+// round(4096 (cos, sin)(pi k / 4096)), and cos / sin of h pi / 64 (h = -64..64) and of
+// h pi / 256 (h = -256..256), the sector boundaries of the exact decisions.
+void fill_tables(int2 lut[kLutSize], double2 half[129], double2 half128[513]) {
+    for (int k = 0; k < kLutSize; ++k) {
+        const double phi = M_PI * k / kLutSize;
+        lut[k] = make_int2((int)floor(kLutOne * cos(phi) + 0.5), (int)floor(kLutOne * sin(phi) + 0.5));
+    }
+    for (int h = -64; h <= 64; ++h) half[h + 64] = make_double2(cos(M_PI * h / 64.0), sin(M_PI * h / 64.0));
+    for (int h = -256; h <= 256; ++h) half128[h + 256] = make_double2(cos(M_PI * h / 256.0), sin(M_PI * h / 256.0));
+}
+
 // Apply a launch shape to a frame (clamped to valid values).
 void set_launch(FrameArgs& A, LaunchShape L) {
     if (!(L.lp == 1 || L.lp == 2 || L.lp == 4 || L.lp == 8)) L.lp = 1;
@@ -491,10 +503,8 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
     ssvb_ctx* ctx = new (std::nothrow) ssvb_ctx();
     if (!ctx) return fail(SSVB_ERR_OUT_OF_MEMORY, "host allocation");
     ctx->device = device;
-    for (int k = 0; k < kLutSize; ++k) {
-        const double phi = M_PI * k / kLutSize;
-        ctx->h_lut[k] = make_int2((int)floor(kLutOne * cos(phi) + 0.5), (int)floor(kLutOne * sin(phi) + 0.5));
-    }
+    double2 half[129], half128[513];
+    fill_tables(ctx->h_lut, half, half128);
     int prev = 0;
     (void)hipGetDevice(&prev);
     if ((e = hipSetDevice(device)) != hipSuccess) {
@@ -502,9 +512,6 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
         return hip_fail(e, "hipSetDevice");
     }
     load_tune_cache(ctx);
-    double2 half[129], half128[513];
-    for (int h = -64; h <= 64; ++h) half[h + 64] = make_double2(cos(M_PI * h / 64.0), sin(M_PI * h / 64.0));
-    for (int h = -256; h <= 256; ++h) half128[h + 256] = make_double2(cos(M_PI * h / 256.0), sin(M_PI * h / 256.0));
     e = hipMalloc((void**)&ctx->tab.d_lut, sizeof ctx->h_lut);
     if (e == hipSuccess) e = hipMemcpy(ctx->tab.d_lut, ctx->h_lut, sizeof ctx->h_lut, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->tab.d_half, sizeof half);

@@ -48,6 +48,10 @@ hipError_t init_slot(BatchSlot& s);
 hipError_t slot_graph(BatchSlot& s, int kinds, const int grid[2], hipStream_t cap_stream, hipGraphExec_t* exec);
 void free_slot(BatchSlot& s);
 
+// The slice-direction table and the sector-boundary tables (32 and 128 sectors) that a
+// context uploads, computed on the host.
+void fill_tables(int2 lut[kLutSize], double2 half[129], double2 half128[513]);
+
 // Frame constants (FP64 derivation, one rounding to FP32) and the launch shape from
 // `tab` (forced, tuned for the frame's class, else the default).
 void fill_frame(FrameArgs& A, const FrameTables* tab, const ssvb_image* depth, const ssvb_image* normal,

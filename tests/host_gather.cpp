@@ -1,0 +1,78 @@
+// Host build of the gather's per-pixel code (csrc/ssvb_pixel.h), for the CPU test suite.
+//
+// host_gather() runs, on the CPU, the same per-pixel functions the gfx950 kernels run
+// (gather_pixel, and upsample_pixel at half resolution) on every computed pixel of a frame
+// in host memory, one lane per pixel, with the frame constants and tables the library
+// itself derives (fill_frame, fill_tables from libssvb.so).  The template instance is the
+// one the library's single-frame launcher picks for the frame's mode, or with `generic`
+// the run-time-dispatch instance the batch kernel uses.  Only the device primitives differ
+// from the GPU: the hardware reciprocal (about 1 ulp) is an exact division here, and the
+// compiler may contract differently, so results match the GPU to FP32 rounding, not bit
+// for bit.
+#include <math.h>
+#include <string.h>
+
+#include "ssvb_host.h"
+#include "ssvb_pixel.h"
+
+using namespace ssvb;
+
+namespace {
+
+ExactLds g_lds;  // slot 0 is the one lane's
+
+template <int CRIT, bool TINF, int FMT, int NB>
+void run_pixels(const FrameArgs& A) {
+    for (int y = 0; y < A.H; y += A.sub)
+        for (int x = 0; x < A.W; x += A.sub)
+            gather_pixel<CRIT, MODE_COMPUTE, TINF, FMT, NB>(A, g_lds, x, y, 0, 1, nullptr, nullptr);
+}
+
+template <int CRIT, bool TINF>
+void run_fmt(const FrameArgs& A) {
+    switch (A.normal_f16 | (A.radiance_f16 << 1)) {
+        case 0: run_pixels<CRIT, TINF, 0, 32>(A); break;
+        case 1: run_pixels<CRIT, TINF, 1, 32>(A); break;
+        case 2: run_pixels<CRIT, TINF, 2, 32>(A); break;
+        default: run_pixels<CRIT, TINF, 3, 32>(A); break;
+    }
+}
+
+}  // namespace
+
+extern "C" int host_gather(const ssvb_image* depth, const ssvb_image* normal, const ssvb_image* radiance,
+                           const ssvb_camera* camera, const ssvb_params* params, const ssvb_outputs* out,
+                           int generic) {
+    const ssvb_status s = ssvb_validate(depth, normal, radiance, camera, params, out);
+    if (s != SSVB_OK) return (int)s;
+    if ((int64_t)camera->width * camera->height == 0) return 0;
+    static int2 lut[kLutSize];
+    static double2 half[129], half128[513];
+    fill_tables(lut, half, half128);
+    FrameTables tab;
+    tab.d_lut = lut;
+    tab.d_half = half;
+    tab.d_half128 = half128;
+    FrameArgs A;
+    fill_frame(A, &tab, depth, normal, radiance, camera, params, out);
+    const bool tinf = isinf(A.t0);
+    // the instance the library launches for this frame (launch_plain), or the batch kernel's
+    if (A.nb == 128) {
+        if (!generic && A.criterion == SSVB_HIT_ROUND && !tinf && !A.normal_f16 && !A.radiance_f16)
+            run_pixels<SSVB_HIT_ROUND, false, 0, 128>(A);
+        else
+            run_pixels<-1, false, -1, 128>(A);
+    } else if (generic) {
+        run_pixels<-1, false, -1, 32>(A);
+    } else if (A.criterion == SSVB_HIT_ROUND) {
+        if (tinf) run_fmt<SSVB_HIT_ROUND, true>(A);
+        else run_fmt<SSVB_HIT_ROUND, false>(A);
+    } else {
+        if (tinf) run_fmt<SSVB_HIT_PSEUDOCODE, true>(A);
+        else run_fmt<SSVB_HIT_PSEUDOCODE, false>(A);
+    }
+    if (A.sub == 2)
+        for (int y = 0; y < A.H; ++y)
+            for (int x = 0; x < A.W; ++x) upsample_pixel(A, x, y);
+    return 0;
+}

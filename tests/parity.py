@@ -14,6 +14,7 @@ import math
 import numpy as np
 
 import oracle as O
+from gbuffer_scene import make_camera, make_scene, render_gbuffer
 
 TOL_FP32 = 1e-3
 MASK_AGREEMENT = 0.999
@@ -148,3 +149,60 @@ def sample_pixels(H, W, n, seed):
     extra_y = np.array([0, 0, H - 1, H - 1] + [H - 1] * 8 + list(rng.integers(0, H, 8)))
     extra_x = np.array([0, W - 1, 0, W - 1] + list(rng.integers(0, W, 8)) + [W - 1] * 8)
     return np.concatenate([ys, extra_y]), np.concatenate([xs, extra_x])
+
+
+# ----------------------------------------------------------------------------------------
+# cases shared by the GPU parity tests and the CPU tests of the host build of the kernels
+# ----------------------------------------------------------------------------------------
+INF = float("inf")
+_SCENES = {}
+
+
+def tiny(width=64, height=48, fp16=False, channels=3, seed=7):
+    key = (width, height, fp16, channels, seed)
+    if key not in _SCENES:
+        sc = make_scene(seed, 40, 20)
+        cam = make_camera(width, height, fov_y_deg=60, pitch_deg=-25)
+        dt = np.float16 if fp16 else np.float32
+        gb = render_gbuffer(sc, cam, normal_dtype=dt, radiance_dtype=dt, channels=channels, cache=False)
+        _SCENES[key] = (gb, cam, sc)
+    return _SCENES[key]
+
+
+VARIANTS = {
+    "hash_t04": dict(slices=3, steps=6, radius=1.2, thickness=0.4, noise=O.NOISE_HASH, seed=11),
+    "r2_tinf": dict(slices=4, steps=10, radius=2.5, thickness=INF, noise=O.NOISE_R2, seed=12),
+    "fixed_thin": dict(slices=2, steps=9, radius=0.8, thickness=0.05, noise=O.NOISE_FIXED),
+    "slope": dict(slices=2, steps=7, radius=1.5, thickness=0.1, thickness_slope=0.05, noise=O.NOISE_HASH, seed=13),
+    "pseudocode": dict(slices=3, steps=6, radius=1.5, thickness=0.3, noise=O.NOISE_HASH, seed=14, hit_criterion=1),
+    "one_slice_one_step": dict(slices=1, steps=1, radius=1.0, noise=O.NOISE_HASH, seed=15),
+    "many_slices": dict(slices=16, steps=3, radius=1.0, noise=O.NOISE_R2, seed=16, ambient_samples=32),
+    "ambient1": dict(slices=2, steps=4, radius=1.0, noise=O.NOISE_HASH, seed=17, ambient_samples=1),
+    "capped_subpixel": dict(slices=2, steps=20, radius=4.0, noise=O.NOISE_HASH, seed=18, max_radius_px=6.0,
+                            min_step_q4=2),
+    "zero_thickness": dict(slices=2, steps=6, radius=1.5, thickness=0.0, noise=O.NOISE_HASH, seed=19),
+    "quadratic_steps": dict(slices=3, steps=12, radius=2.0, thickness=0.3, noise=O.NOISE_R2, seed=20,
+                            step_distribution=1),
+    "sectors128": dict(slices=3, steps=8, radius=1.5, thickness=0.4, noise=O.NOISE_HASH, seed=41, sectors=128),
+    "sectors128_pseudocode_tinf": dict(slices=2, steps=10, radius=2.0, thickness=INF, noise=O.NOISE_R2, seed=42,
+                                       sectors=128, hit_criterion=1, ambient_samples=16),
+    "sectors128_slope_quadratic": dict(slices=4, steps=6, radius=1.0, thickness=0.1, thickness_slope=0.05,
+                                       noise=O.NOISE_HASH, seed=43, sectors=128, step_distribution=1,
+                                       ambient_samples=32),
+    "quadratic_pseudocode_tinf": dict(slices=2, steps=8, radius=1.5, thickness=INF, noise=O.NOISE_HASH, seed=21,
+                                      step_distribution=1, hit_criterion=1),
+    # the largest slice and step counts the library accepts
+    "max_slices": dict(slices=64, steps=2, radius=1.0, thickness=0.3, noise=O.NOISE_HASH, seed=44, ambient_samples=32),
+    "max_slices_128": dict(slices=64, steps=2, radius=1.0, thickness=0.3, noise=O.NOISE_R2, seed=45, sectors=128,
+                           ambient_samples=32),
+    "max_steps": dict(slices=1, steps=1024, radius=6.0, thickness=0.4, noise=O.NOISE_R2, seed=46, min_step_q4=1),
+    "max_steps_quadratic": dict(slices=1, steps=1024, radius=6.0, thickness=INF, noise=O.NOISE_HASH, seed=47,
+                                min_step_q4=1, step_distribution=1),
+}
+
+
+HALF_CASES = {
+    "uniform": dict(slices=3, steps=6, radius=1.2, thickness=0.4, noise=O.NOISE_HASH, seed=31),
+    "table2_f": dict(slices=2, steps=16, radius=4.0, thickness=0.2, noise=O.NOISE_R2, seed=32,
+                     step_distribution=1),
+}

@@ -1,0 +1,210 @@
+"""CPU tests of the gather kernels' per-pixel code, built for the host (host_gather.cpp).
+
+csrc/ssvb_pixel.h holds everything a kernel thread computes for its pixel; its functions
+are __host__ __device__, so the same source runs here on the CPU, with the frame constants
+and tables the library derives.  These tests hold that code to the FP64 oracle with the
+GPU parity tests' bar (masks equal, every mismatch traced to a near-tie endpoint, AO / GI /
+ambient within 1e-3) on the same cases, and check that the batch kernel's run-time
+dispatch instance gives the single-frame instance's results bit for bit.  The device
+differs only in its primitives (the hardware reciprocal, FP contraction), so this shows
+the kernel source right, not the GPU's rounding."""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+import parity as PY
+from gbuffer_scene import make_camera, make_scene, render_gbuffer, workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.fixture(scope="module")
+def host():
+    if not os.path.exists(HIPCC):
+        pytest.skip("needs hipcc")
+    from paper_2301_11376_amd import binding, build_lib
+    if not os.path.exists(binding.LIB_PATH):
+        build_lib.build()
+    libdir = os.path.dirname(binding.LIB_PATH)
+    with tempfile.TemporaryDirectory() as d:
+        so = os.path.join(d, "host_gather.so")
+        cmd = [HIPCC, "-x", "hip", "--cuda-host-only", "-O2", "-std=c++17", "-fPIC", "-shared",
+               "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2301_11376_amd", "csrc"),
+               os.path.join(ROOT, "tests", "host_gather.cpp"), "-L", libdir, "-lssvb", f"-Wl,-rpath,{libdir}",
+               "-o", so]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        assert res.returncode == 0, res.stdout + res.stderr
+        L = ctypes.CDLL(so)
+        B = binding
+        L.host_gather.restype = ctypes.c_int32
+        L.host_gather.argtypes = [ctypes.POINTER(B.ssvb_image)] * 3 + [
+            ctypes.POINTER(B.ssvb_camera), ctypes.POINTER(B.ssvb_params), ctypes.POINTER(B.ssvb_outputs),
+            ctypes.c_int32]
+        yield L
+
+
+def _image(a, pad=0):
+    """ssvb_image of a host array (optionally in rows padded by `pad` elements)."""
+    from paper_2301_11376_amd import binding as B
+    a = np.ascontiguousarray(a)
+    if pad:
+        H, W = a.shape[:2]
+        buf = np.zeros((H, W + pad) + a.shape[2:], a.dtype)
+        buf[:, :W] = a
+        a = buf[:, :W]
+    ch = 1 if a.ndim == 2 else a.shape[2]
+    dt = B.F16 if a.dtype == np.float16 else B.F32
+    return B.ssvb_image(a.ctypes.data, a.strides[0], dt, ch), a
+
+
+def run_host(L, gb, cam, masks=True, generic=False, pad=0, **kw):
+    from paper_2301_11376_amd import binding as B
+    H, W = gb["depth"].shape
+    d, da = _image(gb["depth"], pad)
+    n, na = _image(gb["normal"], pad)
+    r, ra = _image(gb["radiance"], pad)
+    bc, _ = PY.cams(cam)
+    bp, _ = PY.params(**kw)
+    words = kw["slices"] * kw.get("sectors", 32) // 32
+    out = {"ao": np.full((H, W), np.nan, np.float32), "gi": np.full((H, W, 3), np.nan, np.float32),
+           "ambient": np.full((H, W, 3), np.nan, np.float32)}
+    if masks:
+        out["masks"] = np.full((H, W, words), 0xDEADBEEF, np.uint32)
+    o = B.ssvb_outputs(out["ao"].ctypes.data, out["gi"].ctypes.data, out["ambient"].ctypes.data,
+                       out["masks"].ctypes.data if masks else None, 0, 0, 0, 0)
+    c, p = bc.to_c(), bp.to_c()
+    st = L.host_gather(ctypes.byref(d), ctypes.byref(n), ctypes.byref(r), ctypes.byref(c), ctypes.byref(p),
+                       ctypes.byref(o), int(generic))
+    assert st == 0, st
+    return out
+
+
+def host_case(L, gb, cam, report=None, pixels=None, **kw):
+    """The host build against the oracle, and the batch instance against the single-frame
+    instance (bit for bit)."""
+    g = run_host(L, gb, cam, **kw)
+    gen = run_host(L, gb, cam, generic=True, **kw)
+    for k in g:
+        assert np.array_equal(g[k].view(np.uint32), gen[k].view(np.uint32)), ("generic instance", k)
+    _, oc = PY.cams(cam)
+    _, op = PY.params(**kw)
+    ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, pixels=pixels, return_masks=True)
+    PY.compare(g, ref, gb, oc, op, pixels=pixels, report=report)
+    return g
+
+
+def test_host_c1_full_frame(host):
+    gb, cam, w, sc = workload("c1_128")
+    rep = {}
+    host_case(host, gb, cam, report=rep, slices=2, steps=8, radius=2.0, thickness=0.5, noise=O.NOISE_HASH, seed=1,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    print(rep)
+    assert rep["mask_agreement"] == 1.0
+
+
+@pytest.mark.parametrize("name", sorted(PY.VARIANTS))
+def test_host_variants(host, name):
+    gb, cam, sc = PY.tiny()
+    host_case(host, gb, cam, ambient_sh=tuple(sc.ambient_sh.reshape(-1)), **PY.VARIANTS[name])
+
+
+@pytest.mark.parametrize("fp16,channels", [(False, 4), (True, 3), (True, 4)])
+def test_host_formats(host, fp16, channels):
+    gb, cam, sc = PY.tiny(fp16=fp16, channels=channels)
+    host_case(host, gb, cam, slices=3, steps=6, radius=1.3, thickness=0.3, noise=O.NOISE_R2, seed=2,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+
+
+@pytest.mark.parametrize("shape", [(67, 45), (1, 1), (1, 37), (37, 1), (129, 3)])
+def test_host_ragged_shapes(host, shape):
+    W, H = shape
+    sc = make_scene(21, 40, 20)
+    cam = make_camera(W, H, fov_y_deg=60, pitch_deg=-25)
+    gb = render_gbuffer(sc, cam, cache=False)
+    host_case(host, gb, cam, slices=3, steps=5, radius=1.0, noise=O.NOISE_HASH, seed=3,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+
+
+def test_host_pitched_buffers(host):
+    """Rows padded in every input: the same results as dense rows, bit for bit."""
+    gb, cam, sc = PY.tiny()
+    kw = dict(slices=3, steps=6, radius=1.3, thickness=0.3, noise=O.NOISE_R2, seed=2,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    a = run_host(host, gb, cam, **kw)
+    b = run_host(host, gb, cam, pad=13, **kw)
+    for k in a:
+        assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), k
+
+
+@pytest.mark.parametrize("sectors", [32, 128])
+def test_host_quadratic_probe(host, sectors):
+    gb, cam, sc = PY.tiny()
+    sh = np.random.default_rng(31).uniform(-1.0, 1.0, (9, 3))
+    sh[0] = 1.5
+    host_case(host, gb, cam, slices=4, steps=6, radius=1.5, thickness=0.4, noise=O.NOISE_R2, seed=31,
+              ambient_samples=8, sectors=sectors, ambient_sh=tuple(sh.reshape(-1)))
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+def test_host_sectors128_c1(host, fp16):
+    gb, cam, w, sc = workload("c1_128")
+    if fp16:
+        gb = dict(gb, normal=gb["normal"].astype(np.float16), radiance=gb["radiance"].astype(np.float16))
+    rep = {}
+    host_case(host, gb, cam, report=rep, slices=2, steps=8, radius=2.0, thickness=0.5, noise=O.NOISE_HASH, seed=1,
+              sectors=128, ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    print(rep)
+
+
+def test_host_background(host):
+    """A frame of sky only: AO 1, GI 0, ambient 0, masks 0 everywhere."""
+    cam = make_camera(19, 11, fov_y_deg=60, pitch_deg=0)
+    gb = {"depth": np.zeros((11, 19), np.float32), "normal": np.zeros((11, 19, 3), np.float32),
+          "radiance": np.ones((11, 19, 3), np.float32)}
+    g = run_host(host, gb, cam, slices=3, steps=4, radius=1.0, noise=O.NOISE_HASH, seed=1)
+    assert np.all(g["ao"] == 1) and np.all(g["gi"] == 0) and np.all(g["ambient"] == 0) and np.all(g["masks"] == 0)
+
+
+@pytest.mark.parametrize("name", sorted(PY.HALF_CASES))
+@pytest.mark.parametrize("size", [(64, 48), (67, 45)])
+def test_host_half_resolution(host, name, size):
+    """Half resolution: the gathered (even, even) pixels are the full-resolution run's bit
+    for bit; the upsampler matches the oracle's FP64 one on the same gathered values within
+    1e-5; the whole image matches the oracle's half-resolution result within 1e-3."""
+    gb, cam, sc = PY.tiny(*size)
+    kw = dict(PY.HALF_CASES[name], ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    full = host_case(host, gb, cam, **kw)
+    half = run_host(host, gb, cam, masks=False, resolution=2, **kw)
+    for k in ("ao", "gi", "ambient"):
+        assert np.array_equal(half[k][0::2, 0::2].view(np.uint32), full[k][0::2, 0::2].view(np.uint32)), k
+    a, g, m = O.bilateral_upsample(gb["depth"], half["ao"].astype(np.float64), half["gi"].astype(np.float64),
+                                   half["ambient"].astype(np.float64))
+    assert max(np.abs(half["ao"] - a).max(), np.abs(half["gi"] - g).max(), np.abs(half["ambient"] - m).max()) <= 1e-5
+    _, oc = PY.cams(cam)
+    _, op = PY.params(resolution=2, **kw)
+    ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op)
+    for k in ("ao", "gi", "ambient"):
+        assert np.abs(half[k] - ref[k]).max() <= 1e-3, k
+
+
+def test_host_c2_1080p_sampled(host):
+    """The whole 1920x1080 frame through the host build; the oracle checks a seeded sample
+    of 3,000 pixels plus the corners and the last row and column."""
+    gb, cam, w, sc = workload("c2_1080p")
+    H, W = gb["depth"].shape
+    rep = {}
+    kw = dict(slices=4, steps=16, radius=3.0, thickness=0.5, noise=O.NOISE_R2, seed=2,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    g = run_host(host, gb, cam, **kw)
+    pix = PY.sample_pixels(H, W, 3000, 2)
+    _, oc = PY.cams(cam)
+    _, op = PY.params(**kw)
+    ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, pixels=pix, return_masks=True)
+    PY.compare(g, ref, gb, oc, op, pixels=pix, report=rep)
+    print(rep)
