@@ -53,7 +53,7 @@ def samples_of(f):
 def device_source_sha256():
     import hashlib
     h = hashlib.sha256()
-    for f in ("ssvb_kernels.hip", "ssvb_internal.h"):
+    for f in ("ssvb_kernels.hip", "ssvb_pixel.h", "ssvb_internal.h"):
         with open(os.path.join(ROOT, "paper_2301_11376_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
