@@ -128,7 +128,22 @@ SSVB_HD uint32_t jitter8(const FrameArgs& A, int x, int y, int i) {
 // G-buffer access (every image spans less than 4 GiB: 32-bit byte offsets)
 // ---------------------------------------------------------------------------------------
 
+#if !defined(__HIP_DEVICE_COMPILE__)
+// Host build only: an observer of every image read (address, bytes), for the CPU cache
+// model of the reads; null unless a test sets it.
+inline void (*host_read_observer)(const void* addr, int bytes) = nullptr;
+#define SSVB_OBSERVE_READ(p, n) \
+    do {                        \
+        if (host_read_observer) host_read_observer((p), (n)); \
+    } while (0)
+#else
+#define SSVB_OBSERVE_READ(p, n) \
+    do {                        \
+    } while (0)
+#endif
+
 SSVB_HD float depth_load(const FrameArgs& A, uint32_t off) {
+    SSVB_OBSERVE_READ((const char*)A.depth + off, 4);
     return *(const GMEM float*)((const GMEM char*)A.depth + off);
 }
 
@@ -137,6 +152,7 @@ template <int F>
 SSVB_HD float3 load3(const char* base, int64_t pitch, int ch, int f16, int x, int y) {
     const bool h = F < 0 ? f16 != 0 : F == 1;
     const GMEM char* b = (const GMEM char*)base + image_off(pitch, ch, h, x, y);
+    SSVB_OBSERVE_READ((const char*)b, h ? 6 : 12);
     if (h) {
         const GMEM _Float16* p = (const GMEM _Float16*)b;
         return make_float3((float)p[0], (float)p[1], (float)p[2]);
