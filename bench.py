@@ -131,16 +131,15 @@ def cpu_baseline_leg(loaded, workers, names):
         gb, cam, w, scene = loaded["c2_1080p"][:4]
         H = gb["depth"].shape[0]
         res, _, _ = compute_rows(gb, oracle_camera(O, cam), oracle_params(O, w, scene), 0, H, workers,
-                                 return_masks=True, bands=4 * workers)
+                                 return_masks=True)
         refs["c2_1080p"] = {"rows": (0, H), "fp": res}
     if "c3_4k_fp16" in names:
         gb, cam, w, scene, gb32 = loaded["c3_4k_fp16"]
         H = gb["depth"].shape[0]
         r0 = (H - C3_PARITY_ROWS) // 2
         oc, prm = oracle_camera(O, cam), oracle_params(O, w, scene)
-        res16, _, _ = compute_rows(gb, oc, prm, r0, r0 + C3_PARITY_ROWS, workers, return_masks=True,
-                                   bands=2 * workers)
-        res32, _, _ = compute_rows(gb32, oc, prm, r0, r0 + C3_PARITY_ROWS, workers, bands=2 * workers)
+        res16, _, _ = compute_rows(gb, oc, prm, r0, r0 + C3_PARITY_ROWS, workers, return_masks=True)
+        res32, _, _ = compute_rows(gb32, oc, prm, r0, r0 + C3_PARITY_ROWS, workers)
         refs["c3_4k_fp16"] = {"rows": (r0, r0 + C3_PARITY_ROWS), "fp": res16, "fp32_originals": res32}
     print(f"oracle reference outputs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     return base, refs

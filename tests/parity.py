@@ -206,3 +206,51 @@ HALF_CASES = {
     "table2_f": dict(slices=2, steps=16, radius=4.0, thickness=0.2, noise=O.NOISE_R2, seed=32,
                      step_distribution=1),
 }
+
+
+# ----------------------------------------------------------------------------------------
+# oracle references of the large-frame GPU parity tests
+# ----------------------------------------------------------------------------------------
+# Each is the oracle over row bands of a workload frame.  They are computed in forked
+# processes when the test session's collection ends (tests/conftest.py), before any test
+# initialises the GPU (a process that uses the GPU must not fork), and kept here; a test
+# that finds none computes it in this process.
+BAND_REFS = {}
+C3_BAND_ROWS = 270
+
+
+def band_cases():
+    """name -> (G-buffer, camera, oracle params kwargs, first row, end row, masks)."""
+    from gbuffer_scene import workload
+    out = {}
+    gb, cam, w, sc = workload("c2_1080p")
+    kw = dict(slices=4, steps=16, radius=3.0, thickness=0.5, noise=O.NOISE_R2, seed=2,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    out["c2_full"] = (gb, cam, kw, 0, gb["depth"].shape[0], True)
+    gb, cam, w, sc = workload("c3_4k_fp16")
+    H = gb["depth"].shape[0]
+    r0 = (H - C3_BAND_ROWS) // 2
+    kw = dict(slices=8, steps=32, radius=8.0, thickness=w["thickness"], noise=O.NOISE_R2, seed=3,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    out["c3_band_fp16"] = (gb, cam, kw, r0, r0 + C3_BAND_ROWS, True)
+    out["c3_band_fp32"] = (render_gbuffer(make_scene(3, 64, 32), cam), cam, kw, r0, r0 + C3_BAND_ROWS, False)
+    return out
+
+
+def compute_band_refs(names, workers, threads=False):
+    """Fill BAND_REFS for `names` (the oracle over the cases' rows)."""
+    import os
+    import time
+    from oracle.bands import compute_rows
+    cases = band_cases()
+    for n in names:
+        if n in BAND_REFS:
+            continue
+        gb, cam, kw, r0, r1, masks = cases[n]
+        _, oc = cams(cam)
+        t0 = time.perf_counter()
+        res, _, _ = compute_rows(gb, oc, O.Params(**kw), r0, r1, workers, return_masks=masks, threads=threads)
+        BAND_REFS[n] = res
+        print(f"oracle reference {n}: rows {r0}..{r1 - 1} in {time.perf_counter() - t0:.1f} s "
+              f"({'threads' if threads else 'processes'}, {workers})", flush=True)
+    return {n: BAND_REFS[n] for n in names}

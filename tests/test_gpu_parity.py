@@ -278,17 +278,10 @@ def test_deterministic(ctx):
         assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
 
 
-ORACLE_THREADS = 16  # oracle bands run as threads: this process already uses the GPU
-
-
-def oracle_rows(gb, cam, r0, r1, masks=True, **kw):
-    from oracle.bands import compute_rows
-    _, oc = PY.cams(cam)
-    _, op = PY.params(**kw)
-    res, wall, _ = compute_rows(gb, oc, op, r0, r1, ORACLE_THREADS, return_masks=masks, bands=4 * ORACLE_THREADS,
-                                threads=True)
-    log(f"  oracle rows {r0}..{r1 - 1}: {wall:.1f} s")
-    return res
+def band_refs(*names):
+    """The oracle references computed when collection ended (in this process, with threads,
+    if the test runs without them)."""
+    return PY.compute_band_refs(list(names), 16, threads=True)
 
 
 def band_pixels(r0, r1, W):
@@ -299,15 +292,13 @@ def test_parity_c2_1080p_full_frame(ctx):
     """Every pixel of the 1920x1080 frame as the benchmark runs it (its launch shape),
     against the oracle: masks equal on >= 99.9 % of pixels with every mismatch traced to a
     near-tie endpoint, AO / GI / ambient within 1e-3."""
-    gb, cam, w, sc = workload("c2_1080p")
     log("parity c2 1080p (full frame)")
+    gb, cam, kw, _, _, _ = PY.band_cases()["c2_full"]
     H, W = gb["depth"].shape
-    kw = dict(slices=4, steps=16, radius=3.0, thickness=0.5, noise=O.NOISE_R2, seed=2,
-              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
     bc, oc = PY.cams(cam)
     bp, op = PY.params(**kw)
     gpu = PY.gpu_run(ctx, gb, bc, bp)
-    ref = oracle_rows(gb, cam, 0, H, **kw)
+    ref = band_refs("c2_full")["c2_full"]
     rep = {}
     PY.compare(gpu, {k: v.reshape((H * W,) + v.shape[2:]) for k, v in ref.items()}, gb, oc, op,
                pixels=band_pixels(0, H, W), report=rep)
@@ -318,23 +309,19 @@ def test_parity_c3_4k_fp16_band(ctx):
     """A 270-row band across the middle of the 3840x2160 FP16 frame (GPU run on the whole
     frame): against the oracle on the same FP16 values (masks, tracer, 1e-3) and against
     the oracle on the FP32 originals (p99.9 and max of |error| <= 2e-2 per output)."""
-    gb, cam, w, sc = workload("c3_4k_fp16")
     log("parity c3 4k fp16 (270-row band)")
+    gb, cam, kw, r0, r1, _ = PY.band_cases()["c3_band_fp16"]
     H, W = gb["depth"].shape
-    r0, r1 = (H - 270) // 2, (H - 270) // 2 + 270
-    kw = dict(slices=8, steps=32, radius=8.0, thickness=w["thickness"], noise=O.NOISE_R2, seed=3,
-              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
     bc, oc = PY.cams(cam)
     bp, op = PY.params(**kw)
     gpu = PY.gpu_run(ctx, gb, bc, bp)
     pix = band_pixels(r0, r1, W)
-    ref = oracle_rows(gb, cam, r0, r1, **kw)
+    refs = band_refs("c3_band_fp16", "c3_band_fp32")
+    ref, ref32 = refs["c3_band_fp16"], refs["c3_band_fp32"]
     rep = {}
     PY.compare(gpu, {k: v.reshape((len(pix[0]),) + v.shape[2:]) for k, v in ref.items()}, gb, oc, op, pixels=pix,
                report=rep)
     log(f"  vs FP16 inputs: {rep}")
-    gb32 = render_gbuffer(make_scene(3, 64, 32), cam)
-    ref32 = oracle_rows(gb32, cam, r0, r1, masks=False, **kw)
     stats = {}
     for k in ("ao", "gi", "ambient"):
         e = np.abs(gpu[k][r0:r1] - ref32[k]).reshape(-1)
