@@ -256,6 +256,12 @@ static void emulate_batch(const std::vector<Frame>& frames, LaunchShape shape, i
     tab.forced = true;
     tab.force = shape;
     build_batch(&tab, &D, F.data(), (int)F.size());
+    // the descriptor's frame constants are the single-frame launch's, byte for byte (both
+    // come from fill_frame, which clears the padding), so a batched frame runs the same
+    // per-pixel code on the same constants as its own launch
+    CHECK(D.n_frames == (int)F.size(), "batch of %d frames, descriptor %d", (int)F.size(), D.n_frames);
+    for (size_t i = 0; i < F.size(); ++i)
+        CHECK(memcmp(&D.frames[i], &A[i], sizeof(FrameArgs)) == 0, "frame %zu: batch constants differ", i);
     for (int w = 0; w < 2; ++w) {
         const int pn = D.pn[w];
         const uint32_t total = pn ? D.prefix[w][pn] : 0;
