@@ -264,7 +264,8 @@ ssvb_status ssvb_sequence_create(ssvb_ctx* ctx, int32_t width, int32_t height, s
  * gain finite and >= 0.  Everything is validated before anything is launched; the frame
  * counter advances only when the step was enqueued.  Steps of one sequence must be
  * ordered on the device (one stream, or the caller orders them); steps of different
- * sequences are independent. */
+ * sequences are independent.  A step uses the sequence's context, so the context's rule
+ * holds: one host thread at a time. */
 ssvb_status ssvb_sequence_step(ssvb_sequence* seq, const ssvb_image* depth, const ssvb_image* normal,
                                const ssvb_image* direct, const ssvb_image* albedo, const ssvb_camera* camera,
                                const ssvb_params* params, float gain, const ssvb_outputs* out, void* hip_stream);
