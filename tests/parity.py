@@ -67,10 +67,13 @@ def gpu_run(ctx, gb, cam, prm, masks=True):
     return res
 
 
-def compare(gpu, ref, gb, ocam, oprm, pixels=None, tol=TOL_FP32, report=None):
+def compare(gpu, ref, gb, ocam, oprm, pixels=None, tol=TOL_FP32, report=None, agreement=MASK_AGREEMENT,
+            max_bad=200):
     """Compare GPU outputs with the oracle's; explain every mismatch by flipping near-tie
     roundings in an FP64 replay.  ``gpu`` holds full images, ``ref`` the oracle results at
-    ``pixels`` (or full images).  Returns a stats dict; raises AssertionError on failure."""
+    ``pixels`` (or full images).  At most ``max_bad`` pixels may differ and the masks must
+    agree on at least ``agreement`` of them.  Returns a stats dict; raises AssertionError
+    on failure."""
     if pixels is None:
         H, W = gb["depth"].shape
         ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
@@ -99,44 +102,178 @@ def compare(gpu, ref, gb, ocam, oprm, pixels=None, tol=TOL_FP32, report=None):
         "explained": 0,
     }
     unexplained = []
-    for idx in np.flatnonzero(bad)[:200]:
+    for idx in np.flatnonzero(bad)[:max_bad]:
         if explain_pixel(gpu, gb, ocam, oprm, int(ys[idx]), int(xs[idx]), tol):
             stats["explained"] += 1
         else:
             unexplained.append((int(ys[idx]), int(xs[idx])))
     if report is not None:
         report.update(stats)
-    assert bad.sum() <= 200, f"{bad.sum()} mismatched pixels: {stats}"
+    assert bad.sum() <= max_bad, f"{bad.sum()} mismatched pixels: {stats}"
     assert not unexplained, f"unexplained mismatches at {unexplained[:10]}: {stats}"
-    assert stats["mask_agreement"] >= MASK_AGREEMENT, stats
+    assert stats["mask_agreement"] >= agreement, stats
     return stats
 
 
-def explain_pixel(gpu, gb, ocam, oprm, y, x, tol):
-    """Replay pixel (y, x) in FP64 with every combination of flipped near-tie roundings;
-    True if one reproduces the GPU's masks exactly and its outputs within ``tol``."""
-    r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam, oprm, pixels=([y], [x]),
-                  return_endpoints=True)
-    ep = r["endpoints"][0]
+def _flip(v, ceil):
+    """Bias that moves the rounding of an endpoint argument ``v`` across its nearest integer:
+    +1 below it, -1 above it; exactly on it, a floor drops (-1) and a ceiling rises (+1)."""
+    r = np.round(v)
+    if v != r:
+        return 1 if v < r else -1
+    return 1 if ceil else -1
+
+
+def _near_ties(ep, oprm):
+    """Near-tie endpoints of one pixel: a list of (index into ``ep``, bias).  A sector start
+    exactly at 0 has no flip: an angle past the hemisphere edge is clamped back onto it."""
+    pseudo = oprm.hit_criterion != O.ROUND
     dist = np.abs(ep - np.round(ep))
-    near = np.argwhere(np.isfinite(ep) & (dist < tie_sectors(oprm.sectors)))
-    if len(near) == 0 or len(near) > 10:
+    out = []
+    for pos in np.argwhere(np.isfinite(ep) & (dist < tie_sectors(oprm.sectors))):
+        pos = tuple(int(p) for p in pos)
+        v = ep[pos]
+        f = _flip(v, pseudo and pos[-1] == 1)
+        if pos[-1] == 0 and v == 0.0 and f < 0:
+            continue
+        out.append((pos, f))
+    return out
+
+
+def _replay(gpu, gb, ocam, oprm, y, x, bias, tol):
+    """The oracle at pixel (y, x) with rounding biases: does it give the GPU's masks and
+    outputs within ``tol``?"""
+    rr = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam, oprm, pixels=([y], [x]),
+                   return_masks=True, index_bias=bias[None])
+    if not np.array_equal(packed_masks(rr["masks"])[0], gpu["masks"][y, x]):
         return False
-    for flips in itertools.product((0, 1), repeat=len(near)):
-        if not any(flips):
+    return bool(abs(rr["ao"][0] - gpu["ao"][y, x]) <= tol and np.abs(rr["gi"][0] - gpu["gi"][y, x]).max() <= tol
+                and np.abs(rr["ambient"][0] - gpu["ambient"][y, x]).max() <= tol)
+
+
+def _sample_bits(e, d, nb, pseudo):
+    """Sector set (an int bit mask) of one sample from its endpoint arguments ``e`` and
+    rounding biases ``d``: [floor, floor) under ROUND; start floor and width ceil under
+    PSEUDOCODE.  Used only to steer the search; every candidate is replayed by the oracle."""
+    a = math.floor(e[0]) + d[0]
+    b = min(a + math.ceil(e[1]) + d[1], nb) if pseudo else math.floor(e[1]) + d[1]
+    a, b = max(a, 0), min(b, nb)
+    return ((1 << b) - (1 << a)) if b > a else 0
+
+
+def _slice_solutions(ep_i, ties, target, nb, pseudo, limit=16):
+    """Up to ``limit`` bias choices for one slice whose sample sets OR to ``target``: a
+    depth-first search over the samples in march order (side +, then -, steps in order),
+    each keeping its rounding or taking flips of its own near-tie endpoints, fewest flips
+    first.  Returns a list of {(side, step): (bias0, bias1)}."""
+    order = [(s, j) for s in range(ep_i.shape[0]) for j in range(ep_i.shape[1])]
+    alts = []
+    for s, j in order:
+        e = ep_i[s, j]
+        if not np.all(np.isfinite(e)):
+            alts.append([((0, 0), 0)])
             continue
-        bias = np.zeros((1,) + ep.shape, dtype=np.int64)
-        for f, pos in zip(flips, near):
-            if f:
-                v = ep[tuple(pos)]
-                bias[(0,) + tuple(pos)] = 1 if v < np.round(v) else -1
-        rr = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam, oprm, pixels=([y], [x]),
-                       return_masks=True, index_bias=bias)
-        if not np.array_equal(packed_masks(rr["masks"])[0], gpu["masks"][y, x]):
-            continue
-        if (abs(rr["ao"][0] - gpu["ao"][y, x]) <= tol and np.abs(rr["gi"][0] - gpu["gi"][y, x]).max() <= tol
-                and np.abs(rr["ambient"][0] - gpu["ambient"][y, x]).max() <= tol):
+        t = ties.get((s, j), {})
+        opts = {}
+        for f0 in ((0,) if 0 not in t else (0, t[0])):
+            for f1 in ((0,) if 1 not in t else (0, t[1])):
+                bits = _sample_bits(e, (f0, f1), nb, pseudo)
+                if bits & ~target:
+                    continue
+                if bits not in opts or abs(f0) + abs(f1) < sum(map(abs, opts[bits])):
+                    opts[bits] = (f0, f1)
+        alts.append(sorted(((d, b) for b, d in opts.items()), key=lambda db: sum(map(abs, db[0]))))
+    suffix = [0] * (len(order) + 1)
+    for k in range(len(order) - 1, -1, -1):
+        suffix[k] = suffix[k + 1]
+        for _, b in alts[k]:
+            suffix[k] |= b
+    out, dead, path = [], set(), []
+
+    def dfs(k, covered):
+        if len(out) >= limit:
             return True
+        if (covered | suffix[k]) & target != target or (k, covered) in dead:
+            return False
+        if k == len(order):
+            if covered == target:
+                out.append({order[i]: d for i, d in enumerate(path) if d != (0, 0)})
+                return True
+            return False
+        found = False
+        for d, b in alts[k]:
+            path.append(d)
+            found |= dfs(k + 1, covered | b)
+            path.pop()
+            if len(out) >= limit:
+                return True
+        if not found:
+            dead.add((k, covered))
+        return found
+
+    dfs(0, 0)
+    return out
+
+
+def explain_pixel(gpu, gb, ocam, oprm, y, x, tol):
+    """Replay pixel (y, x) in FP64 with flipped near-tie roundings; True if one choice
+    reproduces the GPU's masks exactly and its outputs within ``tol``.  Up to 10 near
+    ties every combination is tried; beyond that (whole rows of samples exactly on a
+    hemisphere edge) each mismatched slice is searched on its own for flips whose sector
+    sets OR to the GPU's slice mask, and the candidates are replayed."""
+    r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam, oprm, pixels=([y], [x]),
+                  return_masks=True, return_endpoints=True)
+    ep = r["endpoints"][0]
+    near = _near_ties(ep, oprm)
+    if not near:
+        return False
+    if len(near) <= 10:
+        for flips in itertools.product((0, 1), repeat=len(near)):
+            if not any(flips):
+                continue
+            bias = np.zeros(ep.shape, dtype=np.int64)
+            for f, (pos, d) in zip(flips, near):
+                if f:
+                    bias[pos] = d
+            if _replay(gpu, gb, ocam, oprm, y, x, bias, tol):
+                return True
+        return False
+    nb, pseudo = oprm.sectors, oprm.hit_criterion != O.ROUND
+    wpc = nb // 32
+    mine = packed_masks(r["masks"])[0]
+    theirs = gpu["masks"][y, x]
+    per_slice = []
+    for i in range(ep.shape[0]):
+        if np.array_equal(mine[i * wpc:(i + 1) * wpc], theirs[i * wpc:(i + 1) * wpc]):
+            continue
+        target = sum(int(w) << (32 * k) for k, w in enumerate(theirs[i * wpc:(i + 1) * wpc]))
+        ties = {}
+        for pos, d in near:
+            if pos[0] == i:
+                ties.setdefault((pos[1], pos[2]), {})[pos[3]] = d
+        sols = _slice_solutions(ep[i], ties, target, nb, pseudo)
+        if not sols:
+            return False
+        per_slice.append((i, sols))
+    if not per_slice:
+        return False
+
+    def bias_of(choice):
+        bias = np.zeros(ep.shape, dtype=np.int64)
+        for (i, sols), c in zip(per_slice, choice):
+            for (s, j), (d0, d1) in sols[c].items():
+                bias[i, s, j] = (d0, d1)
+        return bias
+
+    base = [0] * len(per_slice)
+    if _replay(gpu, gb, ocam, oprm, y, x, bias_of(base), tol):
+        return True
+    for k, (_, sols) in enumerate(per_slice):
+        for c in range(1, len(sols)):
+            choice = list(base)
+            choice[k] = c
+            if _replay(gpu, gb, ocam, oprm, y, x, bias_of(choice), tol):
+                return True
     return False
 
 
@@ -254,3 +391,26 @@ def compute_band_refs(names, workers, threads=False):
         print(f"oracle reference {n}: rows {r0}..{r1 - 1} in {time.perf_counter() - t0:.1f} s "
               f"({'threads' if threads else 'processes'}, {workers})", flush=True)
     return {n: BAND_REFS[n] for n in names}
+
+
+def random_case(rng):
+    """A seeded random frame and parameter set over the library's whole parameter space."""
+    W, H = int(rng.integers(1, 41)), int(rng.integers(1, 31))
+    fp16 = bool(rng.integers(2))
+    ch = int(rng.choice([3, 4]))
+    sc = make_scene(int(rng.integers(1000)), int(rng.integers(5, 40)), int(rng.integers(0, 20)))
+    cam = make_camera(W, H, fov_y_deg=float(rng.uniform(40, 100)), pitch_deg=float(rng.uniform(-60, 0)))
+    dt = np.float16 if fp16 else np.float32
+    gb = render_gbuffer(sc, cam, normal_dtype=dt, radiance_dtype=dt, channels=ch, cache=False)
+    sectors = int(rng.choice([32, 128]))
+    na = int(rng.choice([n for n in (1, 2, 4, 8, 16, 32) if sectors % n == 0]))
+    kw = dict(slices=int(rng.integers(1, 9)), steps=int(rng.integers(1, 21)), sectors=sectors,
+              ambient_samples=na, radius=float(rng.uniform(0.2, 4.0)),
+              thickness=float(rng.choice([0.0, INF, rng.uniform(0.01, 1.0)])),
+              thickness_slope=float(rng.choice([0.0, rng.uniform(0.0, 0.1)])),
+              max_radius_px=float(rng.choice([0.0, rng.uniform(1.0, 30.0)])),
+              min_step_q4=int(rng.choice([16, int(rng.integers(1, 17))])),
+              step_distribution=int(rng.integers(2)), hit_criterion=int(rng.integers(2)),
+              noise=int(rng.integers(3)), seed=int(rng.integers(0, 1 << 32)),
+              ambient_sh=tuple(rng.uniform(-1.0, 1.0, 27)))
+    return gb, cam, kw
