@@ -175,11 +175,13 @@ template <int NB>
 SSVB_HD bool near_integer(float v) { return fabsf(v - rintf(v)) < kGuard * (NB / 32); }
 
 // Visibility mask of one slice: N_b sectors in N_b / 32 words, sector k in bit k % 32 of
-// word k / 32.
+// word k / 32.  Above 32 sectors a slice's mask also carries its number of set sectors,
+// kept up to date by cover().
 template <int NB>
 struct SMask {
     static constexpr int W = NB / 32;
     uint32_t w[W];
+    int n;
 };
 
 template <int NB>
@@ -187,7 +189,28 @@ SSVB_HD SMask<NB> mask_none() {
     SMask<NB> m;
 #pragma unroll
     for (int i = 0; i < SMask<NB>::W; ++i) m.w[i] = 0u;
+    m.n = 0;
     return m;
+}
+
+// Word I of 2^c mod 2^128, for c clamped to word I's span [32 I, 32 I + 32]: that is
+// 2^(c - 32 I) mod 2^32.  The 64-bit shift reads its amount mod 64, so the low half of
+// 2^(c mod 64) is word I for even I and the high half is word I for odd I (c = 32 I + 32
+// of an odd word wraps to 2^0, whose high half is 0, as it should be).
+template <int I>
+SSVB_HD uint32_t pow2_word(int c) {
+    c = min(max(c, 32 * I), 32 * I + 32);
+    const uint64_t p = 1ull << (c & 63);
+    return (I & 1) ? (uint32_t)(p >> 32) : (uint32_t)p;
+}
+
+template <int NB, int I = 0>
+SSVB_HD void range_words(SMask<NB>& m, int a, int b) {
+    if constexpr (I < SMask<NB>::W) {
+        // bits [a, b) of word I: 2^b - 2^a in that word, mod 2^32
+        m.w[I] = pow2_word<I>(b) - pow2_word<I>(a);
+        range_words<NB, I + 1>(m, a, b);
+    }
 }
 
 // sectors [a, b) for 0 <= a <= b <= N_b
@@ -197,11 +220,31 @@ SSVB_HD SMask<NB> mask_range(int a, int b) {
     if constexpr (NB == 32) {
         m.w[0] = range_bits(a, b);
     } else {
-#pragma unroll
-        for (int i = 0; i < SMask<NB>::W; ++i)
-            m.w[i] = range_bits(min(max(a - 32 * i, 0), 32), min(max(b - 32 * i, 0), 32));
+        range_words<NB>(m, a, b);
     }
+    m.n = 0;
     return m;
+}
+
+// B |= m; returns the number of sectors of m not already in B.  Above 32 sectors this is
+// the change in B's count (one popcount pass over the updated words, no m & ~B pass).
+template <int NB>
+SSVB_HD int cover(SMask<NB>& B, const SMask<NB>& m) {
+    if constexpr (NB == 32) {
+        const int c = popc32(m.w[0] & ~B.w[0]);
+        B.w[0] |= m.w[0];
+        return c;
+    } else {
+        int n = 0;
+#pragma unroll
+        for (int i = 0; i < SMask<NB>::W; ++i) {
+            B.w[i] |= m.w[i];
+            n += popc32(B.w[i]);
+        }
+        const int c = n - B.n;
+        B.n = n;
+        return c;
+    }
 }
 
 // m & ~B
@@ -458,8 +501,19 @@ SSVB_HD void march_sample(const FrameArgs& A, const SliceF& S, const ExactLds& L
         b = min(a + w, NB);
     }
     const SMask<NB> m = ok ? mask_range<NB>(a, b) : mask_none<NB>();
-    const SMask<NB> fresh = mask_and_not<NB>(m, B);
-    if (mask_any<NB>(fresh)) {
+    // newly covered sectors: at 32 sectors m & ~B before B |= m (below); above, cover()
+    // updates B and its count at once
+    SMask<NB> fresh_m;
+    int fresh = 0;
+    bool any;
+    if constexpr (NB == 32) {
+        fresh_m = mask_and_not<NB>(m, B);
+        any = mask_any<NB>(fresh_m);
+    } else {
+        fresh = cover<NB>(B, m);
+        any = fresh > 0;
+    }
+    if (any) {
         // indirect light from the newly covered sectors (Algorithm 1; Section 3.3)
         const float3 nj = load3<FMT < 0 ? -1 : (FMT & 1)>(A.normal, A.normal_pitch, A.normal_ch, A.normal_f16, X, Y);
         const float hs = s > 0 ? h : -h;
@@ -467,8 +521,8 @@ SSVB_HD void march_sample(const FrameArgs& A, const SliceF& S, const ExactLds& L
         const float njv = nj.x * vx + nj.y * vy + nj.z * vz;
         const float nje = nj.x * S.ex + nj.y * S.ey + nj.z * S.ez;
         const float ndj = fmaf(njv, c, nje * hs);
-        const float w = (float)mask_popc<NB>(fresh) * (1.0f / (float)NB) * fmaxf(ndp, 0.0f) * fmaxf(-ndj, 0.0f) *
-                        rcp_approx(fmaf(c, c, h * h));
+        const float w = (float)(NB == 32 ? mask_popc<NB>(fresh_m) : fresh) * (1.0f / (float)NB) *
+                        fmaxf(ndp, 0.0f) * fmaxf(-ndj, 0.0f) * rcp_approx(fmaf(c, c, h * h));
         if (w > 0.0f) {
             const float3 cj = load3<FMT < 0 ? -1 : (FMT >> 1)>(A.radiance, A.radiance_pitch, A.radiance_ch,
                                                               A.radiance_f16, X, Y);
@@ -477,8 +531,7 @@ SSVB_HD void march_sample(const FrameArgs& A, const SliceF& S, const ExactLds& L
             gib = fmaf(w, cj.z, gib);
         }
     }
-#pragma unroll
-    for (int k = 0; k < SMask<NB>::W; ++k) B.w[k] |= m.w[k];
+    if constexpr (NB == 32) B.w[0] |= m.w[0];
 }
 
 // One pixel of the gather.
@@ -611,7 +664,7 @@ SSVB_HD void gather_pixel_steps(const FrameArgs& A, ExactLds& L, int x, int y, i
             }
         }
         if (MODE != MODE_COMPUTE) continue;
-        ao_acc += 1.0f - (float)mask_popc<NB>(B) * (1.0f / (float)NB);
+        ao_acc += 1.0f - (float)(NB == 32 ? mask_popc<NB>(B) : B.n) * (1.0f / (float)NB);
         if (A.masks) {
             GMEM uint32_t* mk = (GMEM uint32_t*)((GMEM char*)A.masks + (int64_t)y * A.masks_pitch) +
                                 (int64_t)x * A.nd * SMask<NB>::W;

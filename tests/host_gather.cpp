@@ -76,3 +76,40 @@ extern "C" int host_gather(const ssvb_image* depth, const ssvb_image* normal, co
             for (int x = 0; x < A.W; ++x) upsample_pixel(A, x, y);
     return 0;
 }
+
+// The visibility-mask primitives at N_b = 32, 64 or 128 sectors, for exhaustive checks:
+// host_mask_range writes mask_range(a, b)'s N_b / 32 words; host_mask_cover ORs the ranges
+// [a[j], b[j]) into an empty mask in order with cover(), writing each step's newly covered
+// count and the final words and count.  Return 0, or -1 for another N_b.
+template <int NB>
+static void mask_range_words(int a, int b, uint32_t* out) {
+    const SMask<NB> m = mask_range<NB>(a, b);
+    for (int i = 0; i < SMask<NB>::W; ++i) out[i] = m.w[i];
+}
+
+template <int NB>
+static void mask_cover_run(const int* a, const int* b, int n, int* fresh, uint32_t* words, int* count) {
+    SMask<NB> B = mask_none<NB>();
+    for (int j = 0; j < n; ++j) fresh[j] = cover<NB>(B, mask_range<NB>(a[j], b[j]));
+    for (int i = 0; i < SMask<NB>::W; ++i) words[i] = B.w[i];
+    *count = NB == 32 ? popc32(B.w[0]) : B.n;
+}
+
+extern "C" int host_mask_range(int nb, int a, int b, uint32_t* out) {
+    switch (nb) {
+        case 32: mask_range_words<32>(a, b, out); return 0;
+        case 64: mask_range_words<64>(a, b, out); return 0;
+        case 128: mask_range_words<128>(a, b, out); return 0;
+        default: return -1;
+    }
+}
+
+extern "C" int host_mask_cover(int nb, const int* a, const int* b, int n, int* fresh, uint32_t* words,
+                               int* count) {
+    switch (nb) {
+        case 32: mask_cover_run<32>(a, b, n, fresh, words, count); return 0;
+        case 64: mask_cover_run<64>(a, b, n, fresh, words, count); return 0;
+        case 128: mask_cover_run<128>(a, b, n, fresh, words, count); return 0;
+        default: return -1;
+    }
+}

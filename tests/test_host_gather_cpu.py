@@ -46,6 +46,11 @@ def host():
         L.host_gather.argtypes = [ctypes.POINTER(B.ssvb_image)] * 3 + [
             ctypes.POINTER(B.ssvb_camera), ctypes.POINTER(B.ssvb_params), ctypes.POINTER(B.ssvb_outputs),
             ctypes.c_int32]
+        u32p, i32p = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int32)
+        L.host_mask_range.restype = ctypes.c_int32
+        L.host_mask_range.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, u32p]
+        L.host_mask_cover.restype = ctypes.c_int32
+        L.host_mask_cover.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p, u32p, i32p]
         yield L
 
 
@@ -234,3 +239,44 @@ def test_host_random_cases(host, case):
                                        half["gi"].astype(np.float64), half["ambient"].astype(np.float64))
         assert max(np.abs(half["ao"] - a).max(), np.abs(half["gi"] - g).max(),
                    np.abs(half["ambient"] - m).max()) <= 1e-5
+
+
+def _words(bits, nb):
+    """A Python int of sector bits as N_b / 32 little-endian 32-bit words."""
+    return [(bits >> (32 * i)) & 0xFFFFFFFF for i in range(nb // 32)]
+
+
+@pytest.mark.parametrize("nb", [32, 64, 128])
+def test_mask_range_exhaustive(host, nb):
+    """Every sector range [a, b), 0 <= a <= b <= N_b, against the bits it names."""
+    out = (ctypes.c_uint32 * (nb // 32))()
+    for a in range(nb + 1):
+        for b in range(a, nb + 1):
+            assert host.host_mask_range(nb, a, b, out) == 0
+            assert list(out) == _words(((1 << b) - 1) ^ ((1 << a) - 1), nb), (a, b)
+
+
+@pytest.mark.parametrize("nb", [32, 64, 128])
+def test_mask_cover_sequences(host, nb):
+    """Seeded sequences of ranges ORed in order: each step's newly covered count is the
+    number of its sectors not in the union so far, and the final words and count are the
+    union's (short, long, empty and full ranges mixed)."""
+    rng = np.random.default_rng(nb)
+    for trial in range(400):
+        n = int(rng.integers(1, 40))
+        a = rng.integers(0, nb + 1, n)
+        w = np.where(rng.random(n) < 0.7, rng.integers(0, 6, n), rng.integers(0, nb + 1, n))
+        b = np.minimum(a + w, nb)
+        a32, b32 = a.astype(np.int32), b.astype(np.int32)
+        fresh = np.zeros(n, np.int32)
+        words = (ctypes.c_uint32 * (nb // 32))()
+        count = ctypes.c_int32()
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        assert host.host_mask_cover(nb, a32.ctypes.data_as(i32p), b32.ctypes.data_as(i32p), n,
+                                    fresh.ctypes.data_as(i32p), words, ctypes.byref(count)) == 0
+        union = 0
+        for j in range(n):
+            r = ((1 << int(b[j])) - 1) ^ ((1 << int(a[j])) - 1)
+            assert fresh[j] == bin(r & ~union).count("1"), (trial, j)
+            union |= r
+        assert list(words) == _words(union, nb) and count.value == bin(union).count("1")
