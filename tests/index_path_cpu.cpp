@@ -9,13 +9,14 @@
 //   - every tile of every frame is claimed exactly once, and every computed pixel is
 //     reached by exactly lp lanes (each lane once) and lies inside the frame;
 //   - every byte the pixel's code reads (own depth, normal, radiance) or writes (AO, GI,
-//     ambient, slice masks) lies inside its buffer;
+//     ambient, slice masks) lies inside its buffer, and every input offset the kernels
+//     form in 32 bits, for any texel a sample can land on, equals the exact one;
 //   - the integer lattice never overflows int32 at the frame's extreme pixels, longest
 //     offsets and every direction of the slice-direction table;
 //   - sampled texels pass the kernels' on-screen test only inside the frame.
 // It runs the library's strip walk and, with --interleaved, a reconstruction of the
 // interleaved strip walk (strips 0, 8, 16, ... then 1, 9, 17, ...) that was timed and then
-// withdrawn.
+// withdrawn.  With --fuzz N SEED it draws N random inputs instead (see fuzz() below).
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -144,11 +145,18 @@ static void check_pixel(const FrameArgs& A, const Sizes& S, int x, int y, int li
     CHECK(x >= 0 && x < A.W && y >= 0 && y < A.H, "pixel (%d, %d) outside %dx%d", x, y, A.W, A.H);
     CHECK(x % A.sub == 0 && y % A.sub == 0, "pixel (%d, %d) not on the computed grid (sub %d)", x, y, A.sub);
     CHECK(li >= 0 && li < A.lp, "lane %d of %d", li, A.lp);
+    // the kernels' 32-bit offsets equal the exact ones (no wrap can land inside the buffer
+    // at the wrong texel) and lie inside the buffer
     const int64_t d = depth_off(A, x, y);
+    CHECK(d == (int64_t)y * A.depth_pitch + 4 * (int64_t)x, "depth offset %lld wrapped", (long long)d);
     CHECK(d >= 0 && d + 4 <= S.depth, "depth offset %lld of %lld", (long long)d, (long long)S.depth);
     const int64_t n = image_off(A.normal_pitch, A.normal_ch, A.normal_f16, x, y);
+    CHECK(n == (int64_t)y * A.normal_pitch + (int64_t)x * A.normal_ch * (A.normal_f16 ? 2 : 4),
+          "normal offset %lld wrapped", (long long)n);
     CHECK(n + 3 * (A.normal_f16 ? 2 : 4) <= S.normal, "normal offset %lld of %lld", (long long)n, (long long)S.normal);
     const int64_t r = image_off(A.radiance_pitch, A.radiance_ch, A.radiance_f16, x, y);
+    CHECK(r == (int64_t)y * A.radiance_pitch + (int64_t)x * A.radiance_ch * (A.radiance_f16 ? 2 : 4),
+          "radiance offset %lld wrapped", (long long)r);
     CHECK(r + 3 * (A.radiance_f16 ? 2 : 4) <= S.radiance, "radiance offset %lld", (long long)r);
     // outputs, as the kernels address them (row pointer + element)
     CHECK((int64_t)y * A.ao_pitch + (int64_t)x * 4 + 4 <= S.ao, "ao (%d, %d)", x, y);
@@ -161,6 +169,22 @@ static void check_pixel(const FrameArgs& A, const Sizes& S, int x, int y, int li
             CHECK(m >= 0 && m + 4 * words <= S.masks, "masks (%d, %d) slice %d", x, y, i);
         }
     }
+}
+
+// Every texel a sample can land on (any pixel of the frame, computed or not): the depth,
+// normal and radiance offsets the kernels form for it are exact and inside the images.
+static void check_texels(const FrameArgs& A, const Sizes& S) {
+    const int ne = A.normal_f16 ? 2 : 4, re = A.radiance_f16 ? 2 : 4;
+    for (int Y = 0; Y < A.H; ++Y)
+        for (int X = 0; X < A.W; ++X) {
+            const int64_t d = depth_off(A, X, Y), n = image_off(A.normal_pitch, A.normal_ch, A.normal_f16, X, Y),
+                          r = image_off(A.radiance_pitch, A.radiance_ch, A.radiance_f16, X, Y);
+            CHECK(d == (int64_t)Y * A.depth_pitch + 4 * (int64_t)X && d + 4 <= S.depth, "texel (%d, %d) depth", X, Y);
+            CHECK(n == (int64_t)Y * A.normal_pitch + (int64_t)X * A.normal_ch * ne && n + 3 * ne <= S.normal,
+                  "texel (%d, %d) normal", X, Y);
+            CHECK(r == (int64_t)Y * A.radiance_pitch + (int64_t)X * A.radiance_ch * re && r + 3 * re <= S.radiance,
+                  "texel (%d, %d) radiance", X, Y);
+        }
 }
 
 // One frame as gather_frame runs it: 8 XCD runs of the walk, 256 threads per tile.
@@ -201,6 +225,7 @@ static void emulate_frame(const FrameArgs& A) {
         }
     CHECK(wrong == 0, "%ld pixels not reached by exactly lp lanes (%dx%d, tile %dx%d, strip %d, lp %d, sub %d)", wrong,
           A.W, A.H, A.tile_w, A.tile_h, A.strip, A.lp, A.sub);
+    check_texels(A, S);
 }
 
 // The lattice at the frame's extreme pixels, for the longest offsets and every direction
@@ -235,6 +260,7 @@ static void check_lattice(const FrameArgs& A) {
                                       (long long)Y64);
                                 if ((unsigned)X < (unsigned)A.W && (unsigned)Y < (unsigned)A.H) {
                                     const int64_t d = depth_off(A, X, Y);
+                                    CHECK(d == (int64_t)Y * A.depth_pitch + 4 * (int64_t)X, "texel (%d, %d) wrapped", X, Y);
                                     CHECK(d + 4 <= sizes_of(A).depth, "texel (%d, %d)", X, Y);
                                 }
                             }
@@ -245,16 +271,11 @@ static void check_lattice(const FrameArgs& A) {
 // A batch as gather_batch runs it: per mask width, 8 runs of the packed tile list, claimed
 // by `wgs` workgroups in turn (each starting at its own XCD's run and keeping its frame
 // cursor across claims, as the kernel does).
-static void emulate_batch(const std::vector<Frame>& frames, LaunchShape shape, int wgs) {
-    std::vector<ssvb_frame> F(frames.size());
-    std::vector<FrameArgs> A(frames.size());
-    for (size_t i = 0; i < frames.size(); ++i) make_frame(frames[i], shape, true, A[i], &F[i]);
+static void emulate_batch_frames(const std::vector<ssvb_frame>& F, const std::vector<FrameArgs>& A,
+                                 const FrameTables& tab, int wgs) {
     static BatchDesc D;
     memset(&D, 0, sizeof D);
-    // the descriptor as the library builds it for a context with this (forced) launch shape
-    static FrameTables tab;
-    tab.forced = true;
-    tab.force = shape;
+    // the descriptor as the library builds it for a context with this launch shape
     build_batch(&tab, &D, F.data(), (int)F.size());
     // the descriptor's frame constants are the single-frame launch's, byte for byte (both
     // come from fill_frame, which clears the padding), so a batched frame runs the same
@@ -328,11 +349,198 @@ static void emulate_batch(const std::vector<Frame>& frames, LaunchShape shape, i
     }
 }
 
+
+static void emulate_batch(const std::vector<Frame>& frames, LaunchShape shape, int wgs) {
+    std::vector<ssvb_frame> F(frames.size());
+    std::vector<FrameArgs> A(frames.size());
+    for (size_t i = 0; i < frames.size(); ++i) make_frame(frames[i], shape, true, A[i], &F[i]);
+    static FrameTables tab;
+    tab.forced = true;
+    tab.force = shape;
+    emulate_batch_frames(F, A, tab, wgs);
+}
+
+// ---------------------------------------------------------------------------------------
+// fuzz: random frames, cameras, parameters, pitches, formats and launch shapes, each field
+// now and then outside what the library accepts.  Every input ssvb_validate accepts is
+// run through the index path as above; the rest must be rejected before any kernel.
+// ---------------------------------------------------------------------------------------
+struct FuzzRng {
+    uint64_t s;
+    uint64_t next() {  // splitmix64
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    int range(int lo, int hi) { return lo + (int)(next() % (uint64_t)(hi - lo + 1)); }  // [lo, hi]
+    double uni() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+    double logu(double lo, double hi) { return lo * pow(hi / lo, uni()); }
+    bool coin(double p) { return uni() < p; }
+};
+
+static void fuzz(long n, uint64_t seed, long& accepted, long& rejected, long& emulated, long& batches) {
+    FuzzRng R{seed};
+    std::vector<ssvb_frame> pending;
+    const double bad = 0.02;  // chance of each field being drawn outside the accepted range
+    static const int kTilesF[][3] = {{32, 8, 1}, {16, 16, 1}, {64, 4, 1}, {8, 32, 1}, {16, 8, 2}, {8, 16, 2},
+                                     {32, 4, 2}, {8, 8, 4},   {16, 4, 4}, {8, 4, 8},  {4, 8, 8},  {7, 9, 3}};
+    static FrameTables tab;
+    for (long it = 0; it < n; ++it) {
+        int W, H;
+        switch (R.range(0, 9)) {
+            case 0: W = R.range(1, 16384), H = R.range(1, 8); break;  // thin extremes
+            case 1: W = R.range(1, 8), H = R.range(1, 16384); break;
+            case 2: W = R.range(0, 3), H = R.range(0, 3); break;
+            default: W = R.range(1, 420), H = R.range(1, 300); break;
+        }
+        if (R.coin(bad)) W = R.coin(0.5) ? -R.range(1, 5) : 16385 + R.range(0, 5);
+        if (R.coin(bad)) H = R.coin(0.5) ? -R.range(1, 5) : 16385 + R.range(0, 5);
+        ssvb_camera cam;
+        cam.width = W, cam.height = H;
+        cam.fx = (float)R.logu(1e-3, 1e5);
+        cam.fy = R.coin(0.5) ? cam.fx : (float)R.logu(1e-3, 1e5);
+        cam.cx = (float)((R.uni() * 5.0 - 2.0) * (W > 0 ? W : 1));
+        cam.cy = (float)((R.uni() * 5.0 - 2.0) * (H > 0 ? H : 1));
+        for (int i = 0; i < 9; ++i) cam.view_to_world[i] = (float)(R.uni() * 2.0 - 1.0);
+        if (R.coin(bad)) cam.fx = R.coin(0.5) ? 0.0f : NAN;
+        if (R.coin(bad)) cam.cy = INFINITY;
+        ssvb_params p;
+        ssvb_default_params(&p);
+        p.slices = R.coin(0.8) ? R.range(1, 8) : R.range(1, 64);
+        p.steps = R.coin(0.7) ? R.range(1, 32) : R.range(1, 1024);
+        p.sectors = R.coin(0.5) ? 32 : 128;
+        {
+            static const int na[] = {1, 2, 4, 8, 16, 32};
+            p.ambient_samples = na[R.range(0, 5)];
+        }
+        p.radius = (float)R.logu(1e-4, 1e9);
+        p.thickness = R.coin(0.2) ? INFINITY : (float)(R.uni() * 2.0);
+        p.thickness_slope = R.coin(0.5) ? 0.0f : (float)(R.uni() * 0.2);
+        p.max_radius_px = R.coin(0.5) ? 0.0f : (float)R.logu(0.01, 40000.0);
+        p.min_step_q4 = R.range(1, 16);
+        p.step_distribution = R.range(0, 1);
+        p.resolution = R.range(1, 2);
+        p.hit_criterion = R.range(0, 1);
+        p.noise = R.range(0, 2);
+        p.seed = (uint32_t)R.next();
+        if (R.coin(bad)) p.slices = R.coin(0.5) ? 0 : 65;
+        if (R.coin(bad)) p.steps = R.coin(0.5) ? 0 : 1025;
+        if (R.coin(bad)) p.sectors = R.coin(0.5) ? 64 : 0;
+        if (R.coin(bad)) p.ambient_samples = R.coin(0.5) ? 3 : 64;
+        if (R.coin(bad)) p.radius = R.coin(0.5) ? -1.0f : NAN;
+        if (R.coin(bad)) p.max_radius_px = -1.0f;
+        if (R.coin(bad)) p.min_step_q4 = R.coin(0.5) ? 0 : 17;
+        if (R.coin(bad)) p.resolution = 3;
+        // inputs: formats, channels and pitches (padded rows, some spanning close to 4 GiB)
+        auto image = [&](uintptr_t base, bool depth) {
+            ssvb_image im;
+            const bool f16 = !depth && R.coin(0.5);
+            im.dtype = f16 ? SSVB_F16 : SSVB_F32;
+            im.channels = depth ? 1 : (R.coin(0.5) ? 3 : 4);
+            const int64_t es = f16 ? 2 : 4;
+            const int64_t row = (int64_t)(W > 0 ? W : 0) * im.channels * es;
+            im.ptr = (const void*)base;
+            switch (R.range(0, 3)) {
+                case 0: im.pitch_bytes = 0; break;
+                case 1: im.pitch_bytes = row + es * R.range(0, 64); break;
+                case 2: {  // as wide as the 4 GiB span allows
+                    const int64_t hmax = H > 1 ? H - 1 : 1;
+                    const int64_t room = ((int64_t)1 << 32) - row;
+                    int64_t pitch = room / hmax;
+                    pitch -= pitch % es;
+                    im.pitch_bytes = pitch >= row ? pitch - es * R.range(0, 3) : 0;
+                    if (im.pitch_bytes < row) im.pitch_bytes = 0;
+                    break;
+                }
+                default: im.pitch_bytes = row + es * R.range(0, 4096); break;
+            }
+            if (R.coin(bad)) im.pitch_bytes = row > es ? row - es : row + 1;
+            if (R.coin(bad)) im.ptr = (const void*)(base + 1);
+            if (R.coin(bad)) im.channels = depth ? 3 : 5;
+            if (R.coin(bad)) im.dtype = depth ? SSVB_F16 : (ssvb_dtype)7;
+            return im;
+        };
+        const ssvb_image depth = image(0x10000000ull, true);
+        const ssvb_image normal = image(0x1000000000ull, false);
+        const ssvb_image radiance = image(0x2000000000ull, false);
+        const bool masks = R.coin(0.4) && (p.resolution == 1 || R.coin(bad));  // no masks at half resolution
+        auto opitch = [&](int64_t row) -> int64_t {
+            if (R.coin(bad)) return row + 2;
+            return R.coin(0.5) ? 0 : row + 4 * R.range(0, 256);
+        };
+        const int64_t Wc = W > 0 ? W : 0;
+        ssvb_outputs o{(float*)0x3000000000ull, (float*)0x4000000000ull, (float*)0x5000000000ull,
+                       masks ? (uint32_t*)0x6000000000ull : nullptr, opitch(Wc * 4), opitch(Wc * 12), opitch(Wc * 12),
+                       masks ? opitch(Wc * (p.slices > 0 ? p.slices : 1) * (p.sectors > 0 ? p.sectors / 32 : 1) * 4)
+                             : 0};
+        const int ti = R.range(0, 11);
+        tab.forced = R.coin(0.7);
+        tab.force = LaunchShape{kTilesF[ti][0], kTilesF[ti][1], R.range(0, 9), kTilesF[ti][2]};
+        if (ssvb_validate(&depth, &normal, &radiance, &cam, &p, &o) != SSVB_OK) {
+            ++rejected;
+            continue;
+        }
+        ++accepted;
+        if ((int64_t)W * H == 0) continue;
+        FrameArgs A;
+        fill_frame(A, &tab, &depth, &normal, &radiance, &cam, &p, &o);
+        CHECK(A.tile_w * A.tile_h * A.lp == 256 && A.strip >= 1 && A.strip <= (A.tiles_x > 0 ? A.tiles_x : 1),
+              "launch shape %dx%d lp %d strip %d", A.tile_w, A.tile_h, A.lp, A.strip);
+        check_lattice(A);
+        if ((int64_t)W * H <= 300000) {
+            emulate_frame(A);
+            ++emulated;
+        }
+        // small frames also go into batches of up to kMaxBatch, as ssvb_compute_batch packs
+        // them (frames of at most kPackTiles tiles), under one context launch shape
+        if ((uint32_t)A.tiles_x * (uint32_t)A.tiles_y <= kPackTiles && (int64_t)W * H <= 60000) {
+            pending.push_back(ssvb_frame{depth, normal, radiance, cam, p, o});
+            if ((int)pending.size() == R.range(1, kMaxBatch) || (int)pending.size() == kMaxBatch) {
+                static FrameTables btab;
+                const int bi = R.range(0, 11);
+                btab.forced = R.coin(0.7);
+                btab.force = LaunchShape{kTilesF[bi][0], kTilesF[bi][1], R.range(0, 9), kTilesF[bi][2]};
+                std::vector<FrameArgs> BA(pending.size());
+                for (size_t i = 0; i < pending.size(); ++i) {
+                    const ssvb_frame& f = pending[i];
+                    fill_frame(BA[i], &btab, &f.depth, &f.normal, &f.radiance, &f.camera, &f.params, &f.out);
+                }
+                // the packed list holds only frames small enough under this shape
+                std::vector<ssvb_frame> keep;
+                std::vector<FrameArgs> keepA;
+                for (size_t i = 0; i < pending.size(); ++i)
+                    if ((uint32_t)BA[i].tiles_x * (uint32_t)BA[i].tiles_y <= kPackTiles) {
+                        keep.push_back(pending[i]);
+                        keepA.push_back(BA[i]);
+                    }
+                static const int kWgs[] = {1, 7, 1024};
+                emulate_batch_frames(keep, keepA, btab, kWgs[R.range(0, 2)]);
+                ++batches;
+                pending.clear();
+            }
+        }
+    }
+}
+
 int main(int argc, char** argv) {
     bool quick = false;
+    long fuzz_n = 0;
+    uint64_t fuzz_seed = 1;
     for (int i = 1; i < argc; ++i) {
         if (!strcmp(argv[i], "--interleaved")) g_interleaved = true;
         if (!strcmp(argv[i], "--quick")) quick = true;
+        if (!strcmp(argv[i], "--fuzz") && i + 2 < argc) {
+            fuzz_n = atol(argv[i + 1]);
+            fuzz_seed = strtoull(argv[i + 2], nullptr, 10);
+        }
+    }
+    if (fuzz_n > 0) {
+        long acc = 0, rej = 0, emu = 0, bat = 0;
+        fuzz(fuzz_n, fuzz_seed, acc, rej, emu, bat);
+        printf("fuzz: %ld inputs, %ld accepted (%ld emulated), %ld rejected, %ld batches, %ld checks, %ld failed\n",
+               fuzz_n, acc, emu, rej, bat, g_checks, g_fail);
+        return g_fail != 0;
     }
     // the launch shapes of the autotuner (tile w, h, lanes) x strips, and the default
     static const int kTiles[][3] = {{32, 8, 1}, {16, 16, 1}, {64, 4, 1}, {8, 32, 1}, {16, 8, 2}, {8, 16, 2},
