@@ -333,6 +333,129 @@ def pin_horizon_uniform_integral(O):
                 assert abs((1 - occ / nb) - vis) <= 1.0 / nb + 1e-12, (nb, idx, sl, 1 - occ / nb, vis)
 
 
+def _edge_u(th, delta=1e-9):
+    """(u, tie) of an angle th from the projected normal: u = (th + pi/2)/pi after clamping
+    to the hemisphere; an angle within delta of an edge is a tie (rounding decides on
+    which side it falls)."""
+    if th <= -math.pi / 2 - delta:
+        return 0.0, False
+    if th >= math.pi / 2 + delta:
+        return 1.0, False
+    if abs(th + math.pi / 2) <= delta or abs(th - math.pi / 2) <= delta:
+        return None, True
+    return (th + math.pi / 2) / math.pi, False
+
+
+def pin_pseudocode_horizon(O):
+    """PSEUDOCODE criterion (Algorithm 1: floor of the start, ceil of the width), t = inf:
+    a + side sample covers [theta_f, pi/2], so it sets [floor(N_b u_f), floor(N_b u_f) +
+    ceil(N_b (1 - u_f))) = [floor(N_b u_f), N_b); a - side sample covers [-pi/2, theta_f]
+    and sets [0, ceil(N_b u_f)).  Per slice the mask is therefore the + side horizon's
+    [floor, N_b) and the - side horizon's [0, ceil), with the horizons from the
+    independent GTAO search (plain 3D geometry of texel centres)."""
+    gb, cam, _ = tiny_scene()
+    k, steps = 2, 6
+    prm = integer_step_params(O, k, steps, thickness=INF, hit_criterion=O.PSEUDOCODE)
+    valid = np.argwhere(gb["depth"] > 0)
+    sel = valid[:: max(1, len(valid) // 300)]
+    ys, xs = sel[:, 0], sel[:, 1]
+    r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm, pixels=(ys, xs),
+                  return_masks=True)
+    hz, _ = _horizons_integer_lattice(gb, cam, k, steps, ys, xs)
+    checked = differs_from_round = 0
+    for idx in range(hz.shape[0]):
+        for sl in range(2):
+            want, want_round, tie = 0, 0, False
+            for si, s in enumerate((1, -1)):
+                th = hz[idx, sl, si]
+                if np.isnan(th):
+                    continue
+                u, t = _edge_u(th)
+                if t:
+                    tie = True
+                    continue
+                x = 32 * u
+                if abs(x - round(x)) < 1e-7 or abs(x + 0.5 - round(x + 0.5)) < 1e-7:
+                    tie = True
+                if s == 1:
+                    want |= range_mask(math.floor(x), 32)
+                    want_round |= range_mask(math.floor(x + 0.5), 32)
+                else:
+                    want |= range_mask(0, math.ceil(x))
+                    want_round |= range_mask(0, math.floor(x + 0.5))
+            if tie:
+                continue
+            assert int(r["masks"][idx, sl]) == want, (idx, sl, hex(int(r["masks"][idx, sl])), hex(want))
+            checked += 1
+            differs_from_round += want != want_round
+    assert checked > 200 and differs_from_round > 100, (checked, differs_from_round)
+
+
+def pin_pseudocode_wall(O):
+    """PSEUDOCODE on the crease (a wall rising at alpha from a plane facing the camera).
+    Centre row, t = inf: the + side covers [floor(32 u), 32) from the highest wall
+    sample's elevation.  Hinge pixel, finite t (and slope): every wall sample's front
+    direction is the wall's, u_f = 1 - alpha/pi; the widest interval is the nearest
+    sample's, up to its back angle atan2(l cos a, l sin a - t), so the mask is
+    [floor(32 u_f), floor(32 u_f) + ceil(32 (u_b - u_f))).  The samples on the plane lie
+    exactly in the pixel's tangent plane, on the - side's edge, where the ceiling of a
+    zero width is decided by rounding: bit 0 of slice 0 and every bit of slice 1 (all on
+    the plane) are left out, except that slice 1 may hold only edge bits."""
+    size, D, k, steps = 41, 4.0, 2, 6
+    c = size // 2
+    checked = 0
+    for deg in (30.0, 37.0, 45.0, 60.0):
+        alpha = math.radians(deg)
+        gb, cam = _crease(alpha, size, D)
+        f = float(np.float32(cam.fx))
+        prm = integer_step_params(O, k, steps, thickness=INF, hit_criterion=O.PSEUDOCODE)
+        xs = np.arange(c - 12, c + 1)
+        ys = np.full_like(xs, c)
+        r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                      pixels=(ys, xs), return_masks=True)
+        for idx, x in enumerate(xs):
+            z_p = float(gb["depth"][c, x])
+            p = np.array([z_p * (x + 0.5 - c - 0.5) / f, 0.0, -z_p])
+            beta = 0.0
+            for j in range(steps):
+                X = x + k * (j + 1)
+                if X >= size:
+                    break
+                z = float(gb["depth"][c, X])
+                P = np.array([z * (X + 0.5 - c - 0.5) / f, 0.0, -z])
+                d = P - p
+                beta = max(beta, math.atan2(d[2], d[0]))
+            x32 = 32 * (1 - beta / math.pi)
+            if beta == 0.0 or abs(x32 - round(x32)) < 1e-6:
+                continue
+            want = range_mask(math.floor(x32), 32)
+            got = int(r["masks"][idx, 0])
+            assert got & ~1 == want & ~1, (deg, x, hex(got), hex(want))
+            assert int(r["masks"][idx, 1]) & ~((1 << 31) | 1) == 0
+            checked += 1
+        for t0, slope in ((0.02, 0.0), (0.1, 0.0), (0.3, 0.0), (0.8, 0.0), (0.0, 0.05), (0.1, 0.1)):
+            t = t0 + slope * D
+            prm = integer_step_params(O, k, steps, thickness=t0, thickness_slope=slope,
+                                      hit_criterion=O.PSEUDOCODE)
+            r = O.compute(gb["depth"], gb["normal"], gb["radiance"], ocam(O, cam), prm,
+                          pixels=([c], [c]), return_masks=True)
+            X = c + k
+            z = float(gb["depth"][c, X])
+            d = np.array([z * (X - c) / f, 0.0, D - z])
+            th_b = min(math.pi / 2, math.atan2(d[0], d[2] - t))
+            u_f = 1 - alpha / math.pi
+            u_b = (th_b + math.pi / 2) / math.pi
+            a, wd = 32 * u_f, 32 * (u_b - u_f)
+            if min(abs(a - round(a)), abs(wd - round(wd))) < 1e-6:
+                continue
+            lo = math.floor(a)
+            want = range_mask(lo, min(lo + math.ceil(wd), 32))
+            got = int(r["masks"][0, 0])
+            assert got & ~1 == want & ~1, (deg, t, hex(got), hex(want))
+            checked += 1
+    assert checked > 40, checked
+
+
 def gtao_inner(h1, h2, gamma):
     """GTAO's closed-form inner integral of cos(theta - gamma) |sin theta| over the
     visible arc [h1, h2] (h1 <= 0 <= h2, angles from v), Jimenez et al. 2016, which
@@ -1106,6 +1229,8 @@ ALL_PINS = [
     pin_gtao_cosine_closed_form,
     pin_wall_infinite_thickness,
     pin_wall_finite_thickness,
+    pin_pseudocode_horizon,
+    pin_pseudocode_wall,
     pin_wall_indirect,
     pin_wall_random_rotations,
     pin_bruteforce_sound,

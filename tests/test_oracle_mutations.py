@@ -94,6 +94,12 @@ MUTATIONS = {
     "sequence light kept in FP64": (".astype(light_dtype)", ""),
     "denoise background overwritten": ("sig = np.where(fg[..., None], acc / wsum[..., None], sig)",
                                        "sig = acc / wsum[..., None]"),
+    "pseudocode width floored": ("b = np.ceil(arg1).astype(np.int64)", "b = np.floor(arg1).astype(np.int64)"),
+    "pseudocode start rounded": ("arg0, arg1 = nb * u_lo, nb * (u_hi - u_lo)",
+                                 "arg0, arg1 = nb * u_lo + 0.5, nb * (u_hi - u_lo)"),
+    "pseudocode width read as the end": ("b = np.minimum(a + b, nb)", "b = np.minimum(b, nb)"),
+    "pseudocode width from the upper angle": ("arg0, arg1 = nb * u_lo, nb * (u_hi - u_lo)",
+                                              "arg0, arg1 = nb * u_lo, nb * u_hi"),
 }
 
 
@@ -112,7 +118,8 @@ def _mutant(name, old, new):
 FIRST = [("denoise", "pin_denoise"), ("a-trous", "pin_denoise"), ("plane distance", "pin_denoise"),
          ("plane falloff", "pin_denoise"), ("normal weight", "pin_denoise"), ("sequence", "pin_bounce_sequence"),
          ("SH ", "pin_sh_basis"), ("bounce", "pin_multi_bounce"), ("upsampling", "pin_half_resolution"),
-         ("half resolution", "pin_half_resolution"), ("quadratic", "pin_quadratic_steps")]
+         ("half resolution", "pin_half_resolution"), ("quadratic", "pin_quadratic_steps"),
+         ("pseudocode", "pin_pseudocode_horizon")]
 
 
 def pin_order(name):
