@@ -121,7 +121,8 @@ def test_sequence_equals_composition(ctx, light_dtype, resolution, fp16_inputs):
 
 def test_sequence_feedback_converges(ctx):
     """The lit crease with FIXED noise (the same slices every frame): the GI grows frame
-    after frame toward a fixed point, as the oracle's sequence does."""
+    after frame to a fixed point (reached exactly in FP32 within a few frames), as the
+    oracle's sequence does."""
     import torch
     from paper_2301_11376_amd import Sequence
     cam = make_camera(48, 32, fov_y_deg=70, pitch_deg=-30)
@@ -146,7 +147,9 @@ def test_sequence_feedback_converges(ctx):
             sums.append(float(gi.sum()))
         inc = np.diff(sums)
         log(f"GI sums {sums}")
-        assert np.all(inc > 0) and inc[-1] < inc[0]
+        # rises, never falls, and settles (in FP32 the fixed point is reached exactly
+        # within a few frames, after which the increments are 0)
+        assert inc[0] > 0 and np.all(inc >= 0) and inc[-1] < 1e-2 * inc[0]
     finally:
         seq.close()
 
