@@ -19,6 +19,8 @@
 // run, slice 0 of every tile, then slice 1, ...; the per-slice partial sums would be
 // added in slice order afterwards).  Layout "packed" puts a texel's normal and radiance
 // in one 16-byte (FP16) or 32-byte (FP32) record, so one sample's two reads share a line.
+// A layout suffix "+d<w>x<h>" (w h = 32, e.g. "planar+d8x4") stores depth in 2D blocks, a
+// 128-byte line holding w x h texels instead of 32 texels of one row.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -104,6 +106,7 @@ struct Config {
     int W, H, nd, ns, fp16;
     std::string order, layout;
     int chunk = 0;
+    int dlw = 0, dlh = 0;  // depth line shape in texels ("...+d<w>x<h>" layouts), 0: rows
 };
 
 // The reads of one pixel, labelled with their load instruction: 0 centre depth, 1 centre
@@ -159,7 +162,17 @@ struct Model {
     void lines_of(const Read& r, uint64_t out[2], int& n) const {
         uint64_t a = r.addr;
         int bytes = r.bytes;
-        if (C.layout == "packed" && r.kind != DEPTH) {
+        if (r.kind == DEPTH && C.dlw > 0) {
+            // depth in 2D blocks: one 128-byte line holds dlw x dlh texels (dlw * dlh = 32),
+            // lines row-major over the grid of blocks
+            const uint64_t t = r.addr / 4;
+            const uint64_t x = t % (uint64_t)A.W, y = t / (uint64_t)A.W;
+            const uint64_t bw = ((uint64_t)A.W + C.dlw - 1) / C.dlw;
+            out[0] = (y / C.dlh) * bw + x / C.dlw;
+            n = 1;
+            return;
+        }
+        if (C.layout.rfind("packed", 0) == 0 && r.kind != DEPTH) {
             const int es = A.normal_f16 ? 2 : 4;
             const uint64_t t = (r.addr & ((1ull << 40) - 1)) / (uint64_t)(3 * es);
             const int rec = A.normal_f16 ? 16 : 32;
@@ -243,6 +256,14 @@ int main(int argc, char** argv) {
     C.order = argv[12];
     const double fraction = atof(argv[13]);
     C.layout = argc > 14 ? argv[14] : "planar";
+    {
+        const size_t at = C.layout.find("+d");
+        if (at != std::string::npos && sscanf(C.layout.c_str() + at + 2, "%dx%d", &C.dlw, &C.dlh) == 2 &&
+            C.dlw * C.dlh != 32) {
+            fprintf(stderr, "a depth line holds 32 texels: %dx%d\n", C.dlw, C.dlh);
+            return 2;
+        }
+    }
     const int wg_per_cu = argc > 15 ? atoi(argv[15]) : 4;
     g_hash_sets = argc > 16 && !strcmp(argv[16], "hash");
     if (C.order.rfind("slice", 0) == 0) C.chunk = atoi(C.order.c_str() + 5);

@@ -2,9 +2,9 @@
 library and the kernels' per-pixel header, runs on the 128x128 workload in the library's
 strip order, a slice-major order and the packed normal + radiance layout, and reports
 self-consistent figures: L2 misses never above L2 requests, at most 64 lines per load
-instruction, the indirect term's normal and radiance reads present, and with the packed
+instruction, the indirect term's normal and radiance reads present, with the packed
 layout no more radiance requests reaching the L2 than with separate images (a sample's two
-reads then share a line)."""
+reads then share a line), and with depth in 8 x 4-texel lines the same load instructions."""
 import os
 import re
 import subprocess
@@ -52,7 +52,8 @@ def test_cache_model_runs_and_is_consistent():
             np.ascontiguousarray(gb[k]).tofile(f)
             files.append(f)
         runs = {}
-        for order, layout in (("strip", "planar"), ("slice64", "planar"), ("strip", "packed")):
+        for order, layout in (("strip", "planar"), ("slice64", "planar"), ("strip", "packed"),
+                              ("strip", "planar+d8x4")):
             args = [exe, *files, "128", "128", "0", str(w["slices"]), str(w["steps"]), str(w["radius"]),
                     str(w["thickness"]), str(w["seed"]), order, "1.0", layout]
             r = subprocess.run(args, capture_output=True, text=True, timeout=300)
@@ -69,3 +70,6 @@ def test_cache_model_runs_and_is_consistent():
     # the same samples in every order
     assert runs[("strip", "planar")]["depth"][0] <= runs[("slice64", "planar")]["depth"][0]
     assert runs[("strip", "packed")]["radiance"][2] <= runs[("strip", "planar")]["radiance"][2]
+    # a 2D depth layout changes addresses only: the same load instructions and samples
+    assert runs[("strip", "planar+d8x4")]["depth"][0] == runs[("strip", "planar")]["depth"][0]
+    assert runs[("strip", "planar+d8x4")]["normal"][:2] == runs[("strip", "planar")]["normal"][:2]
