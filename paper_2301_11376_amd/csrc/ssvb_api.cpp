@@ -358,6 +358,55 @@ void build_batch(const FrameTables* tab, BatchDesc* D, const ssvb_frame* frames,
     }
 }
 
+// Arguments of one denoising pass from `in` to `out` (validated inputs).
+void fill_denoise(DenoiseArgs& D, const ssvb_image* depth, const ssvb_image* normal, const ssvb_camera* camera,
+                  const ssvb_denoise_params* dp, const ssvb_outputs* in, const ssvb_outputs* out) {
+    const int W = camera->width, H = camera->height;
+    D = DenoiseArgs{};
+    D.depth = (const float*)depth->ptr;
+    D.depth_pitch = depth->pitch_bytes ? depth->pitch_bytes : (int64_t)W * 4;
+    D.normal = (const char*)normal->ptr;
+    D.normal_ch = normal->channels;
+    D.normal_f16 = normal->dtype == SSVB_F16;
+    D.normal_pitch = normal->pitch_bytes ? normal->pitch_bytes : (int64_t)W * normal->channels * elem_size(normal->dtype);
+    D.W = W;
+    D.H = H;
+    D.g = dp->resolution;
+    D.gw = (W + D.g - 1) / D.g;
+    D.gh = (H + D.g - 1) / D.g;
+    D.tiles_x = (D.gw + kDenoiseTile - 1) / kDenoiseTile;
+    D.tiles = D.tiles_x * ((D.gh + kDenoiseTile - 1) / kDenoiseTile);
+    D.cx = camera->cx;
+    D.cy = camera->cy;
+    D.inv_fx = (float)(1.0 / camera->fx);
+    D.inv_fy = (float)(1.0 / camera->fy);
+    D.inv_sigma = isinf(dp->plane_sigma) ? 0.0f : (float)(1.0 / (double)dp->plane_sigma);
+    D.normal_power = dp->normal_power;
+    D.in_ao = in->ao, D.in_gi = in->gi, D.in_amb = in->ambient;
+    D.in_ao_pitch = in->ao_pitch_bytes ? in->ao_pitch_bytes : (int64_t)W * 4;
+    D.in_gi_pitch = in->gi_pitch_bytes ? in->gi_pitch_bytes : (int64_t)W * 12;
+    D.in_amb_pitch = in->ambient_pitch_bytes ? in->ambient_pitch_bytes : (int64_t)W * 12;
+    D.out_ao = out->ao, D.out_gi = out->gi, D.out_amb = out->ambient;
+    D.out_ao_pitch = out->ao_pitch_bytes ? out->ao_pitch_bytes : (int64_t)W * 4;
+    D.out_gi_pitch = out->gi_pitch_bytes ? out->gi_pitch_bytes : (int64_t)W * 12;
+    D.out_amb_pitch = out->ambient_pitch_bytes ? out->ambient_pitch_bytes : (int64_t)W * 12;
+}
+
+// Frame constants of the half-resolution fill of the signal set `out` (the upsampler reads
+// depth and writes the uncomputed pixels in place).
+void fill_upsample(FrameArgs& A, const ssvb_image* depth, const ssvb_camera* camera, const ssvb_outputs* out) {
+    const int W = camera->width, H = camera->height;
+    memset(&A, 0, sizeof A);
+    A.depth = (const float*)depth->ptr;
+    A.depth_pitch = depth->pitch_bytes ? depth->pitch_bytes : (int64_t)W * 4;
+    A.W = W;
+    A.H = H;
+    A.ao = out->ao, A.gi = out->gi, A.amb = out->ambient;
+    A.ao_pitch = out->ao_pitch_bytes ? out->ao_pitch_bytes : (int64_t)W * 4;
+    A.gi_pitch = out->gi_pitch_bytes ? out->gi_pitch_bytes : (int64_t)W * 12;
+    A.amb_pitch = out->ambient_pitch_bytes ? out->ambient_pitch_bytes : (int64_t)W * 12;
+}
+
 hipError_t batch_grid_size(int device, int grid[2]) {
     hipDeviceProp_t prop;
     hipError_t e = hipGetDeviceProperties(&prop, device);
@@ -861,38 +910,7 @@ ssvb_status ssvb_denoise(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     if (dp->passes > 1 && (sets_overlap(in, tmp, W, H) || sets_overlap(tmp, out, W, H)))
         return fail(SSVB_ERR_INVALID_ARG, "tmp overlaps in or out");
 
-    DenoiseArgs D{};
-    D.depth = (const float*)depth->ptr;
-    D.depth_pitch = depth->pitch_bytes ? depth->pitch_bytes : (int64_t)W * 4;
-    D.normal = (const char*)normal->ptr;
-    D.normal_ch = normal->channels;
-    D.normal_f16 = normal->dtype == SSVB_F16;
-    D.normal_pitch = normal->pitch_bytes ? normal->pitch_bytes : (int64_t)W * normal->channels * elem_size(normal->dtype);
-    D.W = W;
-    D.H = H;
-    D.g = dp->resolution;
-    D.gw = (W + D.g - 1) / D.g;
-    D.gh = (H + D.g - 1) / D.g;
-    D.tiles_x = (D.gw + kDenoiseTile - 1) / kDenoiseTile;
-    D.tiles = D.tiles_x * ((D.gh + kDenoiseTile - 1) / kDenoiseTile);
-    D.cx = camera->cx;
-    D.cy = camera->cy;
-    D.inv_fx = (float)(1.0 / camera->fx);
-    D.inv_fy = (float)(1.0 / camera->fy);
-    D.inv_sigma = isinf(dp->plane_sigma) ? 0.0f : (float)(1.0 / (double)dp->plane_sigma);
-    D.normal_power = dp->normal_power;
-    auto set_in = [&](const ssvb_outputs* o) {
-        D.in_ao = o->ao, D.in_gi = o->gi, D.in_amb = o->ambient;
-        D.in_ao_pitch = o->ao_pitch_bytes ? o->ao_pitch_bytes : (int64_t)W * 4;
-        D.in_gi_pitch = o->gi_pitch_bytes ? o->gi_pitch_bytes : (int64_t)W * 12;
-        D.in_amb_pitch = o->ambient_pitch_bytes ? o->ambient_pitch_bytes : (int64_t)W * 12;
-    };
-    auto set_out = [&](const ssvb_outputs* o) {
-        D.out_ao = o->ao, D.out_gi = o->gi, D.out_amb = o->ambient;
-        D.out_ao_pitch = o->ao_pitch_bytes ? o->ao_pitch_bytes : (int64_t)W * 4;
-        D.out_gi_pitch = o->gi_pitch_bytes ? o->gi_pitch_bytes : (int64_t)W * 12;
-        D.out_amb_pitch = o->ambient_pitch_bytes ? o->ambient_pitch_bytes : (int64_t)W * 12;
-    };
+    DenoiseArgs D;
     hipStream_t stream = (hipStream_t)hip_stream;
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -902,20 +920,13 @@ ssvb_status ssvb_denoise(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     for (int i = 0; i < dp->passes && e == hipSuccess; ++i) {
         // the passes alternate so that the last one writes `out`
         const ssvb_outputs* dst = ((dp->passes - 1 - i) % 2 == 0) ? out : tmp;
-        set_in(src);
-        set_out(dst);
+        fill_denoise(D, depth, normal, camera, dp, src, dst);
         e = launch_denoise(D, i, stream);
         src = dst;
     }
     if (e == hipSuccess && dp->resolution == 2) {
         FrameArgs A;
-        memset(&A, 0, sizeof A);
-        A.depth = D.depth;
-        A.depth_pitch = D.depth_pitch;
-        A.W = W;
-        A.H = H;
-        A.ao = out->ao, A.gi = out->gi, A.amb = out->ambient;
-        A.ao_pitch = D.out_ao_pitch, A.gi_pitch = D.out_gi_pitch, A.amb_pitch = D.out_amb_pitch;
+        fill_upsample(A, depth, camera, out);
         e = launch_upsample(A, stream);
     }
     if (prev != ctx->device) (void)hipSetDevice(prev);

@@ -1,6 +1,6 @@
 // Host-side pieces shared by the C ABI (ssvb_api.cpp) and the request loop
-// (ssvb_server.cpp): frame constants, launch-shape tables, batch descriptor slots,
-// launchers and error reporting.
+// (ssvb_server.cpp): frame and denoiser constants, launch-shape tables, batch descriptor
+// slots, launchers and error reporting.
 #ifndef SSVB_HOST_H
 #define SSVB_HOST_H
 
@@ -8,6 +8,7 @@
 #include <string>
 #include <tuple>
 
+#include "ssvb_denoise.h"
 #include "ssvb_internal.h"
 
 namespace ssvb {
@@ -77,6 +78,12 @@ hipError_t launch_debug_endpoints(const FrameArgs& A, float* out, hipStream_t st
 hipError_t enqueue_batch(const BatchDesc* d_desc, const BatchDesc* h_desc, uint32_t* d_queues, const int grid[2],
                          int kinds, hipStream_t s);
 int batch_blocks_per_cu(int sectors);
+
+// Arguments of one denoising pass reading `in` and writing `out`, and the frame constants
+// of the half-resolution fill of `out` (inputs already validated by ssvb_denoise).
+void fill_denoise(DenoiseArgs& D, const ssvb_image* depth, const ssvb_image* normal, const ssvb_camera* camera,
+                  const ssvb_denoise_params* dp, const ssvb_outputs* in, const ssvb_outputs* out);
+void fill_upsample(FrameArgs& A, const ssvb_image* depth, const ssvb_camera* camera, const ssvb_outputs* out);
 
 // The argument checks of ssvb_inject_bounce (nothing launched).
 ssvb_status validate_bounce(int32_t width, int32_t height, const ssvb_image* direct, const ssvb_image* albedo,
