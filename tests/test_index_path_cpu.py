@@ -62,14 +62,14 @@ def test_interleaved_walk_reconstruction_index_path(emulator):
 
 @pytest.mark.parametrize("seed", [7, 2024])
 def test_validated_inputs_keep_the_index_path_in_bounds(emulator, seed):
-    """3,000 random inputs (frames from 0x0 to 16384-wide strips, cameras with any principal
+    """2,000 random inputs (frames from 0x0 to 16384-wide strips, cameras with any principal
     point and focal lengths from 1e-3 to 1e5, every parameter over its range, FP16 / FP32,
     3 / 4 channels, pitches up to the 4 GiB span, forced and default launch shapes), each
     field now and then outside what the library accepts: every input ssvb_validate accepts
     runs the whole per-frame emulation (tiles, lanes, every texel's 32-bit offsets exact,
     outputs in bounds) and the lattice check; the small ones also run in random batches of
     up to 64 frames under a random context launch shape (descriptor, packed list, cursor)."""
-    out = run(emulator, "--fuzz", "3000", str(seed))
+    out = run(emulator, "--fuzz", "2000", str(seed))
     m = re.search(r"fuzz: (\d+) inputs, (\d+) accepted \((\d+) emulated\), (\d+) rejected, (\d+) batches", out)
     n, acc, emu, rej, bat = (int(v) for v in m.groups())
     assert acc + rej == n and acc >= 0.4 * n and emu >= 0.9 * acc and bat >= 10
