@@ -503,8 +503,16 @@ def serve_leg(ctx, pool, n_requests, rates):
             st0 = srv.stats()
             lat, wall = run(list(sched), len(reqs))
             st = srv.stats()
-            keep = np.array(lat[200:]) if len(lat) > 400 else np.array(lat)
+            first = 200 if len(lat) > 400 else 0
+            keep = np.array(lat[first:])
             samples = sum(samples_of(r) for r in reqs)
+            # where the tail comes from: latency per resolution (a large frame's own work
+            # against small frames waiting behind it)
+            by_res = {}
+            for r, lt in zip(reqs[first:], lat[first:]):
+                by_res.setdefault(f"{r['width']}x{r['height']}", []).append(lt)
+            by_res = {k: {"n": len(v), "p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99))}
+                      for k, v in sorted(by_res.items(), key=lambda kv: int(kv[0].split("x")[0]))}
             res = {"rate_fraction_of_saturated": frac, "rate_hz": lam, "requests": len(reqs),
                    "discarded_warmup": len(reqs) - len(keep), "p50_ms": float(np.percentile(keep, 50)),
                    "p99_ms": float(np.percentile(keep, 99)), "mean_ms": float(keep.mean()),
@@ -513,7 +521,8 @@ def serve_leg(ctx, pool, n_requests, rates):
                    "frames_per_round": (st["frames_in_rounds"] - st0["frames_in_rounds"]) /
                                        max(1, st["rounds"] - st0["rounds"]),
                    "admitted_while_running": st["admitted_while_running"] - st0["admitted_while_running"],
-                   "max_running_rounds": st["max_running_rounds"], "arena_peak_bytes": st["arena_peak"]}
+                   "max_running_rounds": st["max_running_rounds"], "arena_peak_bytes": st["arena_peak"],
+                   "by_resolution": by_res}
             print(f"serve at {frac:.2f} x saturated ({lam:.1f}/s): p50 {res['p50_ms']:.2f} ms, "
                   f"p99 {res['p99_ms']:.2f} ms, {res['frames_per_s']:.1f} frames/s", file=sys.stderr, flush=True)
             results.append(res)
