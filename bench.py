@@ -538,10 +538,12 @@ def serve_leg(ctx, pool, n_requests, rates):
             "plain_frames_per_s": plain_fps, "served_vs_plain": sat_fps / plain_fps, "rates": results}
 
 
-def frame_leg(ctx, name, gb, cam, w, scene, steps, warmup, own_noise=True):
+def frame_leg(ctx, name, gb, cam, w, scene, steps, warmup, own_noise=True, tune=False):
     """One workload's frame, inputs resident in HBM: `warmup` untimed launches, then `steps`
     launches timed by the host clock around the loop (ms/frame, Gsamples/s) and by HIP
-    events on the stream the kernels run on (the gather kernel's duration, the roofline)."""
+    events on the stream the kernels run on (the gather kernel's duration, the roofline).
+    With `tune` the library's autotuner first picks the frame class's launch shape (untimed),
+    else the context's default shape runs."""
     import torch
     from paper_2301_11376_amd import Camera, Params, NOISE_NAMES
     dev = torch.device("cuda:0")
@@ -554,6 +556,10 @@ def frame_leg(ctx, name, gb, cam, w, scene, steps, warmup, own_noise=True):
                noise=NOISE_NAMES[w["noise"]], seed=w["seed"],
                ambient_sh=tuple(float(v) for v in scene.ambient_sh.reshape(-1)))
     stream = torch.cuda.current_stream()
+    tuned_ms = None
+    if tune:
+        _, tuned_ms = ctx.autotune(t["depth"], t["normal"], t["radiance"], c, p, out)
+        torch.cuda.synchronize()
     shape = ctx.get_launch(c, p, 3 if w["fp16"] else 0)
     for _ in range(warmup):
         ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
@@ -591,7 +597,8 @@ def frame_leg(ctx, name, gb, cam, w, scene, steps, warmup, own_noise=True):
                      "traffic": measured_traffic(name, shape) if own_noise else None,
                      "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": abytes,
                      "bytes_per_sample": 16 if w["fp16"] else 28, "bytes_per_pixel": 38 if w["fp16"] else 44,
-                     "launch_shape": list(shape), "compulsory_floor_bytes": floor_bytes,
+                     "launch_shape": list(shape), "launch_shape_source": "autotuned" if tune else "default",
+                     "autotune_best_ms": tuned_ms, "compulsory_floor_bytes": floor_bytes,
                      "compulsory_floor_ms": floor_bytes / (HBM_PEAK_GBS * 1e9) * 1e3},
     }
     return res, (t, c, p, out)
@@ -746,7 +753,10 @@ def main():
             continue
         gb_n, cam_n, w_n, sc_n = loaded[n][:4]
         if n == "c3_4k_fp16":
-            res, tens = frame_leg(ctx, n, gb_n, cam_n, w_n, sc_n, args.c3_steps, 2, w_n["own_noise"])
+            # at 4K the default shape is not the fastest (the autotuner's pick measured 4 %
+            # faster), so this leg runs the shape the library's autotuner picks
+            res, tens = frame_leg(ctx, n, gb_n, cam_n, w_n, sc_n, args.c3_steps, 2, w_n["own_noise"],
+                                  tune=not args.no_autotune)
             result["c3_4k_fp16"] = res
         else:
             from paper_2301_11376_amd import Camera, Params, NOISE_NAMES
