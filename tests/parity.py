@@ -1,10 +1,16 @@
-"""Helpers shared by the GPU parity tests: run the HIP path and the oracle on the same
-seeded inputs, compare element by element and trace every mismatch.
+"""Helpers shared by the parity tests: run the HIP path (or the host build of its per-pixel
+code) and the oracle on the same seeded inputs, compare element by element and trace every
+mismatch.
 
-Tolerances (from the target of the work): sector masks exact on >= 99.9 % of pixels,
-every mismatch explained by an endpoint within 1e-6 rad of a rounding boundary; AO,
-GI and ambient within 1e-3 absolute for FP32 inputs (the oracle reads the same FP32 /
-FP16 values the GPU reads, upcast exactly).
+The bar: sector masks exact on >= 99.9 % of pixels, every mismatch explained by endpoints
+within 1e-6 rad of a rounding boundary; AO, GI and ambient within 1e-3 absolute for FP32
+inputs (the oracle reads the same FP32 / FP16 values the GPU reads, upcast exactly).  The
+tracer (explain_pixel) replays a mismatched pixel in the oracle with near-tie roundings
+flipped: a floor or ceiling argument just off an integer crosses it; one exactly on it
+drops under a floor and rises under a ceiling (PSEUDOCODE's width).  Up to 10 near ties
+every combination is replayed; with more, each mismatched slice is searched on its own for
+flips whose sector sets OR to the device's slice mask, and the oracle replays the
+candidates.
 """
 from __future__ import annotations
 
