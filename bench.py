@@ -388,6 +388,33 @@ def bounce_leg(ctx, t, out, steps):
             "algorithmic_bytes": nbytes, "achieved_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
 
 
+def sequence_leg(ctx, t, c, p, steps):
+    """Frame sequences on the 1080p frame (multi-bounce feedback through the library's own
+    light buffer, gain 0.8 on a constant albedo, the seed advanced per frame): median of
+    `steps` event-timed steps (injection, gather on the new light, copy of the GI), beside
+    the same frame's gather alone."""
+    import torch
+    from paper_2301_11376_amd import Sequence
+    H, W = t["depth"].shape
+    albedo = torch.full((H, W, 3), 0.6, device="cuda")
+    out = {"ao": torch.empty((H, W), device="cuda"), "gi": torch.empty((H, W, 3), device="cuda"),
+           "ambient": torch.empty((H, W, 3), device="cuda")}
+    stream = torch.cuda.current_stream()
+    seq = Sequence(ctx, W, H)
+    try:
+        fn = lambda: seq.step(t["depth"], t["normal"], t["radiance"], albedo, c, p, 0.8, out=out)
+        fn()
+        med, mn, _ = timed(fn, stream, steps)
+        frames = seq.frame
+    finally:
+        torch.cuda.synchronize()
+        seq.close()
+    gather = lambda: ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
+    g_med = timed(gather, stream, steps)[0]
+    return {"workload": f"{W}x{H}, FP32 light buffer, gain 0.8, constant albedo 0.6, {frames} frames",
+            "ms_per_step": med, "ms_min": mn, "gather_ms": g_med, "overhead_vs_gather": med / g_med - 1.0}
+
+
 def sectors_leg(ctx, t, c, p):
     """The headline frame with 128 visibility sectors against 32 (Section 4.1 reports a
     5-10 % overhead for 128 on its GPU); median of 20 launches each."""
@@ -743,6 +770,9 @@ def main():
         result["bounce"] = bounce_leg(ctx, t, out, 20)
         print(f"bounce: {result['bounce']['ms']:.3f} ms, {result['bounce']['achieved_gbs']:.0f} GB/s",
               file=sys.stderr, flush=True)
+        result["sequence"] = sequence_leg(ctx, t, c, p, 20)
+        print(f"sequence: {result['sequence']['ms_per_step']:.3f} ms per step, gather alone "
+              f"{result['sequence']['gather_ms']:.3f} ms", file=sys.stderr, flush=True)
         print(f"denoise: {result['denoise']['ms']:.3f} ms", file=sys.stderr, flush=True)
         result["sectors128"] = sectors_leg(ctx, t, c, p)
         print(f"sectors: 32 {result['sectors128']['ms_32']:.3f} ms, 128 {result['sectors128']['ms_128']:.3f} ms",
