@@ -287,13 +287,22 @@ def batch_leg(ctx, pool, autotune, kind="mixed"):
     torch.cuda.synchronize()
     identical = all(torch.equal(a[5][n], b[5][n]) for a, b in zip(items_plain, items_batch)
                     for n in ("ao", "gi", "ambient"))
-    p_med, p_min, _ = timed(plain, stream, 5)
-    b_med, b_min, _ = timed(batched, stream, 5)
+    # the two paths alternate, run by run, so that drift of the clock or the box falls on
+    # both; every run is kept so the speed-up can be read against the spread
+    p_all, b_all = [], []
+    for _ in range(7):
+        p_all += timed(plain, stream, 1)[2]
+        b_all += timed(batched, stream, 1)[2]
+    p_med, p_min, p_max = float(np.median(p_all)), min(p_all), max(p_all)
+    b_med, b_min, b_max = float(np.median(b_all)), min(b_all), max(b_all)
     samples = sum(samples_of(f) for f in frames)
     res = {"workload": BATCH_WORKLOADS[kind],
            "frames": len(frames), "samples": samples, "autotuned_classes": tuned,
-           "plain_ms": p_med, "plain_min_ms": p_min, "batched_ms": b_med, "batched_min_ms": b_min,
-           "speedup": p_med / b_med, "plain_gsamples_s": samples / p_med / 1e6,
+           "plain_ms": p_med, "plain_min_ms": p_min, "plain_max_ms": p_max, "plain_runs_ms": p_all,
+           "batched_ms": b_med, "batched_min_ms": b_min, "batched_max_ms": b_max, "batched_runs_ms": b_all,
+           "speedup": p_med / b_med, "speedup_range": [p_min / b_max, p_max / b_min],
+           "speedup_outside_spread": bool(p_min > b_max or p_max < b_min),
+           "plain_gsamples_s": samples / p_med / 1e6,
            "batched_gsamples_s": samples / b_med / 1e6, "bit_identical_to_plain": bool(identical)}
     print(f"batch ({kind}): plain {p_med:.2f} ms, batched {b_med:.2f} ms, x{p_med / b_med:.3f}, identical {identical}",
           file=sys.stderr, flush=True)
