@@ -217,7 +217,7 @@ def render_gbuffer(scene: Scene, cam: CameraSpec, normal_dtype=np.float32,
 
     geom = obj >= 0
     depth = np.where(geom, tbest, 0.0)
-    P = O + tbest[..., None] * d
+    P = O + depth[..., None] * d   # sky rays (no hit, tbest = inf) get 0 here, then 0 below
     P = np.where(geom[..., None], P, 0.0)
 
     # hard shadows toward the directional light
