@@ -14,6 +14,9 @@
 //   - the integer lattice never overflows int32 at the frame's extreme pixels, longest
 //     offsets and every direction of the slice-direction table;
 //   - sampled texels pass the kernels' on-screen test only inside the frame.
+// The half-resolution fill (upsample_pixel) and every denoiser pass (stage_cell and
+// filter_cell over LDS-sized arrays) also run on real host buffers of exactly the bytes
+// the frame's pitches span, so the sanitizer reports any access outside them.
 // It runs the library's strip walk and, with --interleaved, a reconstruction of the
 // interleaved strip walk (strips 0, 8, 16, ... then 1, 9, 17, ...) that was timed and then
 // withdrawn.  With --fuzz N SEED it draws N random inputs instead (see fuzz() below).
@@ -25,7 +28,9 @@
 #include <string>
 #include <vector>
 
+#include "ssvb_denoise_cell.h"
 #include "ssvb_host.h"
+#include "ssvb_pixel.h"
 
 using namespace ssvb;
 
@@ -227,6 +232,102 @@ static void emulate_frame(const FrameArgs& A) {
           A.W, A.H, A.tile_w, A.tile_h, A.strip, A.lp, A.sub);
     check_texels(A, S);
 }
+
+// ---------------------------------------------------------------------------------------
+// the half-resolution fill and the denoiser on real host buffers of exactly the bytes the
+// frame's pitches span (AddressSanitizer reports any access outside them)
+// ---------------------------------------------------------------------------------------
+struct Span {
+    std::vector<char> b;
+    explicit Span(int64_t n) : b((size_t)n) {}
+    char* p() { return b.data(); }
+};
+
+// A depth image with background pixels in it (every 7th and the border of some rows).
+static void fill_depth(const FrameArgs& A, char* d) {
+    for (int y = 0; y < A.H; ++y)
+        for (int x = 0; x < A.W; ++x) {
+            float z = 1.0f + (float)((x * 7 + y * 3) % 11);
+            if ((x + 2 * y) % 7 == 0 || (y % 5 == 0 && x == 0)) z = 0.0f;
+            memcpy(d + (int64_t)y * A.depth_pitch + 4 * (int64_t)x, &z, 4);
+        }
+}
+
+// upsample_pixel on every pixel of a half-resolution frame (each thread's view of it).
+static long check_upsample(const FrameArgs& A0) {
+    const Sizes S = sizes_of(A0);
+    Span depth(S.depth), ao(S.ao), gi(S.gi), amb(S.amb);
+    FrameArgs A = A0;
+    A.depth = (const float*)depth.p();
+    A.ao = (float*)ao.p(), A.gi = (float*)gi.p(), A.amb = (float*)amb.p();
+    fill_depth(A, depth.p());
+    for (int y = 0; y < A.H; ++y)
+        for (int x = 0; x < A.W; ++x) upsample_pixel(A, x, y);
+    return (long)A.W * A.H;
+}
+
+// Every pass of the denoiser (taps 1, 2 and 4 cells apart; normal power 16 by squarings and
+// 3 by square-and-multiply) on the frame's geometry and pitches, at its resolution: each
+// 16 x 16-cell tile staged into LDS-sized arrays and filtered as a workgroup does.
+template <int S, int K2>
+static void denoise_tiles(const DenoiseArgs& D) {
+    constexpr int E = kDenoiseTile + 4 * S, N = E * E;
+    std::vector<float4> sA(N), sB(N), sC(N);  // exactly the kernel's LDS arrays
+    for (int tile = 0; tile < D.tiles; ++tile) {
+        const int u0 = (tile % D.tiles_x) * kDenoiseTile - 2 * S;
+        const int v0 = (tile / D.tiles_x) * kDenoiseTile - 2 * S;
+        for (int i = 0; i < N; ++i) {
+            const int u = u0 + i % E, v = v0 + i / E;
+            float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a, c = a;
+            if (u >= 0 && v >= 0 && u < D.gw && v < D.gh) dn::stage_cell(D, u, v, a, b, c);
+            sA[(size_t)i] = a;
+            sB[(size_t)i] = b;
+            sC[(size_t)i] = c;
+        }
+        for (int t = 0; t < kDenoiseTile * kDenoiseTile; ++t)
+            dn::filter_cell<S, K2>(D, sA.data(), sB.data(), sC.data(), u0, v0, t % kDenoiseTile, t / kDenoiseTile);
+    }
+}
+
+static long check_denoise(const FrameArgs& A0) {
+    const Sizes S = sizes_of(A0);
+    Span depth(S.depth), normal(S.normal), in_ao(S.ao), in_gi(S.gi), in_amb(S.amb), out_ao(S.ao), out_gi(S.gi),
+        out_amb(S.amb);
+    FrameArgs A = A0;
+    A.depth = (const float*)depth.p();
+    fill_depth(A, depth.p());
+    memset(normal.p(), 0, normal.b.size());
+    const ssvb_image d{depth.p(), A.depth_pitch, SSVB_F32, 1};
+    const ssvb_image n{normal.p(), A.normal_pitch, A.normal_f16 ? SSVB_F16 : SSVB_F32, A.normal_ch};
+    const ssvb_camera cam{A.W, A.H, 0.5f * A.H, 0.5f * A.H, 0.5f * A.W, 0.5f * A.H, {1, 0, 0, 0, 1, 0, 0, 0, 1}};
+    const ssvb_outputs in{(float*)in_ao.p(), (float*)in_gi.p(), (float*)in_amb.p(), nullptr, A.ao_pitch, A.gi_pitch,
+                          A.amb_pitch, 0};
+    const ssvb_outputs out{(float*)out_ao.p(), (float*)out_gi.p(), (float*)out_amb.p(), nullptr, A.ao_pitch,
+                           A.gi_pitch, A.amb_pitch, 0};
+    memset(in_ao.p(), 0, in_ao.b.size());
+    memset(in_gi.p(), 0, in_gi.b.size());
+    memset(in_amb.p(), 0, in_amb.b.size());
+    long cells = 0;
+    for (int power : {16, 3}) {
+        const ssvb_denoise_params dp{3, power, 0.05f, A.sub};
+        DenoiseArgs D;
+        fill_denoise(D, &d, &n, &cam, &dp, &in, &out);
+        CHECK(D.gw == (A.W + A.sub - 1) / A.sub && D.gh == (A.H + A.sub - 1) / A.sub, "denoise grid %dx%d", D.gw, D.gh);
+        if (power == 16) {
+            denoise_tiles<1, 4>(D);
+            denoise_tiles<2, 4>(D);
+            denoise_tiles<4, 4>(D);
+        } else {
+            denoise_tiles<1, -1>(D);
+            denoise_tiles<2, -1>(D);
+            denoise_tiles<4, -1>(D);
+        }
+        cells += 3L * D.gw * D.gh;
+    }
+    return cells;
+}
+
+static long g_upsampled = 0, g_denoised = 0;
 
 // The lattice at the frame's extreme pixels, for the longest offsets and every direction
 // of the table (computed as the library builds it): no int32 overflow, and a texel that
@@ -492,6 +593,15 @@ static void fuzz(long n, uint64_t seed, long& accepted, long& rejected, long& em
             emulate_frame(A);
             ++emulated;
         }
+        {
+            const Sizes S = sizes_of(A);
+            const int64_t cap = 16 << 20;  // real buffers only for spans of at most 16 MB
+            if ((int64_t)W * H <= 20000 && S.depth <= cap && S.normal <= cap && S.ao <= cap && S.gi <= cap &&
+                S.amb <= cap) {
+                if (A.sub == 2) g_upsampled += check_upsample(A);
+                g_denoised += check_denoise(A);
+            }
+        }
         // small frames also go into batches of up to kMaxBatch, as ssvb_compute_batch packs
         // them (frames of at most kPackTiles tiles), under one context launch shape
         if ((uint32_t)A.tiles_x * (uint32_t)A.tiles_y <= kPackTiles && (int64_t)W * H <= 60000) {
@@ -538,8 +648,9 @@ int main(int argc, char** argv) {
     if (fuzz_n > 0) {
         long acc = 0, rej = 0, emu = 0, bat = 0;
         fuzz(fuzz_n, fuzz_seed, acc, rej, emu, bat);
-        printf("fuzz: %ld inputs, %ld accepted (%ld emulated), %ld rejected, %ld batches, %ld checks, %ld failed\n",
-               fuzz_n, acc, emu, rej, bat, g_checks, g_fail);
+        printf("fuzz: %ld inputs, %ld accepted (%ld emulated), %ld rejected, %ld batches, %ld upsampled and %ld "
+               "denoised cells on real buffers, %ld checks, %ld failed\n",
+               fuzz_n, acc, emu, rej, bat, g_upsampled, g_denoised, g_checks, g_fail);
         return g_fail != 0;
     }
     // the launch shapes of the autotuner (tile w, h, lanes) x strips, and the default
@@ -598,6 +709,11 @@ int main(int argc, char** argv) {
         emulate_frame(A);
         check_lattice(A);
         ++frames_done;
+        // the half-resolution fill and the denoiser on real buffers of the frame's spans
+        if ((int64_t)s.W * s.H <= 400000 && !g_interleaved) {  // independent of the walk
+            if (A.sub == 2) g_upsampled += check_upsample(A);
+            g_denoised += check_denoise(A);
+        }
     }
     // batches: the mixed small frames of the GPU batch tests, with every launch shape
     std::vector<Frame> batch;
@@ -621,7 +737,8 @@ int main(int argc, char** argv) {
             }
         }
     }
-    printf("%s walk: %ld frame launches, %ld batches, %ld checks, %ld failed\n",
-           g_interleaved ? "interleaved" : "strip", frames_done, batches, g_checks, g_fail);
+    printf("%s walk: %ld frame launches, %ld batches, %ld upsampled and %ld denoised cells on real buffers, "
+           "%ld checks, %ld failed\n",
+           g_interleaved ? "interleaved" : "strip", frames_done, batches, g_upsampled, g_denoised, g_checks, g_fail);
     return g_fail != 0;
 }

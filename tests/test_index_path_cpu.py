@@ -50,8 +50,11 @@ def run(exe, *args):
 
 def test_strip_walk_index_path(emulator):
     """The library's walk, every launch shape of the autotuner on every frame up to 1080p
-    (four shapes on the 4K frame)."""
-    run(emulator)
+    (four shapes on the 4K frame); on the frames up to 400k pixels also the half-resolution
+    fill and every denoiser pass on real buffers of exactly the frames' spans."""
+    out = run(emulator)
+    m = re.search(r"(\d+) upsampled and (\d+) denoised cells", out)
+    assert int(m.group(1)) > 0 and int(m.group(2)) > 0
 
 
 def test_interleaved_walk_reconstruction_index_path(emulator):
@@ -68,8 +71,12 @@ def test_validated_inputs_keep_the_index_path_in_bounds(emulator, seed):
     field now and then outside what the library accepts: every input ssvb_validate accepts
     runs the whole per-frame emulation (tiles, lanes, every texel's 32-bit offsets exact,
     outputs in bounds) and the lattice check; the small ones also run in random batches of
-    up to 64 frames under a random context launch shape (descriptor, packed list, cursor)."""
+    up to 64 frames under a random context launch shape (descriptor, packed list, cursor),
+    and through the half-resolution fill and every denoiser pass on real buffers of exactly
+    their spans (the sanitizer reports any access outside them)."""
     out = run(emulator, "--fuzz", "2000", str(seed))
     m = re.search(r"fuzz: (\d+) inputs, (\d+) accepted \((\d+) emulated\), (\d+) rejected, (\d+) batches", out)
     n, acc, emu, rej, bat = (int(v) for v in m.groups())
     assert acc + rej == n and acc >= 0.4 * n and emu >= 0.9 * acc and bat >= 10
+    m = re.search(r"(\d+) upsampled and (\d+) denoised cells", out)
+    assert int(m.group(1)) > 0 and int(m.group(2)) > 0
