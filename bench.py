@@ -640,6 +640,44 @@ def frame_leg(ctx, name, gb, cam, w, scene, steps, warmup, own_noise=True, tune=
     return res, (t, c, p, out)
 
 
+def slice_order_leg(ctx, tensors, chunk, steps, warmup=3):
+    """The same frame in slice-major order (chunks of `chunk` tiles; both kernels, the
+    per-slice gather and the reduction, inside the timed region), against the default
+    order timed the same way just before; the outputs of the two orders compared (AO bit
+    for bit, GI and ambient max |difference|)."""
+    import torch
+    t, c, p, out = tensors
+    stream = torch.cuda.current_stream()
+
+    def timed():
+        for _ in range(warmup):
+            ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            ctx.compute(t["depth"], t["normal"], t["radiance"], c, p, out=out)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        return float(ms.mean()), float(np.percentile(ms, 50)), {k: v.clone() for k, v in out.items()}
+
+    base_ms, base_p50, base = timed()
+    try:
+        ctx.set_slice_order(chunk)
+        ms, p50, got = timed()
+    finally:
+        ctx.set_slice_order(0)
+    res = {"chunk_tiles": chunk, "ms": ms, "p50_ms": p50, "default_order_ms": base_ms,
+           "default_order_p50_ms": base_p50, "speedup": base_ms / ms,
+           "ao_equal": bool(torch.equal(got["ao"], base["ao"])),
+           "gi_max_diff": float((got["gi"] - base["gi"]).abs().max()),
+           "ambient_max_diff": float((got["ambient"] - base["ambient"]).abs().max())}
+    print(f"slice order (chunk {chunk}): {ms:.3f} ms vs default order {base_ms:.3f} ms, AO equal "
+          f"{res['ao_equal']}, GI max diff {res['gi_max_diff']:.2e}", file=sys.stderr, flush=True)
+    return res
+
+
 def parity_leg(ctx, name, tensors, ref):
     """The workload's frame once more with slice masks, compared with the oracle's outputs
     from the cpu_baseline leg (the rows it computed)."""
@@ -679,6 +717,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rates", default="0.5,0.7,0.9",
                     help="request rates as fractions of the saturated rate (p50 / p99 at each)")
+    ap.add_argument("--slice-order", type=int, default=0, metavar="TILES",
+                    help="also time the frame(s) in slice-major order over chunks of TILES tiles (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the gather, run a plain device copy of MIB MiB (scales HBM counters)")
     args = ap.parse_args()
@@ -768,6 +808,8 @@ def main():
         cpu["host_cpus"] = os.cpu_count()
         cpu["workloads"] = base
         result["cpu_baseline"] = cpu
+    if args.slice_order:
+        result["slice_order"] = {args.workload: slice_order_leg(ctx, tensors, args.slice_order, args.steps)}
     parity = {}
     if args.workload in refs:
         parity[args.workload] = parity_leg(ctx, args.workload, tensors, refs[args.workload])
@@ -797,6 +839,9 @@ def main():
             res, tens = frame_leg(ctx, n, gb_n, cam_n, w_n, sc_n, args.c3_steps, 2, w_n["own_noise"],
                                   tune=not args.no_autotune)
             result["c3_4k_fp16"] = res
+            if args.slice_order:
+                result.setdefault("slice_order", {})[n] = slice_order_leg(ctx, tens, args.slice_order,
+                                                                          args.c3_steps)
         else:
             from paper_2301_11376_amd import Camera, Params, NOISE_NAMES
             tt = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in gb_n.items()}

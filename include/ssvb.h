@@ -212,6 +212,23 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
  * autotuned shape of the frame's class, else the default 32 x 8, strip 4, 1 lane). */
 ssvb_status ssvb_set_launch(ssvb_ctx* ctx, const ssvb_launch* shape);
 
+/* Work order of this context's later ssvb_compute calls (not batches or servers).
+ * chunk_tiles 0 (the default): each workgroup runs every slice of its tile.  chunk_tiles
+ * C in 1..65536: slice-major order, for cache locality (a pixel's slices turn by its own
+ * random offset, so one slice of many pixels samples one wedge of directions rather than
+ * the whole disc, Algorithm 1): the work items of each die's run of tiles are (tile,
+ * slice) pairs, taken for slice 0 of C tiles, then slice 1 of the same C tiles, and so
+ * on; one lane per pixel (a shape with more lanes keeps its pixel count with one lane);
+ * each item writes its slice's sums (32 bytes per computed pixel and slice) to a buffer
+ * the context allocates and grows on demand (freed with the context; growing it waits
+ * for the context's previous slice-major launch), and a second kernel adds the slices in
+ * order.  AO and the masks equal the default order's bit for bit; GI and ambient sum the
+ * same terms grouped by slice (FP32 rounding).  Slice-major launches of one context are
+ * ordered one after another on the device whatever their streams, since they share the
+ * buffer.  SSVB_ERR_INVALID_ARG for C outside [0, 65536]; ssvb_compute returns
+ * SSVB_ERR_OUT_OF_MEMORY when the buffer cannot grow. */
+ssvb_status ssvb_set_slice_order(ssvb_ctx* ctx, int32_t chunk_tiles);
+
 /* The launch shape ssvb_compute would use for this camera / parameter / element-type
  * class (fp16_mask: bit 0 normals FP16, bit 1 radiance FP16). */
 ssvb_status ssvb_get_launch(ssvb_ctx* ctx, const ssvb_camera* camera, const ssvb_params* params,

@@ -28,6 +28,7 @@ STEPS_UNIFORM, STEPS_QUADRATIC = 0, 1
 EXPORTED = [
     "ssvb_status_string", "ssvb_last_error", "ssvb_default_params", "ssvb_create", "ssvb_destroy",
     "ssvb_validate", "ssvb_compute", "ssvb_compute_batch", "ssvb_set_launch", "ssvb_get_launch",
+    "ssvb_set_slice_order",
     "ssvb_autotune", "ssvb_debug_lattice", "ssvb_debug_endpoints", "ssvb_debug_direction_table",
     "ssvb_debug_noise_constants", "ssvb_server_create", "ssvb_server_submit", "ssvb_server_poll",
     "ssvb_server_wait", "ssvb_server_release", "ssvb_server_stats", "ssvb_server_destroy", "ssvb_inject_bounce",
@@ -126,6 +127,8 @@ def lib() -> ctypes.CDLL:
     L.ssvb_compute_batch.argtypes = [V, P(ssvb_frame), I, V]
     L.ssvb_set_launch.restype = I
     L.ssvb_set_launch.argtypes = [V, P(ssvb_launch)]
+    L.ssvb_set_slice_order.restype = I
+    L.ssvb_set_slice_order.argtypes = [V, ctypes.c_int32]
     L.ssvb_get_launch.restype = I
     L.ssvb_get_launch.argtypes = [V, P(ssvb_camera), P(ssvb_params), I, P(ssvb_launch)]
     L.ssvb_autotune.restype = I
@@ -473,6 +476,11 @@ class Context:
         else:
             L = ssvb_launch(*shape)
             check(lib().ssvb_set_launch(self.handle, ctypes.byref(L)), "ssvb_set_launch")
+
+    def set_slice_order(self, chunk_tiles: int = 0):
+        """Slice-major work order of later compute calls in chunks of `chunk_tiles` tiles
+        (0: each workgroup runs every slice of its tile)."""
+        check(lib().ssvb_set_slice_order(self.handle, int(chunk_tiles)), "ssvb_set_slice_order")
 
     def get_launch(self, camera: Camera, params: Params, fp16_mask=0):
         L = ssvb_launch()

@@ -21,6 +21,7 @@ using namespace ssvb;
 constexpr int kBatchSlots = 2;  // descriptor slots of the batched path (double buffering)
 constexpr int kRing = 32;       // queue-counter sets of single-frame launches that may be in flight
 constexpr int kRingStride = 16; // uint32 per set (9 used)
+constexpr int kMaxSliceChunk = 65536;  // tiles per chunk of the slice-major order
 
 struct ssvb_ctx {
     int device = 0;
@@ -34,6 +35,16 @@ struct ssvb_ctx {
     hipEvent_t ring_ev[kRing] = {};
     bool ring_pending[kRing] = {};
     uint64_t next_ring = 0;
+    // slice-major order of ssvb_compute (0: off): chunk size in tiles, the partial-sum
+    // buffer (grown on demand) and the event after its last use (slice-major launches on
+    // any stream are ordered after the previous one, which shares the buffer)
+    uint32_t slice_chunk = 0;
+    int slices_grid = 0;
+    int cus = 0;  // compute units of the device
+    float* partial = nullptr;
+    size_t partial_cap = 0;
+    hipEvent_t partial_ev = nullptr;
+    bool partial_pending = false;
     // batched path
     bool batch_ready = false;
     int batch_grid[2] = {0, 0};
@@ -574,6 +585,7 @@ ssvb_status ssvb_create(int32_t device, ssvb_ctx** out) {
         hipDeviceProp_t prop;
         e = hipGetDeviceProperties(&prop, device);
         ctx->frame_grid = prop.multiProcessorCount * frame_blocks_per_cu();
+        ctx->cus = prop.multiProcessorCount;
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     (void)hipSetDevice(prev);
@@ -603,6 +615,8 @@ ssvb_status ssvb_destroy(ssvb_ctx* ctx) {
     if (ctx->d_ring) (void)hipFree(ctx->d_ring);
     for (int k = 0; k < kRing; ++k)
         if (ctx->ring_ev[k]) (void)hipEventDestroy(ctx->ring_ev[k]);
+    if (ctx->partial) (void)hipFree(ctx->partial);
+    if (ctx->partial_ev) (void)hipEventDestroy(ctx->partial_ev);
     (void)hipSetDevice(prev);
     delete ctx;
     return SSVB_OK;
@@ -664,6 +678,46 @@ hipError_t launch_single(ssvb_ctx* ctx, const FrameArgs& A, hipStream_t stream) 
     return e;
 }
 
+// The same frame in slice-major order (ctx->slice_chunk > 0): one lane per pixel, the
+// per-slice gather into the context's partial buffer (grown when the frame needs more; the
+// old buffer is freed once its last launch has completed), the reduction, the
+// half-resolution fill.  Ordered after the previous slice-major launch of the context.
+hipError_t launch_single_slices(ssvb_ctx* ctx, FrameArgs A, hipStream_t stream) {
+    // set up on first use, so that a context that never turns the order on is unchanged
+    if (!ctx->partial_ev) {
+        const hipError_t c = hipEventCreateWithFlags(&ctx->partial_ev, hipEventDisableTiming);
+        if (c != hipSuccess) {
+            ctx->partial_ev = nullptr;
+            return c;
+        }
+        ctx->slices_grid = ctx->cus * slices_blocks_per_cu();
+    }
+    if (A.lp > 1) set_launch(A, LaunchShape{A.tile_w * A.lp, A.tile_h, A.strip, 1});
+    const size_t gw = (size_t)(A.W + A.sub - 1) / A.sub, gh = (size_t)(A.H + A.sub - 1) / A.sub;
+    const size_t bytes = gw * gh * (size_t)A.nd * kPartialFloats * sizeof(float);
+    hipError_t e = hipSuccess;
+    if (bytes > ctx->partial_cap) {
+        if (ctx->partial_pending) e = hipEventSynchronize(ctx->partial_ev);
+        if (e == hipSuccess && ctx->partial) e = hipFree(ctx->partial);
+        ctx->partial = nullptr;
+        ctx->partial_cap = 0;
+        if (e == hipSuccess) e = hipMalloc((void**)&ctx->partial, bytes);
+        if (e != hipSuccess) return e;
+        ctx->partial_cap = bytes;
+    }
+    if (ctx->partial_pending) e = hipStreamWaitEvent(stream, ctx->partial_ev, 0);
+    const int r = (int)(ctx->next_ring++ % kRing);
+    if (e == hipSuccess && ctx->ring_pending[r]) e = hipEventSynchronize(ctx->ring_ev[r]);
+    if (e == hipSuccess)
+        e = launch_slices(A, ctx->d_ring + r * kRingStride, ctx->slices_grid, ctx->partial, ctx->slice_chunk, stream);
+    if (e == hipSuccess && A.sub == 2) e = launch_upsample(A, stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ring_ev[r], stream);
+    if (e == hipSuccess) ctx->ring_pending[r] = true;
+    if (e == hipSuccess) e = hipEventRecord(ctx->partial_ev, stream);
+    if (e == hipSuccess) ctx->partial_pending = true;
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -680,9 +734,20 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
     int prev = 0;
     (void)hipGetDevice(&prev);
     if (prev != ctx->device) (void)hipSetDevice(ctx->device);
-    const hipError_t e = launch_single(ctx, A, (hipStream_t)hip_stream);
+    const hipError_t e = ctx->slice_chunk ? launch_single_slices(ctx, A, (hipStream_t)hip_stream)
+                                          : launch_single(ctx, A, (hipStream_t)hip_stream);
     if (prev != ctx->device) (void)hipSetDevice(prev);
+    if (e == hipErrorOutOfMemory && ctx->slice_chunk)
+        return fail(SSVB_ERR_OUT_OF_MEMORY, "partial sums of the slice-major order");
     if (e != hipSuccess) return hip_fail(e, "gather launch");
+    return SSVB_OK;
+}
+
+ssvb_status ssvb_set_slice_order(ssvb_ctx* ctx, int32_t chunk_tiles) {
+    if (!ctx) return fail(SSVB_ERR_INVALID_ARG, "NULL context");
+    if (chunk_tiles < 0 || chunk_tiles > kMaxSliceChunk)
+        return fail(SSVB_ERR_INVALID_ARG, "chunk of %d tiles outside [0, %d]", chunk_tiles, kMaxSliceChunk);
+    ctx->slice_chunk = (uint32_t)chunk_tiles;
     return SSVB_OK;
 }
 

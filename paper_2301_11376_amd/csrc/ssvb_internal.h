@@ -67,6 +67,13 @@ struct FrameArgs {
     int32_t lp;
 };
 
+// Slice-major order: the work items are (tile, slice) pairs, taken slice by slice over
+// chunks of tiles of each XCD's run, so that the samples in flight on a die point into one
+// wedge of directions; an item writes its slice's sums (kPartialFloats floats: AO, GI rgb,
+// ambient rgb, unused) to a partial buffer at [computed pixel][slice], and a second pass
+// adds the slices in order.
+constexpr int kPartialFloats = 8;
+
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
 
 // A launch shape: tile of tile_w x tile_h pixels, strip width in tiles, lanes per pixel.
@@ -141,6 +148,24 @@ SSVB_HD uint32_t depth_off(const FrameArgs& A, int X, int Y) {
 SSVB_HD uint32_t image_off(int64_t pitch, int ch, bool f16, int x, int y) {
     return (uint32_t)y * (uint32_t)pitch + (uint32_t)(x * ch) * (f16 ? 2u : 4u);
 }
+// Slice-major order: item j of a run of `count` tiles (count * nd items) is slice `slice` of
+// the run's tile `tile`.  The run is cut into chunks of `chunk` tiles (the last may be
+// shorter); a chunk's items are its tiles for slice 0, then for slice 1, and so on.
+SSVB_HD void slice_item(uint32_t chunk, int nd, uint32_t count, uint32_t j, uint32_t& tile, int& slice) {
+    const uint32_t per = chunk * (uint32_t)nd;  // items of a full chunk
+    const uint32_t c = j / per, r = j - c * per;
+    const uint32_t first = c * chunk;
+    const uint32_t n = min(chunk, count - first);  // tiles of this chunk
+    slice = (int)(r / n);
+    tile = first + r % n;
+}
+
+// Offset (floats) of the partial sums of slice s of the computed pixel (x, y).
+SSVB_HD int64_t partial_off(const FrameArgs& A, int x, int y, int s) {
+    const int64_t gw = (A.W + A.sub - 1) / A.sub;
+    return (((int64_t)(y / A.sub) * gw + x / A.sub) * A.nd + s) * kPartialFloats;
+}
+
 // ---------------------------------------------------------------------------------------
 // batched persistent path
 // ---------------------------------------------------------------------------------------

@@ -67,6 +67,55 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     }
 }
 
+// One frame in slice-major order (A.lp = 1): the work items of XCD k's run of tiles are
+// (tile, slice) pairs, slice by slice over chunks of `chunk` tiles, queued for XCD k with
+// the same stealing as gather_frame; each item runs one slice of its tile's pixels and
+// writes that slice's sums to `partial` (reduce_slices then adds them).  Criterion and
+// element types are taken at run time (the batch kernel's instance).
+template <int NB>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void gather_slices(
+    FrameArgs A, uint32_t* __restrict__ q, float* __restrict__ partial, uint32_t chunk) {
+    __shared__ ExactLds L;
+    __shared__ uint32_t s_item;
+    typedef const __attribute__((address_space(4))) FrameArgs* ConstArgs;
+    const ConstArgs args = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
+    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+    const int home = hw_xcd();
+    for (int qi = 0; qi < kXcds; ++qi) {
+        const int k = (home + qi) & (kXcds - 1);
+        uint32_t first, count;
+        xcd_run(nt, k, first, count);
+        for (;;) {
+            const uint32_t item = grab(&q[k], &s_item);
+            if (item >= count * (uint32_t)A.nd) break;
+            ConstArgs ap = args;
+            asm volatile("" : "+s"(ap));
+            const FrameArgs& F = *(const FrameArgs*)ap;
+            uint32_t tile;
+            int slice, tx, ty, x, y, li;
+            slice_item(chunk, F.nd, count, item, tile, slice);
+            walk_tile(F, first + tile, tx, ty);
+            tile_pixel(F, tx, ty, (int)threadIdx.x, x, y, li);
+            if ((unsigned)x < (unsigned)F.W && (unsigned)y < (unsigned)F.H)
+                gather_pixel<-1, MODE_PARTIAL, false, -1, NB>(F, L, x, y, slice, F.nd, nullptr, partial);
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&q[kXcds], 1u) == gridDim.x - 1) {
+            for (int k = 0; k <= kXcds; ++k) atomicExch(&q[k], 0u);
+        }
+    }
+}
+
+// Second pass of the slice-major order: one thread per computed pixel (16 x 16 blocks of
+// the computed grid).
+__global__ __launch_bounds__(kBlock) void reduce_slices(FrameArgs A, const float* __restrict__ partial) {
+    const int u = (int)(blockIdx.x * 16 + threadIdx.x % 16), v = (int)(blockIdx.y * 16 + threadIdx.x / 16);
+    const int gw = (A.W + A.sub - 1) / A.sub, gh = (A.H + A.sub - 1) / A.sub;
+    if (u < gw && v < gh) reduce_pixel(A, partial, u * A.sub, v * A.sub);
+}
+
 __global__ __launch_bounds__(kBlock) void debug_lattice(FrameArgs A, int32_t* out) {
     __shared__ ExactLds L;
     const int x = blockIdx.x * 16 + (int)(threadIdx.x % 16u);
@@ -246,6 +295,22 @@ hipError_t launch_plain(const FrameArgs& A, uint32_t* queues, int grid, hipStrea
     return hipGetLastError();
 }
 
+hipError_t launch_slices(const FrameArgs& A, uint32_t* queues, int grid, float* partial, uint32_t chunk,
+                         hipStream_t stream) {
+    // no more workgroups than the frame has items (rounded to whole XCD rounds)
+    const uint64_t items = (uint64_t)A.tiles_x * A.tiles_y * (uint64_t)A.nd;
+    const uint64_t need = kXcds * ((items + kXcds - 1) / kXcds);
+    const uint32_t nwg = need < (uint64_t)grid ? (uint32_t)need : (uint32_t)grid;
+    if (A.nb == 128)
+        hipLaunchKernelGGL(gather_slices<128>, dim3(nwg), dim3(kBlock), 0, stream, A, queues, partial, chunk);
+    else
+        hipLaunchKernelGGL(gather_slices<32>, dim3(nwg), dim3(kBlock), 0, stream, A, queues, partial, chunk);
+    const int gw = (A.W + A.sub - 1) / A.sub, gh = (A.H + A.sub - 1) / A.sub;
+    hipLaunchKernelGGL(reduce_slices, dim3((gw + 15) / 16, (gh + 15) / 16), dim3(kBlock), 0, stream, A,
+                       (const float*)partial);
+    return hipGetLastError();
+}
+
 hipError_t launch_upsample(const FrameArgs& A, hipStream_t stream) {
     hipLaunchKernelGGL(upsample_half, dim3((A.W + 15) / 16, (A.H + 15) / 16), dim3(kBlock), 0, stream, A);
     return hipGetLastError();
@@ -259,6 +324,13 @@ hipError_t launch_inject_bounce(const char* direct, int64_t direct_pitch, int di
                        W, H, direct_ch, albedo_ch, next_ch, direct_f16, albedo_f16, next_f16, gain};
     hipLaunchKernelGGL(inject_bounce, dim3((W + 63) / 64, (H + 3) / 4), dim3(kBlock), 0, stream, B);
     return hipGetLastError();
+}
+
+int slices_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gather_slices<32>, kBlock, 0) != hipSuccess || nb < 1)
+        nb = 2;
+    return nb;
 }
 
 int frame_blocks_per_cu() {

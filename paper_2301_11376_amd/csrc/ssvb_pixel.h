@@ -399,7 +399,9 @@ SSVB_HD void endpoint_dir(int side, double cg, double sg, double sv, double se, 
 // ---------------------------------------------------------------------------------------
 // the gather
 // ---------------------------------------------------------------------------------------
-enum { MODE_COMPUTE = 0, MODE_LATTICE = 1, MODE_ENDPOINTS = 2 };
+// MODE_COMPUTE: the pixel's outputs; MODE_PARTIAL: one slice's sums to the partial buffer
+// (slice-major order); MODE_LATTICE / MODE_ENDPOINTS: test hooks
+enum { MODE_COMPUTE = 0, MODE_LATTICE = 1, MODE_ENDPOINTS = 2, MODE_PARTIAL = 3 };
 
 SSVB_HD void store_background(const FrameArgs& A, int x, int y, int li) {
     if (li != 0) return;
@@ -560,6 +562,7 @@ SSVB_HD void gather_pixel_steps(const FrameArgs& A, ExactLds& L, int x, int y, i
         store_background(A, x, y, li);
         return;
     }
+    if (MODE == MODE_PARTIAL && !geom) return;  // the reduction writes background pixels
     const float3 n = MODE == MODE_LATTICE ? make_float3(0.0f, 0.0f, 1.0f)
                                           : load3<FMT < 0 ? -1 : (FMT & 1)>(A.normal, A.normal_pitch, A.normal_ch,
                                                                             A.normal_f16, x, y);
@@ -663,7 +666,7 @@ SSVB_HD void gather_pixel_steps(const FrameArgs& A, ExactLds& L, int x, int y, i
                 }
             }
         }
-        if (MODE != MODE_COMPUTE) continue;
+        if (MODE != MODE_COMPUTE && MODE != MODE_PARTIAL) continue;
         ao_acc += 1.0f - (float)(NB == 32 ? mask_popc<NB>(B) : B.n) * (1.0f / (float)NB);
         if (A.masks) {
             GMEM uint32_t* mk = (GMEM uint32_t*)((GMEM char*)A.masks + (int64_t)y * A.masks_pitch) +
@@ -702,6 +705,13 @@ SSVB_HD void gather_pixel_steps(const FrameArgs& A, ExactLds& L, int x, int y, i
             amb = fmaf(fr, Lb, amb);
         }
     }
+    if (MODE == MODE_PARTIAL) {
+        // slice li's sums (the caller runs one slice per thread, lp = N_d; dbg_f is the
+        // partial buffer)
+        GMEM float* pr = (GMEM float*)dbg_f + partial_off(A, x, y, li);
+        pr[0] = ao_acc, pr[1] = gir, pr[2] = gig, pr[3] = gib, pr[4] = amr, pr[5] = amg, pr[6] = amb;
+        return;
+    }
     if (MODE != MODE_COMPUTE) return;
     // sum the lanes of the pixel (butterfly: every lane ends with the same value)
     for (int off = 1; off < lp; off <<= 1) {
@@ -738,6 +748,33 @@ SSVB_HD void gather_pixel(const FrameArgs& A, ExactLds& L, int x, int y, int li,
         gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, false, true>(A, L, x, y, li, lp, dbg_i, dbg_f);
     else
         gather_pixel_steps<CRIT, MODE, TINF, FMT, NB, false, false>(A, L, x, y, li, lp, dbg_i, dbg_f);
+}
+
+// Second pass of the slice-major order: the computed pixel (x, y)'s outputs from its slices'
+// sums, added in slice order (the AO sums are those of the one-pass kernel, bit for bit);
+// a background pixel gets AO 1, GI 0, ambient 0 and empty masks.
+SSVB_HD void reduce_pixel(const FrameArgs& A, const float* partial, int x, int y) {
+    if (!is_geometry(depth_load(A, depth_off(A, x, y)))) {
+        store_background(A, x, y, 0);
+        return;
+    }
+    const GMEM float* p = (const GMEM float*)partial + partial_off(A, x, y, 0);
+    float ao_acc = 0.0f, gir = 0.0f, gig = 0.0f, gib = 0.0f, amr = 0.0f, amg = 0.0f, amb = 0.0f;
+    for (int i = 0; i < A.nd; ++i, p += kPartialFloats) {
+        ao_acc += p[0];
+        gir += p[1], gig += p[2], gib += p[3];
+        amr += p[4], amg += p[5], amb += p[6];
+    }
+    const float inv_nd = 1.0f / (float)A.nd;
+    *(GMEM float*)((GMEM char*)A.ao + (int64_t)y * A.ao_pitch + (int64_t)x * 4) = ao_acc * inv_nd;
+    GMEM float* g = (GMEM float*)((GMEM char*)A.gi + (int64_t)y * A.gi_pitch) + 3 * (int64_t)x;
+    g[0] = gir * inv_nd;
+    g[1] = gig * inv_nd;
+    g[2] = gib * inv_nd;
+    GMEM float* m = (GMEM float*)((GMEM char*)A.amb + (int64_t)y * A.amb_pitch) + 3 * (int64_t)x;
+    m[0] = amr * inv_nd;
+    m[1] = amg * inv_nd;
+    m[2] = amb * inv_nd;
 }
 
 // Half resolution: every pixel with an odd coordinate takes the average of its 1, 2 or

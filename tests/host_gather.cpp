@@ -12,6 +12,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 #include "ssvb_host.h"
 #include "ssvb_pixel.h"
 
@@ -71,6 +73,60 @@ extern "C" int host_gather(const ssvb_image* depth, const ssvb_image* normal, co
         if (tinf) run_fmt<SSVB_HIT_PSEUDOCODE, true>(A);
         else run_fmt<SSVB_HIT_PSEUDOCODE, false>(A);
     }
+    if (A.sub == 2)
+        for (int y = 0; y < A.H; ++y)
+            for (int x = 0; x < A.W; ++x) upsample_pixel(A, x, y);
+    return 0;
+}
+
+// The slice-major order of a frame on host buffers, as gather_slices and reduce_slices run
+// it: the items of each XCD's run in the kernel's order (slice_item over chunks of `chunk`
+// tiles, the strip walk, one lane per pixel), each running one slice of its tile's pixels
+// into a partial buffer, then the reduction of every computed pixel and, at half
+// resolution, the fill.  Returns 0, or the validation status.
+template <int NB>
+static void run_slices(const FrameArgs& A, float* partial, uint32_t chunk) {
+    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+    for (int k = 0; k < kXcds; ++k) {
+        uint32_t first, count;
+        xcd_run(nt, k, first, count);
+        for (uint32_t j = 0; j < count * (uint32_t)A.nd; ++j) {
+            uint32_t tile;
+            int slice, tx, ty;
+            slice_item(chunk, A.nd, count, j, tile, slice);
+            walk_tile(A, first + tile, tx, ty);
+            for (int t = 0; t < 256; ++t) {
+                int x, y, li;
+                tile_pixel(A, tx, ty, t, x, y, li);
+                if ((unsigned)x < (unsigned)A.W && (unsigned)y < (unsigned)A.H)
+                    gather_pixel<-1, MODE_PARTIAL, false, -1, NB>(A, g_lds, x, y, slice, A.nd, nullptr, partial);
+            }
+        }
+    }
+}
+
+extern "C" int host_gather_slices(const ssvb_image* depth, const ssvb_image* normal, const ssvb_image* radiance,
+                                  const ssvb_camera* camera, const ssvb_params* params, const ssvb_outputs* out,
+                                  int chunk) {
+    const ssvb_status s = ssvb_validate(depth, normal, radiance, camera, params, out);
+    if (s != SSVB_OK) return (int)s;
+    if ((int64_t)camera->width * camera->height == 0) return 0;
+    static int2 lut[kLutSize];
+    static double2 half[129], half128[513];
+    fill_tables(lut, half, half128);
+    FrameTables tab;
+    tab.d_lut = lut;
+    tab.d_half = half;
+    tab.d_half128 = half128;
+    FrameArgs A;
+    fill_frame(A, &tab, depth, normal, radiance, camera, params, out);
+    if (A.lp > 1) set_launch(A, LaunchShape{A.tile_w * A.lp, A.tile_h, A.strip, 1});
+    const size_t gw = (size_t)(A.W + A.sub - 1) / A.sub, gh = (size_t)(A.H + A.sub - 1) / A.sub;
+    std::vector<float> partial(gw * gh * (size_t)A.nd * kPartialFloats, NAN);
+    if (A.nb == 128) run_slices<128>(A, partial.data(), (uint32_t)chunk);
+    else run_slices<32>(A, partial.data(), (uint32_t)chunk);
+    for (size_t v = 0; v < gh; ++v)
+        for (size_t u = 0; u < gw; ++u) reduce_pixel(A, partial.data(), (int)u * A.sub, (int)v * A.sub);
     if (A.sub == 2)
         for (int y = 0; y < A.H; ++y)
             for (int x = 0; x < A.W; ++x) upsample_pixel(A, x, y);

@@ -13,7 +13,10 @@
 //     form in 32 bits, for any texel a sample can land on, equals the exact one;
 //   - the integer lattice never overflows int32 at the frame's extreme pixels, longest
 //     offsets and every direction of the slice-direction table;
-//   - sampled texels pass the kernels' on-screen test only inside the frame.
+//   - sampled texels pass the kernels' on-screen test only inside the frame;
+//   - in slice-major order, every (tile, slice) item is produced once, every computed
+//     pixel's every slice record lands once at its exact offset inside the partial
+//     buffer, and the reduction reads each pixel's records once, inside the buffer.
 // The half-resolution fill (upsample_pixel) and every denoiser pass (stage_cell and
 // filter_cell over LDS-sized arrays) also run on real host buffers of exactly the bytes
 // the frame's pitches span, so the sanitizer reports any access outside them.
@@ -231,6 +234,82 @@ static void emulate_frame(const FrameArgs& A) {
     CHECK(wrong == 0, "%ld pixels not reached by exactly lp lanes (%dx%d, tile %dx%d, strip %d, lp %d, sub %d)", wrong,
           A.W, A.H, A.tile_w, A.tile_h, A.strip, A.lp, A.sub);
     check_texels(A, S);
+}
+
+// One frame in slice-major order as the library launches it (lanes per pixel forced to 1,
+// then gather_slices and reduce_slices): every (tile, slice) item of every XCD run is
+// produced exactly once by slice_item, every computed pixel's every slice is written once
+// at its exact offset inside the partial buffer, the slice's mask words lie inside the mask
+// image, and the reduction's grid reads each computed pixel's partial sums once, inside
+// the buffer, and writes its outputs inside the images.
+static long g_slice_items = 0;
+static void emulate_slices(const FrameArgs& A0, uint32_t chunk) {
+    FrameArgs A = A0;
+    if (A.lp > 1) set_launch(A, LaunchShape{A.tile_w * A.lp, A.tile_h, A.strip, 1});
+    CHECK(A.lp == 1 && A.tile_w * A.tile_h == 256, "slice-major shape %dx%d lp %d", A.tile_w, A.tile_h, A.lp);
+    const Sizes S = sizes_of(A);
+    const int64_t gw = (A.W + A.sub - 1) / A.sub, gh = (A.H + A.sub - 1) / A.sub;
+    const int64_t floats = gw * gh * A.nd * kPartialFloats;
+    const int words = A.nb / 32;
+    std::vector<uint8_t> seen((size_t)(gw * gh * A.nd), 0);
+    const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
+    for (int k = 0; k < kXcds; ++k) {
+        uint32_t first, count;
+        xcd_run(nt, k, first, count);
+        CHECK((uint64_t)count * (uint64_t)A.nd < ((uint64_t)1 << 32), "run of %u tiles x %d slices", count, A.nd);
+        std::vector<uint8_t> item_seen((size_t)count * A.nd, 0);
+        for (uint32_t j = 0; j < count * (uint32_t)A.nd; ++j) {
+            uint32_t tile = ~0u;
+            int slice = -1, tx = -1, ty = -1;
+            slice_item(chunk, A.nd, count, j, tile, slice);
+            ++g_slice_items;
+            CHECK(tile < count && slice >= 0 && slice < A.nd, "item %u -> tile %u slice %d (run of %u, chunk %u)", j,
+                  tile, slice, count, chunk);
+            if (!(tile < count && slice >= 0 && slice < A.nd)) continue;
+            CHECK(item_seen[(size_t)tile * A.nd + slice]++ == 0, "tile %u slice %d twice", tile, slice);
+            walk_tile(A, first + tile, tx, ty);
+            CHECK(tx >= 0 && tx < A.tiles_x && ty >= 0 && ty < A.tiles_y, "tile (%d, %d)", tx, ty);
+            for (int t = 0; t < 256; ++t) {
+                int x, y, li;
+                tile_pixel(A, tx, ty, t, x, y, li);
+                if (!(x < A.W && y < A.H)) continue;
+                CHECK(x >= 0 && y >= 0 && x % A.sub == 0 && y % A.sub == 0 && li == 0, "pixel (%d, %d)", x, y);
+                const int64_t off = partial_off(A, x, y, slice);
+                const int64_t cell = ((int64_t)(y / A.sub) * gw + x / A.sub) * A.nd + slice;
+                CHECK(off == cell * kPartialFloats && off >= 0 && off + 7 <= floats,
+                      "partial offset %lld of %lld floats, pixel (%d, %d) slice %d", (long long)off, (long long)floats,
+                      x, y, slice);
+                if (off == cell * kPartialFloats && off >= 0 && off + 7 <= floats) seen[(size_t)cell]++;
+                if (A.masks) {
+                    const int64_t m =
+                        (int64_t)y * A.masks_pitch + 4 * ((int64_t)x * A.nd * words + (int64_t)slice * words);
+                    CHECK(m >= 0 && m + 4 * words <= S.masks, "masks (%d, %d) slice %d", x, y, slice);
+                }
+            }
+        }
+    }
+    long wrong = 0;
+    for (uint8_t c : seen) wrong += c != 1;
+    CHECK(wrong == 0, "%ld (pixel, slice) partial records not written exactly once (%dx%d, %d slices, chunk %u)",
+          wrong, A.W, A.H, A.nd, chunk);
+    // reduce_slices: 16 x 16 blocks of the computed grid
+    std::vector<uint8_t> red((size_t)(gw * gh), 0);
+    const int bx = (int)((gw + 15) / 16), by = (int)((gh + 15) / 16);
+    for (int b = 0; b < by; ++b)
+        for (int a = 0; a < bx; ++a)
+            for (int t = 0; t < 256; ++t) {
+                const int u = a * 16 + t % 16, v = b * 16 + t / 16;
+                if (!(u < gw && v < gh)) continue;
+                const int x = u * A.sub, y = v * A.sub;
+                const int64_t p0 = partial_off(A, x, y, 0);
+                CHECK(p0 >= 0 && p0 + (int64_t)(A.nd - 1) * kPartialFloats + 7 <= floats, "reduction of (%d, %d)", x,
+                      y);
+                check_pixel(A, S, x, y, 0);
+                red[(size_t)v * gw + u]++;
+            }
+    wrong = 0;
+    for (uint8_t c : red) wrong += c != 1;
+    CHECK(wrong == 0, "%ld computed pixels not reduced exactly once", wrong);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -592,6 +671,7 @@ static void fuzz(long n, uint64_t seed, long& accepted, long& rejected, long& em
         if ((int64_t)W * H <= 300000) {
             emulate_frame(A);
             ++emulated;
+            emulate_slices(A, (p.seed & 7) == 7 ? 65536u : 1u + (p.seed >> 8) % 300u);
         }
         {
             const Sizes S = sizes_of(A);
@@ -648,9 +728,9 @@ int main(int argc, char** argv) {
     if (fuzz_n > 0) {
         long acc = 0, rej = 0, emu = 0, bat = 0;
         fuzz(fuzz_n, fuzz_seed, acc, rej, emu, bat);
-        printf("fuzz: %ld inputs, %ld accepted (%ld emulated), %ld rejected, %ld batches, %ld upsampled and %ld "
-               "denoised cells on real buffers, %ld checks, %ld failed\n",
-               fuzz_n, acc, emu, rej, bat, g_upsampled, g_denoised, g_checks, g_fail);
+        printf("fuzz: %ld inputs, %ld accepted (%ld emulated), %ld rejected, %ld batches, %ld slice-major items, "
+               "%ld upsampled and %ld denoised cells on real buffers, %ld checks, %ld failed\n",
+               fuzz_n, acc, emu, rej, bat, g_slice_items, g_upsampled, g_denoised, g_checks, g_fail);
         return g_fail != 0;
     }
     // the launch shapes of the autotuner (tile w, h, lanes) x strips, and the default
@@ -709,6 +789,16 @@ int main(int argc, char** argv) {
         emulate_frame(A);
         check_lattice(A);
         ++frames_done;
+        // the slice-major order over chunks of 1, 7 and 64 tiles and one chunk of everything
+        if (!g_interleaved) {
+            for (uint32_t c : {1u, 7u, 64u, 65536u}) {
+                if (big && c != 64u) continue;
+                emulate_slices(A, c);
+            }
+            FrameArgs A2;  // and from a launch shape with lanes per pixel
+            make_frame(f, LaunchShape{8, 8, 3, 4}, true, A2);
+            emulate_slices(A2, 5u);
+        }
         // the half-resolution fill and the denoiser on real buffers of the frame's spans
         if ((int64_t)s.W * s.H <= 400000 && !g_interleaved) {  // independent of the walk
             if (A.sub == 2) g_upsampled += check_upsample(A);
@@ -737,8 +827,9 @@ int main(int argc, char** argv) {
             }
         }
     }
-    printf("%s walk: %ld frame launches, %ld batches, %ld upsampled and %ld denoised cells on real buffers, "
-           "%ld checks, %ld failed\n",
-           g_interleaved ? "interleaved" : "strip", frames_done, batches, g_upsampled, g_denoised, g_checks, g_fail);
+    printf("%s walk: %ld frame launches, %ld batches, %ld slice-major items, %ld upsampled and %ld denoised cells "
+           "on real buffers, %ld checks, %ld failed\n",
+           g_interleaved ? "interleaved" : "strip", frames_done, batches, g_slice_items, g_upsampled, g_denoised,
+           g_checks, g_fail);
     return g_fail != 0;
 }

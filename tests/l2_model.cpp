@@ -14,11 +14,15 @@
 // waves are done.  An instruction's distinct 128-byte lines go to the CU's L1 (LRU, 32 KB)
 // and its misses to the XCD's L2 (LRU, 16-way, 4 MB).  Output writes are not modelled.
 //
-// Orders: "strip" (the library's), "interleaved" (strips 0, 8, 16, ... then 1, 9, ...),
-// "slice<C>" (work items are (tile, slice) pairs: for each chunk of C tiles of the XCD's
-// run, slice 0 of every tile, then slice 1, ...; the per-slice partial sums would be
-// added in slice order afterwards).  Layout "packed" puts a texel's normal and radiance
-// in one 16-byte (FP16) or 32-byte (FP32) record, so one sample's two reads share a line.
+// Orders: "strip" (the library's default), "interleaved" (strips 0, 8, 16, ... then 1, 9,
+// ...), "slice<C>" (the library's slice-major order, ssvb_set_slice_order: work items are
+// (tile, slice) pairs, for each chunk of C tiles of the XCD's run slice 0 of every tile,
+// then slice 1, ...; the partial-sum writes and their reduction are not modelled),
+// "block<X>x<Y>" (the tiles cut into an X x Y grid of blocks, one per XCD, each walked in
+// vertical strips).  The replayed share is XCD 0's unless an XCD is named (a share at the
+// frame's edge loses the samples that fall off it).  Layout "packed" puts a texel's normal
+// and radiance in one 16-byte (FP16) or 32-byte (FP32) record, so one sample's two reads
+// share a line.
 // A layout suffix "+d<w>x<h>" (w h = 32, e.g. "planar+d8x4") stores depth in 2D blocks, a
 // 128-byte line holding w x h texels instead of 32 texels of one row.
 #include <math.h>
@@ -242,7 +246,7 @@ bool issue(Model& M, Wave& w, int cu) {
 int main(int argc, char** argv) {
     if (argc < 14) {
         fprintf(stderr, "usage: l2_model depth normal radiance W H fp16 slices steps radius thickness seed order fraction "
-                        "[layout] [wg_per_cu] [hash]\n");
+                        "[layout] [wg_per_cu] [hash|plain] [xcd]\n");
         return 2;
     }
     Config C;
@@ -266,6 +270,7 @@ int main(int argc, char** argv) {
     }
     const int wg_per_cu = argc > 15 ? atoi(argv[15]) : 4;
     g_hash_sets = argc > 16 && !strcmp(argv[16], "hash");
+    const int xcd = argc > 17 ? atoi(argv[17]) : 0;  // which XCD's share to replay (0..7)
     if (C.order.rfind("slice", 0) == 0) C.chunk = atoi(C.order.c_str() + 5);
     const size_t px = (size_t)C.W * C.H, es = C.fp16 ? 2 : 4;
     std::vector<char> depth(px * 4), normal(px * 3 * es), radiance(px * 3 * es);
@@ -308,7 +313,7 @@ int main(int argc, char** argv) {
 
     const uint32_t nt = (uint32_t)A.tiles_x * (uint32_t)A.tiles_y;
     uint32_t first, count;
-    xcd_run(nt, 0, first, count);
+    xcd_run(nt, xcd, first, count);
     const uint32_t take = std::max<uint32_t>(1, (uint32_t)(count * fraction));
     struct Item {
         int tx, ty, slice;
@@ -335,14 +340,30 @@ int main(int argc, char** argv) {
         }
         walk_tile(A, ord, tx, ty);
     };
-    if (C.chunk > 0) {
-        for (uint32_t c0 = 0; c0 < take; c0 += (uint32_t)C.chunk)
-            for (int s = 0; s < C.nd; ++s)
-                for (uint32_t k = c0; k < std::min(take, c0 + (uint32_t)C.chunk); ++k) {
-                    int tx, ty;
-                    walk_tile(A, first + k, tx, ty);
-                    items.push_back({tx, ty, s});
-                }
+    if (C.order.rfind("block", 0) == 0) {
+        // the frame's tiles cut into a bx x by grid of blocks, one per XCD; this XCD's block
+        // (the top-left one) walked in vertical strips of `strip` tiles, top to bottom
+        int bx = 4, by = 2;
+        sscanf(C.order.c_str() + 5, "%dx%d", &bx, &by);
+        const int bw = (A.tiles_x + bx - 1) / bx, bh = (A.tiles_y + by - 1) / by, S = A.strip;
+        const int x0 = (xcd % bx) * bw, y0 = (xcd / bx) * bh;  // this XCD's block
+        const uint32_t in_block = (uint32_t)bw * (uint32_t)bh;
+        const uint32_t tk = std::max<uint32_t>(1, (uint32_t)(in_block * fraction));
+        for (uint32_t k = 0; k < tk; ++k) {
+            const int strip = (int)(k / (uint32_t)(S * bh)), r = (int)(k % (uint32_t)(S * bh));
+            const int w = std::min(S, bw - strip * S);
+            const int tx = x0 + strip * S + r % w, ty = y0 + r / w;
+            if (tx < A.tiles_x && ty < A.tiles_y) items.push_back({tx, ty, -1});
+        }
+    } else if (C.chunk > 0) {
+        // the library's slice-major items (slice_item) over the replayed tiles of the run
+        for (uint32_t j = 0; j < take * (uint32_t)A.nd; ++j) {
+            uint32_t tile;
+            int s, tx, ty;
+            slice_item((uint32_t)C.chunk, A.nd, take, j, tile, s);
+            walk_tile(A, first + tile, tx, ty);
+            items.push_back({tx, ty, s});
+        }
     } else {
         for (uint32_t k = 0; k < take; ++k) {
             int tx, ty;

@@ -186,6 +186,14 @@ def test_sequence_null_handles(B):
     assert L.ssvb_sequence_destroy(None) == 0
 
 
+def test_slice_order_null_context(B):
+    """ssvb_set_slice_order refuses a missing context, whatever the chunk."""
+    L = B.lib()
+    for chunk in (0, 1, 65536, -1, 65537):
+        assert L.ssvb_set_slice_order(None, chunk) == 1
+    assert "context" in B.lib().ssvb_last_error().decode().lower()
+
+
 def test_validate_depth_span_limit(B):
     # images are addressed with 32-bit byte offsets
     assert status(B, frame(B, W=16384, H=16384, d=setter("pitch_bytes", 65536))) == 0

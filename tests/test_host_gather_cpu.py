@@ -46,6 +46,8 @@ def host():
         L.host_gather.argtypes = [ctypes.POINTER(B.ssvb_image)] * 3 + [
             ctypes.POINTER(B.ssvb_camera), ctypes.POINTER(B.ssvb_params), ctypes.POINTER(B.ssvb_outputs),
             ctypes.c_int32]
+        L.host_gather_slices.restype = ctypes.c_int32
+        L.host_gather_slices.argtypes = L.host_gather.argtypes
         u32p, i32p = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int32)
         L.host_mask_range.restype = ctypes.c_int32
         L.host_mask_range.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, u32p]
@@ -68,7 +70,9 @@ def _image(a, pad=0):
     return B.ssvb_image(a.ctypes.data, a.strides[0], dt, ch), a
 
 
-def run_host(L, gb, cam, masks=True, generic=False, pad=0, **kw):
+def run_host(L, gb, cam, masks=True, generic=False, pad=0, chunk=None, **kw):
+    """The host build on a frame: the single-frame (or with ``generic`` the batch) instance,
+    or with ``chunk`` the slice-major order over chunks of that many tiles."""
     from paper_2301_11376_amd import binding as B
     H, W = gb["depth"].shape
     d, da = _image(gb["depth"], pad)
@@ -84,8 +88,9 @@ def run_host(L, gb, cam, masks=True, generic=False, pad=0, **kw):
     o = B.ssvb_outputs(out["ao"].ctypes.data, out["gi"].ctypes.data, out["ambient"].ctypes.data,
                        out["masks"].ctypes.data if masks else None, 0, 0, 0, 0)
     c, p = bc.to_c(), bp.to_c()
-    st = L.host_gather(ctypes.byref(d), ctypes.byref(n), ctypes.byref(r), ctypes.byref(c), ctypes.byref(p),
-                       ctypes.byref(o), int(generic))
+    fn, last = (L.host_gather, int(generic)) if chunk is None else (L.host_gather_slices, int(chunk))
+    st = fn(ctypes.byref(d), ctypes.byref(n), ctypes.byref(r), ctypes.byref(c), ctypes.byref(p), ctypes.byref(o),
+            last)
     assert st == 0, st
     return out
 
@@ -239,6 +244,74 @@ def test_host_random_cases(host, case):
                                        half["gi"].astype(np.float64), half["ambient"].astype(np.float64))
         assert max(np.abs(half["ao"] - a).max(), np.abs(half["gi"] - g).max(),
                    np.abs(half["ambient"] - m).max()) <= 1e-5
+
+
+SLICE_CASES = {
+    "hash_t04": (PY.VARIANTS["hash_t04"], (64, 48)),
+    "r2_tinf": (PY.VARIANTS["r2_tinf"], (67, 45)),
+    "pseudo_128": (dict(slices=3, steps=6, radius=1.3, thickness=0.3, noise=O.NOISE_R2, seed=2, sectors=128,
+                        hit_criterion=1), (37, 29)),
+    "quad_8dirs": (dict(slices=8, steps=5, radius=1.5, thickness=0.4, noise=O.NOISE_HASH, seed=4,
+                        step_distribution=1, ambient_samples=8), (40, 9)),
+    "half_res": (dict(PY.HALF_CASES["uniform"], resolution=2), (67, 45)),
+    "one_pixel": (dict(slices=2, steps=3, radius=1.0, noise=O.NOISE_HASH, seed=5), (1, 1)),
+}
+
+
+def slice_order_case(L, name, chunks=(1, 3, 64)):
+    """The slice-major order against the pixel-major run of the same instance (the batch
+    kernel's): masks and AO bit for bit (each slice's mask is the same march, and the AO adds
+    the same per-slice terms in the same order), GI and ambient within FP32 rounding of a
+    different summation order; every chunk size gives the same outputs bit for bit (the
+    partial sums do not depend on the order items run in).  The partial buffer starts as
+    NaN, so a (pixel, slice) no item covered would show."""
+    kw, (W, H) = SLICE_CASES[name]
+    gb, cam, sc = PY.tiny(W, H)
+    kw = dict(kw, ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    half = kw.get("resolution", 1) == 2
+    ref = run_host(L, gb, cam, masks=not half, generic=True, **kw)
+    runs = [run_host(L, gb, cam, masks=not half, chunk=c, **kw) for c in chunks]
+    for got in runs[1:]:
+        for k in got:
+            assert np.array_equal(got[k].view(np.uint32), runs[0][k].view(np.uint32)), ("chunk", k)
+    got = runs[0]
+    for k in ("ao", "gi", "ambient"):
+        assert np.all(np.isfinite(got[k])), k
+    if not half:
+        assert np.array_equal(got["masks"], ref["masks"])
+        assert np.array_equal(got["ao"].view(np.uint32), ref["ao"].view(np.uint32))
+    else:
+        assert np.abs(got["ao"] - ref["ao"]).max() <= 1e-6
+    for k in ("gi", "ambient"):
+        np.testing.assert_allclose(got[k], ref[k], rtol=2e-6, atol=1e-7, err_msg=k)
+    return got, gb, cam, kw
+
+
+@pytest.mark.parametrize("name", sorted(SLICE_CASES))
+def test_host_slice_order(host, name):
+    """Slice-major order (ssvb_set_slice_order) against the pixel-major run, and against
+    the oracle with the parity bar (full resolution) or within 1e-3 (half)."""
+    got, gb, cam, kw = slice_order_case(host, name)
+    _, oc = PY.cams(cam)
+    _, op = PY.params(**kw)
+    if kw.get("resolution", 1) == 2:
+        ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op)
+        for k in ("ao", "gi", "ambient"):
+            assert np.abs(got[k] - ref[k]).max() <= 1e-3, k
+    else:
+        ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, return_masks=True)
+        H, W = gb["depth"].shape
+        PY.compare(got, ref, gb, oc, op, agreement=0.0 if H * W < 100 else PY.MASK_AGREEMENT)
+
+
+def test_host_slice_order_background(host):
+    """A frame of sky in slice-major order: the reduction writes AO 1, GI 0, ambient 0 and
+    empty masks (no item writes a background pixel's partial sums)."""
+    cam = make_camera(19, 11, fov_y_deg=60, pitch_deg=0)
+    gb = {"depth": np.zeros((11, 19), np.float32), "normal": np.zeros((11, 19, 3), np.float32),
+          "radiance": np.ones((11, 19, 3), np.float32)}
+    g = run_host(host, gb, cam, chunk=2, slices=3, steps=4, radius=1.0, noise=O.NOISE_HASH, seed=1)
+    assert np.all(g["ao"] == 1) and np.all(g["gi"] == 0) and np.all(g["ambient"] == 0) and np.all(g["masks"] == 0)
 
 
 def _words(bits, nb):

@@ -50,11 +50,13 @@ def run(exe, *args):
 
 def test_strip_walk_index_path(emulator):
     """The library's walk, every launch shape of the autotuner on every frame up to 1080p
-    (four shapes on the 4K frame); on the frames up to 400k pixels also the half-resolution
-    fill and every denoiser pass on real buffers of exactly the frames' spans."""
+    (four shapes on the 4K frame); the slice-major order (items over chunks of 1, 7, 64 and
+    65,536 tiles: each (tile, slice) once, each pixel's partial record once and in bounds,
+    the reduction's grid); on the frames up to 400k pixels also the half-resolution fill and
+    every denoiser pass on real buffers of exactly the frames' spans."""
     out = run(emulator)
-    m = re.search(r"(\d+) upsampled and (\d+) denoised cells", out)
-    assert int(m.group(1)) > 0 and int(m.group(2)) > 0
+    m = re.search(r"(\d+) slice-major items, (\d+) upsampled and (\d+) denoised cells", out)
+    assert int(m.group(1)) > 0 and int(m.group(2)) > 0 and int(m.group(3)) > 0
 
 
 def test_interleaved_walk_reconstruction_index_path(emulator):
@@ -70,7 +72,8 @@ def test_validated_inputs_keep_the_index_path_in_bounds(emulator, seed):
     3 / 4 channels, pitches up to the 4 GiB span, forced and default launch shapes), each
     field now and then outside what the library accepts: every input ssvb_validate accepts
     runs the whole per-frame emulation (tiles, lanes, every texel's 32-bit offsets exact,
-    outputs in bounds) and the lattice check; the small ones also run in random batches of
+    outputs in bounds), the slice-major order with a chunk drawn from the seed, and the
+    lattice check; the small ones also run in random batches of
     up to 64 frames under a random context launch shape (descriptor, packed list, cursor),
     and through the half-resolution fill and every denoiser pass on real buffers of exactly
     their spans (the sanitizer reports any access outside them)."""
