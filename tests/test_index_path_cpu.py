@@ -19,8 +19,14 @@ SRC = os.path.join(ROOT, "tests", "index_path_cpu.cpp")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
+RUNS = {"strip": (), "interleaved": ("--interleaved", "--quick"), "fuzz7": ("--fuzz", "2000", "7"),
+        "fuzz2024": ("--fuzz", "2000", "2024")}
+
+
 @pytest.fixture(scope="module")
 def emulator():
+    """Builds the emulator and starts its four runs at once (they are independent, single
+    threaded and take 20-55 s each); each test waits for its own."""
     if not os.path.exists(HIPCC) or shutil.which("ld") is None:
         pytest.skip("needs hipcc")
     from paper_2301_11376_amd import binding, build_lib
@@ -36,16 +42,24 @@ def emulator():
                SRC, "-L", libdir, "-lssvb", f"-Wl,-rpath,{libdir}", "-o", exe]
         res = subprocess.run(cmd, capture_output=True, text=True)
         assert res.returncode == 0, res.stdout + res.stderr
-        yield exe
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+        procs = {k: subprocess.Popen([exe, *a], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+                 for k, a in RUNS.items()}
+        try:
+            yield procs
+        finally:
+            for p in procs.values():
+                if p.poll() is None:
+                    p.kill()
+                p.communicate()
 
 
-def run(exe, *args):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    res = subprocess.run([exe, *args], capture_output=True, text=True, timeout=900, env=env)
-    print(res.stdout)
-    assert res.returncode == 0, res.stdout + res.stderr
-    assert " 0 failed" in res.stdout
-    return res.stdout
+def run(procs, key):
+    out, err = procs[key].communicate(timeout=900)
+    print(out)
+    assert procs[key].returncode == 0, out + err
+    assert " 0 failed" in out
+    return out
 
 
 def test_strip_walk_index_path(emulator):
@@ -54,7 +68,7 @@ def test_strip_walk_index_path(emulator):
     65,536 tiles: each (tile, slice) once, each pixel's partial record once and in bounds,
     the reduction's grid); on the frames up to 400k pixels also the half-resolution fill and
     every denoiser pass on real buffers of exactly the frames' spans."""
-    out = run(emulator)
+    out = run(emulator, "strip")
     m = re.search(r"(\d+) slice-major items, (\d+) upsampled and (\d+) denoised cells", out)
     assert int(m.group(1)) > 0 and int(m.group(2)) > 0 and int(m.group(3)) > 0
 
@@ -62,7 +76,7 @@ def test_strip_walk_index_path(emulator):
 def test_interleaved_walk_reconstruction_index_path(emulator):
     """The reconstructed interleaved walk (strips 0, 8, 16, ... then 1, 9, ...) with the
     strip widths 1, 2 and 4 and the lp = 1 tiles: in bounds and a bijection as well."""
-    run(emulator, "--interleaved", "--quick")
+    run(emulator, "interleaved")
 
 
 @pytest.mark.parametrize("seed", [7, 2024])
@@ -77,7 +91,7 @@ def test_validated_inputs_keep_the_index_path_in_bounds(emulator, seed):
     up to 64 frames under a random context launch shape (descriptor, packed list, cursor),
     and through the half-resolution fill and every denoiser pass on real buffers of exactly
     their spans (the sanitizer reports any access outside them)."""
-    out = run(emulator, "--fuzz", "2000", str(seed))
+    out = run(emulator, f"fuzz{seed}")
     m = re.search(r"fuzz: (\d+) inputs, (\d+) accepted \((\d+) emulated\), (\d+) rejected, (\d+) batches", out)
     n, acc, emu, rej, bat = (int(v) for v in m.groups())
     assert acc + rej == n and acc >= 0.4 * n and emu >= 0.9 * acc and bat >= 10
