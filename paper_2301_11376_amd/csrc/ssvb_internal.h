@@ -70,9 +70,11 @@ struct FrameArgs {
 // Slice-major order: the work items are (tile, slice) pairs, taken slice by slice over
 // chunks of tiles of each XCD's run, so that the samples in flight on a die point into one
 // wedge of directions; an item writes its slice's sums (kPartialFloats floats: AO, GI rgb,
-// ambient rgb, unused) to a partial buffer at [computed pixel][slice], and a second pass
-// adds the slices in order.
+// ambient rgb, unused) to a partial buffer at [slice][computed row][computed column] (one
+// plane per slice, so a wave's records are contiguous), and a second pass adds the slices
+// in order.
 constexpr int kPartialFloats = 8;
+typedef float PartialQuad __attribute__((ext_vector_type(4)));  // half a record: one 16-byte access
 
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
 
@@ -162,8 +164,8 @@ SSVB_HD void slice_item(uint32_t chunk, int nd, uint32_t count, uint32_t j, uint
 
 // Offset (floats) of the partial sums of slice s of the computed pixel (x, y).
 SSVB_HD int64_t partial_off(const FrameArgs& A, int x, int y, int s) {
-    const int64_t gw = (A.W + A.sub - 1) / A.sub;
-    return (((int64_t)(y / A.sub) * gw + x / A.sub) * A.nd + s) * kPartialFloats;
+    const int64_t gw = (A.W + A.sub - 1) / A.sub, gh = (A.H + A.sub - 1) / A.sub;
+    return (((int64_t)s * gh + y / A.sub) * gw + x / A.sub) * kPartialFloats;
 }
 
 // ---------------------------------------------------------------------------------------

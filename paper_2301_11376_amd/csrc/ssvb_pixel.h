@@ -708,8 +708,9 @@ SSVB_HD void gather_pixel_steps(const FrameArgs& A, ExactLds& L, int x, int y, i
     if (MODE == MODE_PARTIAL) {
         // slice li's sums (the caller runs one slice per thread, lp = N_d; dbg_f is the
         // partial buffer)
-        GMEM float* pr = (GMEM float*)dbg_f + partial_off(A, x, y, li);
-        pr[0] = ao_acc, pr[1] = gir, pr[2] = gig, pr[3] = gib, pr[4] = amr, pr[5] = amg, pr[6] = amb;
+        GMEM PartialQuad* pr = (GMEM PartialQuad*)((GMEM float*)dbg_f + partial_off(A, x, y, li));
+        pr[0] = PartialQuad{ao_acc, gir, gig, gib};
+        pr[1] = PartialQuad{amr, amg, amb, 0.0f};
         return;
     }
     if (MODE != MODE_COMPUTE) return;
@@ -758,12 +759,13 @@ SSVB_HD void reduce_pixel(const FrameArgs& A, const float* partial, int x, int y
         store_background(A, x, y, 0);
         return;
     }
-    const GMEM float* p = (const GMEM float*)partial + partial_off(A, x, y, 0);
     float ao_acc = 0.0f, gir = 0.0f, gig = 0.0f, gib = 0.0f, amr = 0.0f, amg = 0.0f, amb = 0.0f;
-    for (int i = 0; i < A.nd; ++i, p += kPartialFloats) {
-        ao_acc += p[0];
-        gir += p[1], gig += p[2], gib += p[3];
-        amr += p[4], amg += p[5], amb += p[6];
+    for (int i = 0; i < A.nd; ++i) {
+        const GMEM PartialQuad* p = (const GMEM PartialQuad*)((const GMEM float*)partial + partial_off(A, x, y, i));
+        const PartialQuad a = p[0], b = p[1];
+        ao_acc += a.x;
+        gir += a.y, gig += a.z, gib += a.w;
+        amr += b.x, amg += b.y, amb += b.z;
     }
     const float inv_nd = 1.0f / (float)A.nd;
     *(GMEM float*)((GMEM char*)A.ao + (int64_t)y * A.ao_pitch + (int64_t)x * 4) = ao_acc * inv_nd;

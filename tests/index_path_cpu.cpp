@@ -275,11 +275,11 @@ static void emulate_slices(const FrameArgs& A0, uint32_t chunk) {
                 if (!(x < A.W && y < A.H)) continue;
                 CHECK(x >= 0 && y >= 0 && x % A.sub == 0 && y % A.sub == 0 && li == 0, "pixel (%d, %d)", x, y);
                 const int64_t off = partial_off(A, x, y, slice);
-                const int64_t cell = ((int64_t)(y / A.sub) * gw + x / A.sub) * A.nd + slice;
-                CHECK(off == cell * kPartialFloats && off >= 0 && off + 7 <= floats,
+                const int64_t cell = ((int64_t)slice * gh + y / A.sub) * gw + x / A.sub;
+                CHECK(off == cell * kPartialFloats && off >= 0 && off + kPartialFloats <= floats,
                       "partial offset %lld of %lld floats, pixel (%d, %d) slice %d", (long long)off, (long long)floats,
                       x, y, slice);
-                if (off == cell * kPartialFloats && off >= 0 && off + 7 <= floats) seen[(size_t)cell]++;
+                if (off == cell * kPartialFloats && off >= 0 && off + kPartialFloats <= floats) seen[(size_t)cell]++;
                 if (A.masks) {
                     const int64_t m =
                         (int64_t)y * A.masks_pitch + 4 * ((int64_t)x * A.nd * words + (int64_t)slice * words);
@@ -301,9 +301,11 @@ static void emulate_slices(const FrameArgs& A0, uint32_t chunk) {
                 const int u = a * 16 + t % 16, v = b * 16 + t / 16;
                 if (!(u < gw && v < gh)) continue;
                 const int x = u * A.sub, y = v * A.sub;
-                const int64_t p0 = partial_off(A, x, y, 0);
-                CHECK(p0 >= 0 && p0 + (int64_t)(A.nd - 1) * kPartialFloats + 7 <= floats, "reduction of (%d, %d)", x,
-                      y);
+                for (int sl = 0; sl < A.nd; ++sl) {
+                    const int64_t p0 = partial_off(A, x, y, sl);
+                    CHECK(p0 >= 0 && p0 % 4 == 0 && p0 + kPartialFloats <= floats, "reduction of (%d, %d) slice %d", x,
+                          y, sl);
+                }
                 check_pixel(A, S, x, y, 0);
                 red[(size_t)v * gw + u]++;
             }
