@@ -212,7 +212,8 @@ ssvb_status ssvb_compute_batch(ssvb_ctx* ctx, const ssvb_frame* frames, int32_t 
  * autotuned shape of the frame's class, else the default 32 x 8, strip 4, 1 lane). */
 ssvb_status ssvb_set_launch(ssvb_ctx* ctx, const ssvb_launch* shape);
 
-/* Work order of this context's later ssvb_compute calls (not batches or servers).
+/* Work order of this context's later ssvb_compute calls, frame sequences included (not
+ * batches or servers).
  * chunk_tiles 0 (the default): each workgroup runs every slice of its tile.  chunk_tiles
  * C in 1..65536: slice-major order, for cache locality (a pixel's slices turn by its own
  * random offset, so one slice of many pixels samples one wedge of directions rather than

@@ -478,8 +478,8 @@ class Context:
             check(lib().ssvb_set_launch(self.handle, ctypes.byref(L)), "ssvb_set_launch")
 
     def set_slice_order(self, chunk_tiles: int = 0):
-        """Slice-major work order of later compute calls in chunks of `chunk_tiles` tiles
-        (0: each workgroup runs every slice of its tile)."""
+        """Slice-major work order of later compute calls and sequence steps in chunks of
+        `chunk_tiles` tiles (0: each workgroup runs every slice of its tile)."""
         check(lib().ssvb_set_slice_order(self.handle, int(chunk_tiles)), "ssvb_set_slice_order")
 
     def get_launch(self, camera: Camera, params: Params, fp16_mask=0):
