@@ -33,6 +33,14 @@ def ctx():
     c.close()
 
 
+def host_copy(out):
+    """Outputs on the host; the masks as unsigned words, as the oracle returns them."""
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    if "masks" in res:
+        res["masks"] = res["masks"].view(np.uint32)
+    return res
+
+
 def both_orders(ctx, gb, cam, kw, chunks=(1, 64, 65536), masks=True):
     """Outputs of the default order and of the slice-major order at each chunk size."""
     import torch
@@ -41,14 +49,14 @@ def both_orders(ctx, gb, cam, kw, chunks=(1, 64, 65536), masks=True):
     t = PY.to_device(gb)
     ref = ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp, masks=masks)
     torch.cuda.synchronize()
-    ref = {k: v.cpu().numpy() for k, v in ref.items()}
+    ref = host_copy(ref)
     runs = []
     try:
         for c in chunks:
             ctx.set_slice_order(c)
             got = ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp, masks=masks)
             torch.cuda.synchronize()
-            runs.append({k: v.cpu().numpy() for k, v in got.items()})
+            runs.append(host_copy(got))
     finally:
         ctx.set_slice_order(0)
     return ref, runs
@@ -159,7 +167,7 @@ def test_slice_order_buffer_growth_two_streams(ctx):
         for t, bc, bp, W, H in frames:
             out = ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp)
             torch.cuda.synchronize()
-            alone.append({k: v.cpu().numpy() for k, v in out.items()})
+            alone.append(host_copy(out))
     finally:
         ctx.set_slice_order(0)
     fresh = Context(0)
