@@ -129,14 +129,14 @@ def test_slice_order_background(ctx):
 
 
 def test_slice_order_1080p_sampled(ctx):
-    """The 1920x1080 workload frame in slice-major order (chunk 64): against the default
+    """The 1920x1080 workload frame in slice-major order (chunk 256): against the default
     order over the whole frame, and the oracle on a seeded sample of 3,000 pixels."""
     gb, cam, w, sc = workload("c2_1080p")
     log("slice order 1920x1080")
     H, W = gb["depth"].shape
     kw = dict(slices=4, steps=16, radius=3.0, thickness=0.5, noise=O.NOISE_R2, seed=2,
               ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
-    ref, runs = both_orders(ctx, gb, cam, kw, chunks=(64,))
+    ref, runs = both_orders(ctx, gb, cam, kw, chunks=(256,))
     got = check_orders(ref, runs)
     pix = PY.sample_pixels(H, W, 3000, 2)
     _, oc = PY.cams(cam)
