@@ -5,7 +5,8 @@ Held out of collection until it has passed on the GPU: run it by naming the file
 (python -m pytest tests/wip_slice_order.py -m gpu).  Bars: masks and AO equal to the default
 order's bit for bit (the same per-slice march; the AO adds multiples of 1/N_b, exact in
 any order), GI and ambient within FP32 rounding of a different grouping of the same
-terms, every chunk size the same outputs bit for bit, and the oracle's parity bar."""
+terms (5e-6 relative, 1e-6 absolute), every chunk size the same outputs bit for bit, and
+the oracle's parity bar."""
 import sys
 
 import numpy as np
@@ -75,8 +76,11 @@ def check_orders(ref, runs, bitwise_ao=True):
         assert np.array_equal(got["ao"].view(np.uint32), ref["ao"].view(np.uint32))
     else:
         assert np.abs(got["ao"] - ref["ao"]).max() <= 1e-6
+    # the same FP32 terms summed in another grouping: at the 1080p and 4K workloads the host
+    # build of both orders differs by at most 1.9e-7 absolute and 6e-7 relative; the bar
+    # leaves a factor of about 5-10 for the device's own contraction choices
     for k in ("gi", "ambient"):
-        np.testing.assert_allclose(got[k], ref[k], rtol=2e-6, atol=1e-7, err_msg=k)
+        np.testing.assert_allclose(got[k], ref[k], rtol=5e-6, atol=1e-6, err_msg=k)
     return got
 
 
