@@ -227,7 +227,8 @@ def test_host_random_cases(host, case):
     sub-pixel steps, quadratic steps, 32 / 128 sectors, N_a): the host build against the
     oracle, every mismatch traced to near-tie endpoints and outputs within 1e-3; one in four
     also at half resolution (gathered pixels those of the traced full-resolution run bit for
-    bit, the upsampler the oracle's FP64 one within 1e-5).  The 99.9 % mask agreement floor
+    bit, the upsampler the oracle's FP64 one within 1e-5), and another one in four in the
+    slice-major order too.  The 99.9 % mask agreement floor
     is not applied: these
     scenes are axis-aligned planes, so under PSEUDOCODE whole rows of samples lie exactly
     in a pixel's tangent plane, on a hemisphere edge, where the ceiling of a zero width
@@ -236,6 +237,14 @@ def test_host_random_cases(host, case):
     gb, cam, kw = PY.random_case(rng)
     H, W = gb["depth"].shape
     full = host_case(host, gb, cam, bar=dict(agreement=0.0, max_bad=H * W), **kw)
+    if case % 4 == 1:
+        # the slice-major order over chunks of 1-7 tiles: the same masks and AO, GI and
+        # ambient within FP32 rounding of the other grouping
+        so = run_host(host, gb, cam, chunk=1 + case % 7, **kw)
+        assert np.array_equal(so["masks"], full["masks"])
+        assert np.array_equal(so["ao"].view(np.uint32), full["ao"].view(np.uint32))
+        for k in ("gi", "ambient"):
+            np.testing.assert_allclose(so[k], full[k], rtol=5e-6, atol=1e-6, err_msg=k)
     if case % 4 == 3:
         half = run_host(host, gb, cam, masks=False, resolution=2, **kw)
         for k in ("ao", "gi", "ambient"):
