@@ -23,6 +23,7 @@ import json
 import os
 import sys
 import time
+import traceback
 
 import numpy as np
 
@@ -640,6 +641,24 @@ def frame_leg(ctx, name, gb, cam, w, scene, steps, warmup, own_noise=True, tune=
     return res, (t, c, p, out)
 
 
+def run_leg(into, key, fn, *a, say=None, **k):
+    """Run one leg after the headline into `into[key]`.  A Python-level failure (an exception
+    from the leg, a status the library returned) is printed with its traceback and
+    recorded as {"error": ...} under the key, so the measurements already taken still reach
+    the JSON line; a device fault still ends the process.  `say` formats a progress line
+    from the leg's result."""
+    try:
+        r = fn(*a, **k)
+    except Exception as e:
+        traceback.print_exc(file=sys.stderr)
+        into[key] = {"error": f"{type(e).__name__}: {e}"}
+        return None
+    into[key] = r
+    if say is not None:
+        print(say(r), file=sys.stderr, flush=True)
+    return r
+
+
 def slice_order_leg(ctx, tensors, chunk, steps, warmup=3):
     """The same frame in slice-major order (chunks of `chunk` tiles; both kernels, the
     per-slice gather and the reduction, inside the timed region), against the default
@@ -809,25 +828,21 @@ def main():
         cpu["workloads"] = base
         result["cpu_baseline"] = cpu
     if args.slice_order:
-        result["slice_order"] = {args.workload: slice_order_leg(ctx, tensors, args.slice_order, args.steps)}
+        result["slice_order"] = {}
+        run_leg(result["slice_order"], args.workload, slice_order_leg, ctx, tensors, args.slice_order, args.steps)
     parity = {}
     if args.workload in refs:
-        parity[args.workload] = parity_leg(ctx, args.workload, tensors, refs[args.workload])
+        run_leg(parity, args.workload, parity_leg, ctx, args.workload, tensors, refs[args.workload])
     if not args.no_table2 and args.workload == "c2_1080p":
-        result["table2"] = table2_leg(ctx, t, c, scene, slices=1)
-        print("table2: " + ", ".join(f"{r['row']} {r['ms']:.3f} ms" for r in result["table2"]["rows"]),
-              file=sys.stderr, flush=True)
-        result["denoise"] = denoise_leg(ctx, t, c, out, 20)
-        result["bounce"] = bounce_leg(ctx, t, out, 20)
-        print(f"bounce: {result['bounce']['ms']:.3f} ms, {result['bounce']['achieved_gbs']:.0f} GB/s",
-              file=sys.stderr, flush=True)
-        result["sequence"] = sequence_leg(ctx, t, c, p, 20)
-        print(f"sequence: {result['sequence']['ms_per_step']:.3f} ms per step, gather alone "
-              f"{result['sequence']['gather_ms']:.3f} ms", file=sys.stderr, flush=True)
-        print(f"denoise: {result['denoise']['ms']:.3f} ms", file=sys.stderr, flush=True)
-        result["sectors128"] = sectors_leg(ctx, t, c, p)
-        print(f"sectors: 32 {result['sectors128']['ms_32']:.3f} ms, 128 {result['sectors128']['ms_128']:.3f} ms",
-              file=sys.stderr, flush=True)
+        run_leg(result, "table2", table2_leg, ctx, t, c, scene, slices=1,
+                say=lambda r: "table2: " + ", ".join(f"{x['row']} {x['ms']:.3f} ms" for x in r["rows"]))
+        run_leg(result, "denoise", denoise_leg, ctx, t, c, out, 20, say=lambda r: f"denoise: {r['ms']:.3f} ms")
+        run_leg(result, "bounce", bounce_leg, ctx, t, out, 20,
+                say=lambda r: f"bounce: {r['ms']:.3f} ms, {r['achieved_gbs']:.0f} GB/s")
+        run_leg(result, "sequence", sequence_leg, ctx, t, c, p, 20,
+                say=lambda r: f"sequence: {r['ms_per_step']:.3f} ms per step, gather alone {r['gather_ms']:.3f} ms")
+        run_leg(result, "sectors128", sectors_leg, ctx, t, c, p,
+                say=lambda r: f"sectors: 32 {r['ms_32']:.3f} ms, 128 {r['ms_128']:.3f} ms")
     del t, out, tensors
     for n in names:
         if n == args.workload:
@@ -836,12 +851,17 @@ def main():
         if n == "c3_4k_fp16":
             # at 4K the default shape is not the fastest (the autotuner's pick measured 4 %
             # faster), so this leg runs the shape the library's autotuner picks
-            res, tens = frame_leg(ctx, n, gb_n, cam_n, w_n, sc_n, args.c3_steps, 2, w_n["own_noise"],
-                                  tune=not args.no_autotune)
-            result["c3_4k_fp16"] = res
+            legs = {}
+            run_leg(legs, n, frame_leg, ctx, n, gb_n, cam_n, w_n, sc_n, args.c3_steps, 2, w_n["own_noise"],
+                    tune=not args.no_autotune)
+            if isinstance(legs[n], dict):  # the leg's error record
+                result[n] = legs[n]
+                torch.cuda.empty_cache()
+                continue
+            result[n], tens = legs[n]
             if args.slice_order:
-                result.setdefault("slice_order", {})[n] = slice_order_leg(ctx, tens, args.slice_order,
-                                                                          args.c3_steps)
+                run_leg(result.setdefault("slice_order", {}), n, slice_order_leg, ctx, tens, args.slice_order,
+                        args.c3_steps)
         else:
             from paper_2301_11376_amd import Camera, Params, NOISE_NAMES
             tt = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in gb_n.items()}
@@ -852,18 +872,18 @@ def main():
                         ambient_sh=tuple(float(v) for v in sc_n.ambient_sh.reshape(-1)))
             tens = (tt, cc, pp, None)
         if n in refs:
-            parity[n] = parity_leg(ctx, n, tens, refs[n])
+            run_leg(parity, n, parity_leg, ctx, n, tens, refs[n])
         del tens
         torch.cuda.empty_cache()
     if parity:
         result["parity"] = parity
     if not args.no_batch:
-        result["batch"] = batch_leg(ctx, pool, autotune=not args.no_autotune)
-        result["batch_small"] = batch_leg(ctx, pool, autotune=not args.no_autotune, kind="small")
+        run_leg(result, "batch", batch_leg, ctx, pool, autotune=not args.no_autotune)
+        run_leg(result, "batch_small", batch_leg, ctx, pool, autotune=not args.no_autotune, kind="small")
     if not args.no_serve:
         rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
-        result["serving"] = serve_leg(ctx, pool, args.serve_requests, rates)
-    ctx.close()
+        run_leg(result, "serving", serve_leg, ctx, pool, args.serve_requests, rates)
+    run_leg({}, "close", ctx.close)
     print(json.dumps(result), flush=True)
 
 
