@@ -133,6 +133,52 @@ extern "C" int host_gather_slices(const ssvb_image* depth, const ssvb_image* nor
     return 0;
 }
 
+// The FP32 sector arguments of every sample of a frame (the endpoint hook's instances, at
+// 32 or 128 sectors), for the error bound behind the exact decision's guard band: ep holds
+// W * H * N_d * 2 * N_s * 2 floats per pixel, slice, side (+ then -), step and argument,
+// left as the caller filled them for skipped samples.  Returns 0, or the validation status.
+template <int CRIT, int NB>
+static void run_endpoints(const FrameArgs& A, float* ep) {
+    const int64_t per = (int64_t)A.nd * 2 * A.ns * 2;
+    for (int y = 0; y < A.H; ++y)
+        for (int x = 0; x < A.W; ++x) {
+            float* d = ep + ((int64_t)y * A.W + x) * per;
+            if (A.normal_f16) gather_pixel<CRIT, MODE_ENDPOINTS, false, 1, NB>(A, g_lds, x, y, 0, 1, nullptr, d);
+            else gather_pixel<CRIT, MODE_ENDPOINTS, false, 0, NB>(A, g_lds, x, y, 0, 1, nullptr, d);
+        }
+}
+
+extern "C" int host_endpoints(const ssvb_image* depth, const ssvb_image* normal, const ssvb_image* radiance,
+                              const ssvb_camera* camera, const ssvb_params* params, const ssvb_outputs* out,
+                              float* ep) {
+    const ssvb_status s = ssvb_validate(depth, normal, radiance, camera, params, out);
+    if (s != SSVB_OK) return (int)s;
+    if ((int64_t)camera->width * camera->height == 0) return 0;
+    static int2 lut[kLutSize];
+    static double2 half[129], half128[513];
+    fill_tables(lut, half, half128);
+    FrameTables tab;
+    tab.d_lut = lut;
+    tab.d_half = half;
+    tab.d_half128 = half128;
+    FrameArgs A;
+    fill_frame(A, &tab, depth, normal, radiance, camera, params, out);
+    const bool round = A.criterion == SSVB_HIT_ROUND;
+    if (A.nb == 128) {
+        if (round) run_endpoints<SSVB_HIT_ROUND, 128>(A, ep);
+        else run_endpoints<SSVB_HIT_PSEUDOCODE, 128>(A, ep);
+    } else {
+        if (round) run_endpoints<SSVB_HIT_ROUND, 32>(A, ep);
+        else run_endpoints<SSVB_HIT_PSEUDOCODE, 32>(A, ep);
+    }
+    return 0;
+}
+
+// atan2_pos, the kernels' FP32 arc tangent for y >= 0, on n argument pairs.
+extern "C" void host_atan2(const float* y, const float* x, float* out, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) out[i] = atan2_pos(y[i], x[i]);
+}
+
 // The visibility-mask primitives at N_b = 32, 64 or 128 sectors, for exhaustive checks:
 // host_mask_range writes mask_range(a, b)'s N_b / 32 words; host_mask_cover ORs the ranges
 // [a[j], b[j]) into an empty mask in order with cover(), writing each step's newly covered

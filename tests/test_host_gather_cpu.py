@@ -48,6 +48,11 @@ def host():
             ctypes.c_int32]
         L.host_gather_slices.restype = ctypes.c_int32
         L.host_gather_slices.argtypes = L.host_gather.argtypes
+        f32p = ctypes.POINTER(ctypes.c_float)
+        L.host_endpoints.restype = ctypes.c_int32
+        L.host_endpoints.argtypes = L.host_gather.argtypes[:6] + [f32p]
+        L.host_atan2.restype = None
+        L.host_atan2.argtypes = [f32p, f32p, f32p, ctypes.c_int64]
         u32p, i32p = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int32)
         L.host_mask_range.restype = ctypes.c_int32
         L.host_mask_range.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, u32p]
@@ -321,6 +326,80 @@ def test_host_slice_order_background(host):
           "radiance": np.ones((11, 19, 3), np.float32)}
     g = run_host(host, gb, cam, chunk=2, slices=3, steps=4, radius=1.0, noise=O.NOISE_HASH, seed=1)
     assert np.all(g["ao"] == 1) and np.all(g["gi"] == 0) and np.all(g["ambient"] == 0) and np.all(g["masks"] == 0)
+
+
+def test_atan2_error_bound(host):
+    """The kernels' FP32 arc tangent (octant reduction to r = min / max, odd degree-13
+    minimax polynomial) against FP64 atan2 of the same FP32 arguments, over a dense sweep of
+    r in [0, 1] in every octant of the upper half plane, at random magnitudes, and at the
+    special arguments (y = 0, x = 0, y = |x|, x = -inf): |error| < 3.3e-7 rad for the
+    polynomial alone (r exact, first octant) and < 5.5e-7 rad everywhere (the rounding of r,
+    and pi/2 - a and pi - a rounded to FP32, whose ulp near pi is 2.4e-7).  The host's
+    exact division stands in for the device's reciprocal (about 1 ulp of r more)."""
+    rng = np.random.default_rng(5)
+    r = np.linspace(0.0, 1.0, 400001)
+    ys, xs = [], []
+    for a, b in ((r, 1.0), (1.0, r), (r, -1.0), (1.0, -r)):
+        scale = 10.0 ** rng.uniform(-18, 18, r.size)
+        ys.append(np.broadcast_to(a, r.shape) * scale)
+        xs.append(np.broadcast_to(b, r.shape) * scale)
+    ys.append(np.array([0.0, 0.0, 1.0, 1.0, 1.0, 0.0, 3.0, 1e-30]))
+    xs.append(np.array([1.0, -1.0, 0.0, 1.0, -1.0, -np.inf, -np.inf, 1e30]))
+    y = np.ascontiguousarray(np.concatenate(ys), np.float32)
+    x = np.ascontiguousarray(np.concatenate(xs), np.float32)
+    out = np.empty_like(y)
+    f32p = ctypes.POINTER(ctypes.c_float)
+    host.host_atan2(y.ctypes.data_as(f32p), x.ctypes.data_as(f32p), out.ctypes.data_as(f32p), y.size)
+    err = np.abs(out.astype(np.float64) - np.arctan2(y.astype(np.float64), x.astype(np.float64)))
+    assert np.all(np.isfinite(out)) and err.max() < 5.5e-7, err.max()
+    # the polynomial alone: r exact (x = 1), first octant
+    r32 = np.ascontiguousarray(r, np.float32)
+    one = np.ones_like(r32)
+    poly = np.empty_like(r32)
+    host.host_atan2(r32.ctypes.data_as(f32p), one.ctypes.data_as(f32p), poly.ctypes.data_as(f32p), r32.size)
+    perr = np.abs(poly.astype(np.float64) - np.arctan(r32.astype(np.float64))).max()
+    assert perr < 3.3e-7, perr
+
+
+ENDPOINT_CASES = {
+    "hash_t04": dict(slices=4, steps=12, radius=1.5, thickness=0.4, noise=O.NOISE_HASH, seed=3),
+    "r2_tinf": dict(slices=2, steps=8, radius=3.0, thickness=float("inf"), noise=O.NOISE_R2, seed=4),
+    "pseudocode": dict(slices=2, steps=8, radius=1.0, thickness=0.2, noise=O.NOISE_HASH, seed=5, hit_criterion=1),
+    "slope_quad": dict(slices=3, steps=10, radius=2.0, thickness=0.1, thickness_slope=0.05, noise=O.NOISE_R2,
+                       seed=6, step_distribution=1),
+}
+
+
+@pytest.mark.parametrize("sectors", [32, 128])
+@pytest.mark.parametrize("name", sorted(ENDPOINT_CASES))
+def test_host_endpoint_error_within_guard(host, name, sectors):
+    """Every sample's FP32 sector arguments (the kernels' own code) against the oracle's
+    FP64 ones: the same samples skipped, and every argument within 2^-16 sectors (in units
+    of the mask's sectors), half the band in which the kernels re-decide in FP64 (2^-15
+    sectors, scaled with N_b), so the exact decision covers every rounding the FP32 path
+    can get wrong.  The GPU test of the same hook holds the device to the same bar."""
+    from paper_2301_11376_amd import binding as B
+    gb, cam, sc = PY.tiny()
+    kw = dict(ENDPOINT_CASES[name], sectors=sectors)
+    H, W = gb["depth"].shape
+    d, da = _image(gb["depth"])
+    n, na = _image(gb["normal"])
+    r, ra = _image(gb["radiance"])
+    bc, oc = PY.cams(cam)
+    bp, op = PY.params(**kw)
+    ao, gi, am = np.zeros((H, W), np.float32), np.zeros((H, W, 3), np.float32), np.zeros((H, W, 3), np.float32)
+    o = B.ssvb_outputs(ao.ctypes.data, gi.ctypes.data, am.ctypes.data, None, 0, 0, 0, 0)
+    ep = np.full((H, W, kw["slices"], 2, kw["steps"], 2), np.nan, np.float32)
+    c, p = bc.to_c(), bp.to_c()
+    st = host.host_endpoints(ctypes.byref(d), ctypes.byref(n), ctypes.byref(r), ctypes.byref(c), ctypes.byref(p),
+                             ctypes.byref(o), ep.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    assert st == 0, st
+    ref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, return_endpoints=True)["endpoints"]
+    assert np.array_equal(np.isnan(ep), np.isnan(ref))
+    ok = np.isfinite(ref)
+    err = np.abs(ep[ok] - ref[ok]).max()
+    print(f"{name}, {sectors} sectors: max endpoint error {err:.3e} sectors over {ok.sum()} values")
+    assert ok.sum() > 1000 and err < 2.0 ** -16 * (sectors // 32), err
 
 
 def _words(bits, nb):
