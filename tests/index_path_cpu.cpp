@@ -2,8 +2,9 @@
 //
 // The kernels' index functions (XCD runs, tile walk, tile -> pixel, batch cursor, step
 // offsets, lattice, image offsets) are __host__ __device__ and are called here as written;
-// the frame constants come from the library's own fill_frame / build_batch (libssvb.so,
-// no GPU needed).  For every frame and launch shape below the emulation claims every work
+// the frame constants come from the library's own fill_frame / build_batch (its sources
+// are built into the test program, their host code under the sanitizers too; no GPU
+// needed).  For every frame and launch shape below the emulation claims every work
 // item the way the persistent kernels do and checks, with bounds assertions (and ASan /
 // UBSan in the test build), that
 //   - every tile of every frame is claimed exactly once, and every computed pixel is

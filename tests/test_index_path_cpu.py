@@ -1,6 +1,7 @@
 """CPU test of the gather kernels' complete index path (index_path_cpu.cpp): the kernels'
 own __host__ __device__ index functions and the library's own frame constants (fill_frame,
-build_batch from libssvb.so), built with hipcc for the host under ASan and UBSan, over
+build_batch, fill_denoise, ssvb_validate: the library's sources compiled in), all host code
+under ASan and UBSan, over
 every frame shape and launch shape the GPU suite uses (autotuner tiles, lanes per pixel
 1-8, strips 1-8, full and half resolution, both mask widths, pitched buffers, 16384-pixel
 frames): every tile is claimed once, every computed pixel reached by each of its lanes
@@ -23,24 +24,35 @@ RUNS = {"strip": (), "interleaved": ("--interleaved", "--quick"), "fuzz7": ("--f
         "fuzz2024": ("--fuzz", "2000", "2024")}
 
 
+CSRC = os.path.join(ROOT, "paper_2301_11376_amd", "csrc")
+# the library's sources, built into the emulator with the sanitizers on their host code
+# (the device code is built too, only because the kernels' launch stubs refer to it)
+LIB_SOURCES = ["ssvb_kernels.hip", "ssvb_denoise.hip", "ssvb_api.cpp", "ssvb_server.cpp", "ssvb_sequence.cpp"]
+
+
 @pytest.fixture(scope="module")
 def emulator():
-    """Builds the emulator and starts its four runs at once (they are independent, single
-    threaded and take 20-55 s each); each test waits for its own."""
+    """Builds the emulator (its own source and the library's, compiled in parallel, the
+    host code under ASan and UBSan) and starts its four runs at once (they are independent,
+    single threaded and take 20-55 s each); each test waits for its own."""
     if not os.path.exists(HIPCC) or shutil.which("ld") is None:
         pytest.skip("needs hipcc")
-    from paper_2301_11376_amd import binding, build_lib
-    if not os.path.exists(binding.LIB_PATH):
-        build_lib.build()
-    libdir = os.path.dirname(binding.LIB_PATH)
+    common = ["-O1", "-g", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+              "-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=all"]
+    device = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     with tempfile.TemporaryDirectory() as d:
+        jobs = {os.path.join(d, "index_path.o"): ["-x", "hip", "--cuda-host-only", *common, "-c", SRC]}
+        for src in LIB_SOURCES:
+            extra = device if src.endswith(".hip") else []
+            jobs[os.path.join(d, src + ".o")] = [*extra, *common, "-c", os.path.join(CSRC, src)]
+        builds = {o: subprocess.Popen([HIPCC, *args, "-o", o], stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                      text=True) for o, args in jobs.items()}
+        for o, b in builds.items():
+            out, _ = b.communicate(timeout=600)
+            assert b.returncode == 0, out
         exe = os.path.join(d, "index_path")
-        # host-only build; the sanitizers apply to the host code
-        cmd = [HIPCC, "-x", "hip", "--cuda-host-only", "-O1", "-g", "-std=c++17",
-               "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2301_11376_amd", "csrc"),
-               "-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=all",
-               SRC, "-L", libdir, "-lssvb", f"-Wl,-rpath,{libdir}", "-o", exe]
-        res = subprocess.run(cmd, capture_output=True, text=True)
+        res = subprocess.run([HIPCC, "-Xarch_host", "-fsanitize=address,undefined", "--hip-link", *jobs, "-o", exe],
+                             capture_output=True, text=True)
         assert res.returncode == 0, res.stdout + res.stderr
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
         procs = {k: subprocess.Popen([exe, *a], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
