@@ -72,9 +72,9 @@ hipError_t launch_inject_bounce(const char* direct, int64_t direct_pitch, int di
                                 const char* albedo, int64_t albedo_pitch, int albedo_ch, int albedo_f16,
                                 const float* gi, int64_t gi_pitch, char* next, int64_t next_pitch, int next_ch,
                                 int next_f16, int W, int H, float gain, hipStream_t stream);
-// Slice-major order (A.lp = 1; `partial` holds computed pixels x N_d x kPartialFloats
-// floats; chunks of `chunk` tiles): the per-slice gather, then the reduction that writes the
-// outputs; `queues` as for launch_plain.
+// Slice-major order (A.lp = 1; `partial` holds N_d planes of computed pixels x
+// kPartialFloats floats, see partial_off; chunks of `chunk` >= 1 tiles): the per-slice
+// gather, then the reduction that writes the outputs; `queues` as for launch_plain.
 hipError_t launch_slices(const FrameArgs& A, uint32_t* queues, int grid, float* partial, uint32_t chunk,
                          hipStream_t stream);
 // Half resolution: fill the pixels with an odd coordinate from the computed ones.
