@@ -246,7 +246,7 @@ bool issue(Model& M, Wave& w, int cu) {
 int main(int argc, char** argv) {
     if (argc < 14) {
         fprintf(stderr, "usage: l2_model depth normal radiance W H fp16 slices steps radius thickness seed order fraction "
-                        "[layout] [wg_per_cu] [hash|plain] [xcd]\n");
+                        "[layout] [wg_per_cu] [hash|plain] [xcd] [r2|hash|fixed]\n");
         return 2;
     }
     Config C;
@@ -271,6 +271,7 @@ int main(int argc, char** argv) {
     const int wg_per_cu = argc > 15 ? atoi(argv[15]) : 4;
     g_hash_sets = argc > 16 && !strcmp(argv[16], "hash");
     const int xcd = argc > 17 ? atoi(argv[17]) : 0;  // which XCD's share to replay (0..7)
+    const char* noise = argc > 18 ? argv[18] : "r2";   // r2 (the workloads'), hash or fixed
     if (C.order.rfind("slice", 0) == 0) C.chunk = atoi(C.order.c_str() + 5);
     const size_t px = (size_t)C.W * C.H, es = C.fp16 ? 2 : 4;
     std::vector<char> depth(px * 4), normal(px * 3 * es), radiance(px * 3 * es);
@@ -301,7 +302,7 @@ int main(int argc, char** argv) {
     p.steps = C.ns;
     p.radius = radius;
     p.thickness = thickness;
-    p.noise = SSVB_NOISE_R2;
+    p.noise = !strcmp(noise, "fixed") ? SSVB_NOISE_FIXED : !strcmp(noise, "hash") ? SSVB_NOISE_HASH : SSVB_NOISE_R2;
     p.seed = seed;
     const ssvb_dtype dt = C.fp16 ? SSVB_F16 : SSVB_F32;
     ssvb_image d{depth.data(), 0, SSVB_F32, 1}, n{normal.data(), 0, dt, 3}, r{radiance.data(), 0, dt, 3};
