@@ -27,3 +27,22 @@ def test_traffic_records_are_well_formed():
         assert abs(total - rec["traffic_bytes_per_launch"]) < 1.0
         # reported only for the shape and the device sources the counters were taken with
         assert bench.measured_traffic(name, (1, 1, 1, 1)) is None
+
+
+def test_a_failing_leg_is_recorded_not_fatal(capsys):
+    """A leg after the headline that raises is recorded as {"error": ...} in its field and
+    the run goes on; a leg that succeeds stores its result and prints its progress line."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    def boom():
+        raise RuntimeError("planted")
+
+    res = {}
+    assert bench.run_leg(res, "bad", boom) is None
+    assert res["bad"] == {"error": "RuntimeError: planted"}
+    assert bench.run_leg(res, "good", lambda a, b=0: {"ms": a + b}, 1.5, b=0.5,
+                         say=lambda r: f"good: {r['ms']} ms") == {"ms": 2.0}
+    assert res["good"] == {"ms": 2.0}
+    err = capsys.readouterr().err
+    assert "planted" in err and "good: 2.0 ms" in err
