@@ -198,9 +198,10 @@ ssvb_status ssvb_compute(ssvb_ctx* ctx, const ssvb_image* depth, const ssvb_imag
  * upload, queue reset, a persistent kernel per mask width present, then the
  * half-resolution fill if any frame asks for it) with their tiles packed into one list
  * cut into equal-cost runs, one per XCD; larger frames each get the persistent
- * single-frame launch of ssvb_compute (each fills the GPU by itself).  Each frame's
- * outputs equal, bit for bit, what ssvb_compute writes for it with the same launch
- * shape.  The first batch with a new set of frame kinds (mask widths, half resolution)
+ * single-frame launch of ssvb_compute (each fills the GPU by itself; always in the
+ * default work order, see ssvb_set_slice_order).  Each frame's outputs equal, bit for
+ * bit, what ssvb_compute writes for it with the same launch shape and the default work
+ * order.  The first batch with a new set of frame kinds (mask widths, half resolution)
  * captures that set's graph on the calling thread: meanwhile no other thread may
  * synchronise the whole device.  Frames are processed in chunks of 64.  The library keeps
  * two descriptor slots and the 32 counter sets of ssvb_compute, so a call may block until
