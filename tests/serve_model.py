@@ -11,6 +11,7 @@ at a measured rate.  Policies:
              the larger frames shortest first; each part retires when it ends
   one_large  every waiting small frame packed, then only the shortest waiting large frame;
              the other large frames wait for a later round
+  one_oldest the same, with the oldest waiting large frame instead of the shortest
   budget     the small frames packed, then at most `budget` seconds of large-frame work
              (shortest remaining first), the rest resumed in later rounds (a persistent
              kernel that could stop and resume inside a frame)
@@ -55,11 +56,12 @@ def simulate(reqs, arrivals, R, c0, policy="rounds", budget=None):
             for j in sorted(lg, key=lambda j: work[j]):
                 t += c0 + work[j]
                 done[j] = t
-        elif policy == "one_large":
+        elif policy in ("one_large", "one_oldest"):
             for j in lg:
                 carried[j] = work[j]
             if carried:
-                j = min(carried, key=lambda j: carried[j])
+                # dicts keep insertion order: the first key is the oldest
+                j = min(carried, key=lambda j: carried[j]) if policy == "one_large" else next(iter(carried))
                 t += c0 + carried.pop(j)
                 done[j] = t
         elif policy == "budget":
@@ -115,8 +117,8 @@ def table(sat_fps=271.6, load=0.7, c0=1e-4):
     reqs = request_stream()
     R = calibrate(reqs, sat_fps, c0)
     rows = []
-    for pol, b in (("rounds", None), ("one_large", None), ("budget", 2e-3), ("budget", 5e-3), ("budget", 10e-3),
-                   ("budget", 20e-3)):
+    for pol, b in (("rounds", None), ("one_large", None), ("one_oldest", None), ("budget", 2e-3), ("budget", 5e-3),
+                   ("budget", 10e-3), ("budget", 20e-3)):
         sat = saturated(reqs, R, c0, policy=pol, budget=b)
         lat, res = latencies(reqs, R, c0, load * sat_fps, policy=pol, budget=b)
         per = {k: float(np.percentile(lat[res == k], 99)) for k in sorted(set(res), key=lambda s: int(s.split("x")[0]))}
@@ -132,5 +134,5 @@ if __name__ == "__main__":
     R, rows = table()
     print(f"device rate {R / 1e9:.0f} Gsamples/s")
     for pol, b, sat, p50, p99, per in rows:
-        print(f"{pol:9s} {'' if b is None else f'{b:g} ms':6s} saturated {sat:.3f}  p50 {p50:6.2f}  p99 {p99:6.2f}  "
+        print(f"{pol:10s} {'' if b is None else f'{b:g} ms':6s} saturated {sat:.3f}  p50 {p50:6.2f}  p99 {p99:6.2f}  "
               + "  ".join(f"{k} {v:.1f}" for k, v in per.items()))

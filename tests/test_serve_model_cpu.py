@@ -26,5 +26,7 @@ def test_serve_model_reproduces_the_measured_tail_and_keeps_its_structure():
     assert all(np.diff(small_p99) > 0) and all(np.diff(big_p99) < 0)   # the trade, budget by budget
     assert small_p99[0] < 0.3 * per[small] and big_p99[0] > 1.5 * per[big]
     assert all(by[("budget", b)][0] <= 1.0 for b in budgets)
-    assert abs(by[("one_large", None)][0] - 1.0) < 1e-3
+    assert abs(by[("one_large", None)][0] - 1.0) < 1e-3 and abs(by[("one_oldest", None)][0] - 1.0) < 1e-3
+    # small frames first halves their tail whichever large frame goes next
+    assert by[("one_large", None)][3][small] < 0.6 * per[small] and by[("one_oldest", None)][3][small] < 0.6 * per[small]
     assert all(r[4] > 0.8 * p99 for r in rows)   # no policy takes the overall p99 far below
