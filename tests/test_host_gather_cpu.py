@@ -318,6 +318,28 @@ def test_host_slice_order(host, name):
         PY.compare(got, ref, gb, oc, op, agreement=0.0 if H * W < 100 else PY.MASK_AGREEMENT)
 
 
+def test_host_slice_order_1080p_band(host):
+    """A 270-row band across the middle of the 1920x1080 workload frame (its own camera
+    cropped, 2,040 tiles: four chunks of 64 tiles per die's run, the last one shorter) in
+    both orders: masks and AO equal bit for bit, GI and ambient within the GPU test's bar
+    for the two orders (5e-6 relative, 1e-6 absolute)."""
+    import dataclasses
+    gb, cam, w, sc = workload("c2_1080p")
+    r0, r1 = 405, 675
+    gb = {k: np.ascontiguousarray(v[r0:r1]) for k, v in gb.items()}
+    cam = dataclasses.replace(cam, height=r1 - r0, cy=float(np.float32(cam.cy - r0)))
+    kw = dict(slices=4, steps=16, radius=3.0, thickness=0.5, noise=O.NOISE_R2, seed=2,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    a = run_host(host, gb, cam, generic=True, **kw)
+    b = run_host(host, gb, cam, chunk=64, **kw)
+    assert np.array_equal(a["masks"], b["masks"])
+    assert np.array_equal(a["ao"].view(np.uint32), b["ao"].view(np.uint32))
+    for k in ("gi", "ambient"):
+        d = np.abs(a[k].astype(np.float64) - b[k])
+        print(f"{k}: max |difference| {d.max():.3g}, on {np.mean(d > 0):.3f} of the values")
+        np.testing.assert_allclose(b[k], a[k], rtol=5e-6, atol=1e-6, err_msg=k)
+
+
 def test_host_slice_order_background(host):
     """A frame of sky in slice-major order: the reduction writes AO 1, GI 0, ambient 0 and
     empty masks (no item writes a background pixel's partial sums)."""
