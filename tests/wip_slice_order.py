@@ -149,6 +149,28 @@ def test_slice_order_1080p_sampled(ctx):
     PY.compare(got, oref, gb, oc, op, pixels=pix)
 
 
+def test_slice_order_4k_fp16_sampled(ctx):
+    """The 3840x2160 FP16 workload frame in slice-major order (chunk 256): against the
+    default order over the whole frame (masks not requested), and the oracle on the same
+    FP16 values on a seeded sample of 800 pixels plus the corners."""
+    gb, cam, w, sc = workload("c3_4k_fp16")
+    log("slice order 3840x2160 fp16")
+    H, W = gb["depth"].shape
+    kw = dict(slices=8, steps=32, radius=8.0, thickness=w["thickness"], noise=O.NOISE_R2, seed=3,
+              ambient_sh=tuple(sc.ambient_sh.reshape(-1)))
+    ref, runs = both_orders(ctx, gb, cam, kw, chunks=(256,), masks=False)
+    got = check_orders(ref, runs)
+    pix = PY.sample_pixels(H, W, 800, 3)
+    _, oc = PY.cams(cam)
+    _, op = PY.params(**kw)
+    oref = O.compute(gb["depth"], gb["normal"], gb["radiance"], oc, op, pixels=pix)
+    ys, xs = pix
+    for k in ("ao", "gi", "ambient"):
+        err = np.abs(got[k][ys, xs] - oref[k]).max()
+        log(f"  {k}: max |error| {err:.3e} against the oracle")
+        assert err <= 1e-3, k
+
+
 def test_slice_order_buffer_growth_two_streams(ctx):
     """On a fresh context: a small frame, then a larger one (the partial buffer grows while
     the first may still run), then the small one again, alternating two streams with no
