@@ -210,3 +210,25 @@ def test_slice_order_buffer_growth_two_streams(ctx):
     for a, o in zip(alone, outs):
         for k in ("ao", "gi", "ambient"):
             assert np.array_equal(o[k].cpu().numpy().view(np.uint32), a[k].view(np.uint32)), k
+
+
+def test_slice_order_rejects(ctx):
+    """Chunk sizes outside [0, 65536] are refused and leave the order as it was."""
+    import torch
+    from paper_2301_11376_amd import SSVBError
+    gb, cam, sc = PY.tiny(40, 30)
+    kw = dict(slices=3, steps=6, radius=1.3, thickness=0.3, noise=O.NOISE_R2, seed=2)
+    ref, _ = both_orders(ctx, gb, cam, kw, chunks=())
+    for bad in (-1, 65537, 1 << 30):
+        with pytest.raises(SSVBError) as e:
+            ctx.set_slice_order(bad)
+        assert e.value.status == 1
+    # still the default order: the same outputs bit for bit
+    bc, _ = PY.cams(cam)
+    bp, _ = PY.params(**kw)
+    t = PY.to_device(gb)
+    out = ctx.compute(t["depth"], t["normal"], t["radiance"], bc, bp, masks=True)
+    torch.cuda.synchronize()
+    out = host_copy(out)
+    for k in ref:
+        assert np.array_equal(out[k].view(np.uint32), ref[k].view(np.uint32)), k
