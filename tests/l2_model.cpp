@@ -18,6 +18,7 @@
 // ...), "slice<C>" (the library's slice-major order, ssvb_set_slice_order: work items are
 // (tile, slice) pairs, for each chunk of C tiles of the XCD's run slice 0 of every tile,
 // then slice 1, ...; the partial-sum writes and their reduction are not modelled),
+// "pair<C>" (the same with two slices per work item),
 // "block<X>x<Y>" (the tiles cut into an X x Y grid of blocks, one per XCD, each walked in
 // vertical strips).  The replayed share is XCD 0's unless an XCD is named (a share at the
 // frame's edge loses the samples that fall off it).  Layout "packed" puts a texel's normal
@@ -110,6 +111,7 @@ struct Config {
     int W, H, nd, ns, fp16;
     std::string order, layout;
     int chunk = 0;
+    int per_item = 1;      // slices per work item in a slice-major order ("pair<C>": 2)
     int dlw = 0, dlh = 0;  // depth line shape in texels ("...+d<w>x<h>" layouts), 0: rows
 };
 
@@ -273,6 +275,7 @@ int main(int argc, char** argv) {
     const int xcd = argc > 17 ? atoi(argv[17]) : 0;  // which XCD's share to replay (0..7)
     const char* noise = argc > 18 ? argv[18] : "r2";   // r2 (the workloads'), hash or fixed
     if (C.order.rfind("slice", 0) == 0) C.chunk = atoi(C.order.c_str() + 5);
+    if (C.order.rfind("pair", 0) == 0) C.chunk = atoi(C.order.c_str() + 4), C.per_item = 2;
     const size_t px = (size_t)C.W * C.H, es = C.fp16 ? 2 : 4;
     std::vector<char> depth(px * 4), normal(px * 3 * es), radiance(px * 3 * es);
     const char* files[3] = {argv[1], argv[2], argv[3]};
@@ -357,13 +360,15 @@ int main(int argc, char** argv) {
             if (tx < A.tiles_x && ty < A.tiles_y) items.push_back({tx, ty, -1});
         }
     } else if (C.chunk > 0) {
-        // the library's slice-major items (slice_item) over the replayed tiles of the run
-        for (uint32_t j = 0; j < take * (uint32_t)A.nd; ++j) {
+        // the library's slice-major items (slice_item) over the replayed tiles of the run;
+        // with two slices per item, item slice s stands for slices 2s and 2s + 1
+        const int groups = (A.nd + C.per_item - 1) / C.per_item;
+        for (uint32_t j = 0; j < take * (uint32_t)groups; ++j) {
             uint32_t tile;
             int s, tx, ty;
-            slice_item((uint32_t)C.chunk, A.nd, take, j, tile, s);
+            slice_item((uint32_t)C.chunk, groups, take, j, tile, s);
             walk_tile(A, first + tile, tx, ty);
-            items.push_back({tx, ty, s});
+            items.push_back({tx, ty, s * C.per_item});
         }
     } else {
         for (uint32_t k = 0; k < take; ++k) {
@@ -407,7 +412,7 @@ int main(int argc, char** argv) {
                 w.lanes.push_back(Lane{rd, 0});
             }
             w.slice_lo = it.slice < 0 ? 0 : instr_lo(A, it.slice);
-            w.slice_hi = it.slice < 0 ? ~0u : instr_lo(A, it.slice + 1);
+            w.slice_hi = it.slice < 0 ? ~0u : instr_lo(A, std::min(it.slice + C.per_item, A.nd));
             // a slice item after the first re-reads the centre depth and normal
             if (it.slice > 0)
                 for (auto& l : w.lanes) l.pos = 0;
