@@ -659,11 +659,11 @@ def run_leg(into, key, fn, *a, say=None, **k):
     return r
 
 
-def slice_order_leg(ctx, tensors, chunk, steps, warmup=3):
-    """The same frame in slice-major order (chunks of `chunk` tiles; both kernels, the
-    per-slice gather and the reduction, inside the timed region), against the default
-    order timed the same way just before; the outputs of the two orders compared (AO bit
-    for bit, GI and ambient max |difference|)."""
+def slice_order_leg(ctx, tensors, chunks, steps, warmup=3):
+    """The same frame in slice-major order, once per chunk size in `chunks` (tiles; both
+    kernels, the per-slice gather and the reduction, inside the timed region), against the
+    default order timed the same way just before; the outputs of each run compared with the
+    default order's (AO bit for bit, GI and ambient max |difference|)."""
     import torch
     t, c, p, out = tensors
     stream = torch.cuda.current_stream()
@@ -682,18 +682,20 @@ def slice_order_leg(ctx, tensors, chunk, steps, warmup=3):
         return float(ms.mean()), float(np.percentile(ms, 50)), {k: v.clone() for k, v in out.items()}
 
     base_ms, base_p50, base = timed()
+    res = {"default_order_ms": base_ms, "default_order_p50_ms": base_p50, "chunks": []}
     try:
-        ctx.set_slice_order(chunk)
-        ms, p50, got = timed()
+        for chunk in chunks:
+            ctx.set_slice_order(chunk)
+            ms, p50, got = timed()
+            r = {"chunk_tiles": chunk, "ms": ms, "p50_ms": p50, "speedup": base_ms / ms,
+                 "ao_equal": bool(torch.equal(got["ao"], base["ao"])),
+                 "gi_max_diff": float((got["gi"] - base["gi"]).abs().max()),
+                 "ambient_max_diff": float((got["ambient"] - base["ambient"]).abs().max())}
+            res["chunks"].append(r)
+            print(f"slice order (chunk {chunk}): {ms:.3f} ms vs default order {base_ms:.3f} ms, AO equal "
+                  f"{r['ao_equal']}, GI max diff {r['gi_max_diff']:.2e}", file=sys.stderr, flush=True)
     finally:
         ctx.set_slice_order(0)
-    res = {"chunk_tiles": chunk, "ms": ms, "p50_ms": p50, "default_order_ms": base_ms,
-           "default_order_p50_ms": base_p50, "speedup": base_ms / ms,
-           "ao_equal": bool(torch.equal(got["ao"], base["ao"])),
-           "gi_max_diff": float((got["gi"] - base["gi"]).abs().max()),
-           "ambient_max_diff": float((got["ambient"] - base["ambient"]).abs().max())}
-    print(f"slice order (chunk {chunk}): {ms:.3f} ms vs default order {base_ms:.3f} ms, AO equal "
-          f"{res['ao_equal']}, GI max diff {res['gi_max_diff']:.2e}", file=sys.stderr, flush=True)
     return res
 
 
@@ -736,11 +738,13 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rates", default="0.5,0.7,0.9",
                     help="request rates as fractions of the saturated rate (p50 / p99 at each)")
-    ap.add_argument("--slice-order", type=int, default=0, metavar="TILES",
-                    help="also time the frame(s) in slice-major order over chunks of TILES tiles (0: skip)")
+    ap.add_argument("--slice-order", default="", metavar="TILES[,TILES...]",
+                    help="also time the frame(s) in slice-major order over chunks of TILES tiles, once per "
+                         "comma-separated size (empty: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the gather, run a plain device copy of MIB MiB (scales HBM counters)")
     args = ap.parse_args()
+    args.slice_order = [int(v) for v in args.slice_order.split(",") if v.strip()]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the gather has no multi-GPU path in this build "
               "(frames or row bands would shard with no exchange; see the design notes)", file=sys.stderr)
