@@ -23,7 +23,8 @@
 // the frame's pitches span, so the sanitizer reports any access outside them.
 // It runs the library's strip walk and, with --interleaved, a reconstruction of the
 // interleaved strip walk (strips 0, 8, 16, ... then 1, 9, 17, ...) that was timed and then
-// withdrawn.  With --fuzz N SEED it draws N random inputs instead (see fuzz() below).
+// withdrawn.  With --fuzz N SEED it draws N random inputs instead (see fuzz() below); with
+// --part k/n it runs every n-th frame shape from the k-th (the batches in the last part).
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -718,11 +719,13 @@ static void fuzz(long n, uint64_t seed, long& accepted, long& rejected, long& em
 
 int main(int argc, char** argv) {
     bool quick = false;
+    int part_k = 0, part_n = 1;  // --part k/n: every n-th frame shape from the k-th (batches in the last)
     long fuzz_n = 0;
     uint64_t fuzz_seed = 1;
     for (int i = 1; i < argc; ++i) {
         if (!strcmp(argv[i], "--interleaved")) g_interleaved = true;
         if (!strcmp(argv[i], "--quick")) quick = true;
+        if (!strcmp(argv[i], "--part") && i + 1 < argc) sscanf(argv[i + 1], "%d/%d", &part_k, &part_n);
         if (!strcmp(argv[i], "--fuzz") && i + 2 < argc) {
             fuzz_n = atol(argv[i + 1]);
             fuzz_seed = strtoull(argv[i + 2], nullptr, 10);
@@ -773,7 +776,9 @@ int main(int argc, char** argv) {
         return f;
     };
     long frames_done = 0;
-    for (const Spec& s : specs) {
+    for (size_t si = 0; si < specs.size(); ++si) {
+        if ((int)(si % (size_t)part_n) != part_k) continue;
+        const Spec& s = specs[si];
         const Frame f = frame_of(s, s.masks != 0);
         const bool big = (int64_t)s.W * s.H > 2000000;
         for (const auto& tl : kTiles) {
@@ -823,7 +828,7 @@ int main(int argc, char** argv) {
     long batches = 0;
     for (const auto& tl : kTiles) {
         for (int st : kStrips) {
-            if (quick && st != 4) continue;
+            if ((quick && st != 4) || part_k != part_n - 1) continue;
             for (int wgs : {1, 7, 1024}) {
                 emulate_batch(batch, LaunchShape{tl[0], tl[1], st, tl[2]}, wgs);
                 ++batches;

@@ -20,8 +20,10 @@ SRC = os.path.join(ROOT, "tests", "index_path_cpu.cpp")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-RUNS = {"strip": (), "interleaved": ("--interleaved", "--quick"), "fuzz7": ("--fuzz", "2000", "7"),
-        "fuzz2024": ("--fuzz", "2000", "2024")}
+# the strip walk's frame shapes in two halves (the batches in the second), the
+# interleaved reconstruction, two fuzz seeds
+RUNS = {"strip0": ("--part", "0/2"), "strip1": ("--part", "1/2"), "interleaved": ("--interleaved", "--quick"),
+        "fuzz7": ("--fuzz", "2000", "7"), "fuzz2024": ("--fuzz", "2000", "2024")}
 
 
 CSRC = os.path.join(ROOT, "paper_2301_11376_amd", "csrc")
@@ -33,8 +35,8 @@ LIB_SOURCES = ["ssvb_kernels.hip", "ssvb_denoise.hip", "ssvb_api.cpp", "ssvb_ser
 @pytest.fixture(scope="module")
 def emulator():
     """Builds the emulator (its own source and the library's, compiled in parallel, the
-    host code under ASan and UBSan) and starts its four runs at once (they are independent,
-    single threaded and take 20-55 s each); each test waits for its own."""
+    host code under ASan and UBSan) and starts its five runs at once (they are independent,
+    single threaded and take 20-30 s each); each test waits for its own."""
     if not os.path.exists(HIPCC) or shutil.which("ld") is None:
         pytest.skip("needs hipcc")
     common = ["-O1", "-g", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
@@ -80,9 +82,11 @@ def test_strip_walk_index_path(emulator):
     65,536 tiles: each (tile, slice) once, each pixel's partial record once and in bounds,
     the reduction's grid); on the frames up to 400k pixels also the half-resolution fill and
     every denoiser pass on real buffers of exactly the frames' spans."""
-    out = run(emulator, "strip")
-    m = re.search(r"(\d+) slice-major items, (\d+) upsampled and (\d+) denoised cells", out)
-    assert int(m.group(1)) > 0 and int(m.group(2)) > 0 and int(m.group(3)) > 0
+    outs = [run(emulator, "strip0"), run(emulator, "strip1")]
+    counts = [[int(v) for v in re.search(r"(\d+) frame launches, (\d+) batches, (\d+) slice-major items, "
+                                         r"(\d+) upsampled and (\d+) denoised cells", o).groups()] for o in outs]
+    frames, batches, items, up, dn = (a + b for a, b in zip(*counts))
+    assert frames > 1000 and batches > 100 and items > 0 and up > 0 and dn > 0
 
 
 def test_interleaved_walk_reconstruction_index_path(emulator):
